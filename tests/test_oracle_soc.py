@@ -1,0 +1,175 @@
+"""Pins of the oracle's Clement interpolant and material strength of connection.
+
+The closed forms below are derived by hand from the definitions of the distance
+Laplacian and the material distance (sections "Strength-of-connection measures
+and dropping criteria" and "A material based strength-of-connection measure")
+on the 5x5-node two-material grid of the paper's test-problem figure
+(nodes numbered 1..25 row-major from the bottom left, low material for x < 1.5,
+high material for x > 1.5, 9-point pattern, pointwise nodal sigma).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import box_mesh, poisson_box
+from workloads.q1 import config1_checkerboard_2d, rotated_anisotropic_3d
+
+
+def fig4_grid(kappa, anisotropic=False):
+    prob = poisson_box((4, 4), lengths=(4.0, 4.0), dirichlet="none")
+    x = prob.coords
+    sig = np.zeros((prob.n, 3))
+    low = x[:, 0] < 1.5
+    sig[low] = [1.0, 0.0, 1.0]
+    sig[~low] = [kappa, 0.0, kappa] if not anisotropic else [kappa, 0.0, 1.0]
+    return prob, x, sig
+
+
+def entry(prob, S, i, j):
+    """S at (node i, node j) with 1-based node numbers of the figure."""
+    i0, j0 = i - 1, j - 1
+    lo, hi = prob.rowptr[i0], prob.rowptr[i0 + 1]
+    k = lo + np.searchsorted(prob.col[lo:hi], j0)
+    assert prob.col[k] == j0
+    return S[k]
+
+
+@pytest.mark.parametrize("kappa", [1.0, 1e2, 1e4, 1e8])
+def test_fig4_scalar_closed_forms(kappa):
+    prob, x, sig = fig4_grid(kappa)
+    lv, ld, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 2, x, sig, soc="material", theta=0.08)
+    assert ld[11] == pytest.approx(6.0, rel=1e-15)                     # L_12,12
+    assert ld[12] == pytest.approx(4 * kappa + 2, rel=1e-15)           # L_13,13
+    assert entry(prob, S, 12, 11) == pytest.approx(1 / math.sqrt(24), rel=1e-14)
+    assert entry(prob, S, 12, 13) == pytest.approx(1 / math.sqrt(6 * (4 * kappa + 2)), rel=1e-14)
+    # S_13,14 = kappa / sqrt((4 kappa + 2) 6 kappa)
+    assert entry(prob, S, 13, 14) == pytest.approx(kappa / math.sqrt((4 * kappa + 2) * 6 * kappa), rel=1e-14)
+    # the low/high edge decays like kappa^{-1/2} (eq. low_high_soc_parameter_relation)
+    if kappa >= 1e4:
+        assert entry(prob, S, 12, 13) * math.sqrt(kappa) == pytest.approx(1 / math.sqrt(24), rel=1e-3)
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e4])
+def test_fig4_anisotropic_closed_forms(kappa):
+    prob, x, sig = fig4_grid(kappa, anisotropic=True)
+    lv, ld, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 2, x, sig, soc="material", theta=0.08)
+    l13 = kappa + 4 + 2 * kappa / (kappa + 1)
+    l14 = 2 * kappa + 2 + 4 * kappa / (kappa + 1)
+    assert ld[12] == pytest.approx(l13, rel=1e-14)
+    assert ld[13] == pytest.approx(l14, rel=1e-14)
+    assert entry(prob, S, 12, 13) == pytest.approx(1 / math.sqrt(6 * l13), rel=1e-14)
+    assert entry(prob, S, 13, 14) == pytest.approx(kappa / math.sqrt(l13 * l14), rel=1e-14)
+    # vertical edge inside the high region is weak: ~1/kappa -> semi-coarsening in x
+    assert entry(prob, S, 13, 8) == pytest.approx(1 / l13, rel=1e-14)
+
+
+def test_fig4_drop_at_kappa_100():
+    prob, x, sig = fig4_grid(100.0)
+    _, _, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 2, x, sig, soc="material", theta=0.08)
+    assert not entry(prob, mask.astype(float), 12, 13)   # interface edge dropped
+    assert entry(prob, mask.astype(float), 12, 11)       # low-low edge kept
+
+
+def test_full_tensor_quadratic_form_matches_inverse():
+    """l_ij = 1/max(q_i, q_j), q = d^T sigma^{-1} d with a full SPD tensor."""
+    rng = np.random.default_rng(7)
+    prob = poisson_box((3, 3, 3), dirichlet="none")
+    n = prob.n
+    sig = np.zeros((n, 6))
+    full = []
+    for i in range(n):
+        B = rng.normal(size=(3, 3))
+        T = B @ B.T + 0.5 * np.eye(3)
+        full.append(T)
+        sig[i] = [T[0, 0], T[0, 1], T[0, 2], T[1, 1], T[1, 2], T[2, 2]]
+    x = prob.coords + rng.normal(scale=0.05, size=prob.coords.shape)
+    lv, ld, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 3, x, sig, soc="material")
+    for i in range(n):
+        for k in range(prob.rowptr[i], prob.rowptr[i + 1]):
+            j = prob.col[k]
+            if j == i:
+                continue
+            d = x[j] - x[i]
+            q = max(d @ np.linalg.solve(full[i], d), d @ np.linalg.solve(full[j], d))
+            assert lv[k] == pytest.approx(1.0 / q, rel=1e-12)
+        assert ld[i] == pytest.approx(sum(lv[prob.rowptr[i]:prob.rowptr[i + 1]]), rel=1e-14)
+
+
+def test_strength_invariants_on_checkerboard():
+    prob = config1_checkerboard_2d(n=16, cells=4)
+    sig = oracle.clement(prob.n, 2, prob.elem_nodes, prob.elem_sigma)
+    d = oracle.detect_dirichlet(prob.rowptr, prob.col, prob.val)
+    assert np.array_equal(d, prob.dirichlet)
+    lv, ld, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 2, prob.coords, sig, dirichlet=d)
+    rows = np.repeat(np.arange(prob.n), np.diff(prob.rowptr))
+    diag = rows == prob.col
+    assert np.all(S[diag] == 1.0)
+    off = ~diag & ~d[rows] & ~d[prob.col]
+    assert np.all(S[off] > 0) and np.all(S[off] <= 1.0 + 1e-15)
+    # bitwise symmetry of |L| and of the mask
+    key = {(int(r), int(c)): k for k, (r, c) in enumerate(zip(rows, prob.col))}
+    for k, (r, c) in enumerate(zip(rows, prob.col)):
+        kt = key[(int(c), int(r))]
+        assert lv[k] == lv[kt]
+        assert mask[k] == mask[kt]
+    # the square-free test agrees with S >= theta away from ties
+    far = off & (np.abs(S - 0.08) > 1e-12)
+    assert np.array_equal(mask[far], S[far] >= 0.08)
+    # Dirichlet rows/cols keep no edge
+    assert not np.any(mask[~diag & (d[rows] | d[prob.col])])
+
+
+def test_constant_sigma_material_equals_distance_laplacian():
+    """With sigma = c I (c a power of two) the material measure is the Euclidean
+    distance Laplacian measure exactly (S is scale invariant)."""
+    prob = rotated_anisotropic_3d(n=4, block=2)
+    sig = np.tile([4.0, 0, 0, 4.0, 0, 4.0], (prob.n, 1))
+    _, _, S1, m1 = oracle.strength(prob.rowptr, prob.col, prob.val, 3, prob.coords, sig, soc="material")
+    _, _, S2, m2 = oracle.strength(prob.rowptr, prob.col, prob.val, 3, prob.coords, sig, soc="distance")
+    assert np.array_equal(S1, S2) and np.array_equal(m1, m2)
+
+
+def test_classical_sa_measure():
+    prob = poisson_box((4, 4), dirichlet="none")
+    lv, ld, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 2, prob.coords,
+                                      np.ones((prob.n, 3)), soc="sa", theta=0.1)
+    A = prob.dense()
+    rows = np.repeat(np.arange(prob.n), np.diff(prob.rowptr))
+    ref = np.abs(A[rows, prob.col]) / np.sqrt(np.abs(A[rows, rows] * A[prob.col, prob.col]))
+    assert np.allclose(S, ref, rtol=1e-14, atol=0)
+
+
+def test_clement_constant_and_interface():
+    from workloads.q1 import layered_stack_3d
+    prob = layered_stack_3d(n=4, repeats=1)
+    sig = oracle.clement(prob.n, 3, prob.elem_nodes, prob.elem_sigma)
+    # node on the first layer boundary: mean of 4 elements below and 4 above
+    kz = prob.meta["layer_k"]
+    zi = np.rint(prob.coords[:, 2] * 4).astype(int)
+    ix = np.rint(prob.coords[:, 0] / prob.lengths[0] * 4).astype(int)
+    iy = np.rint(prob.coords[:, 1] / prob.lengths[1] * 4).astype(int)
+    interior = (ix > 0) & (ix < 4) & (iy > 0) & (iy < 4)
+    for i in np.nonzero(interior & (zi == 1))[0]:
+        assert sig[i, 0] == pytest.approx((4 * kz[0] + 4 * kz[1]) / 8, rel=1e-15)
+        assert sig[i, 1] == 0.0 and sig[i, 2] == 0.0
+        assert sig[i, 3] == sig[i, 0] and sig[i, 5] == sig[i, 0]
+    # constant tensors are reproduced exactly, and component order is the upper triangle
+    T = np.array([[3.0, 0.5, -0.25], [0.5, 2.0, 0.125], [-0.25, 0.125, 1.0]])
+    es = np.repeat(T[None], prob.nelem, axis=0)
+    sig = oracle.clement(prob.n, 3, prob.elem_nodes, es)
+    assert np.all(sig == np.array([3.0, 0.5, -0.25, 2.0, 0.125, 1.0]))
+
+
+def test_clement_2d_corner_edge_counts():
+    coords, en = box_mesh((2, 2), (1.0, 1.0))
+    es = np.zeros((4, 2, 2))
+    for e in range(4):
+        es[e] = (e + 1.0) * np.eye(2)
+    sig = oracle.clement(9, 2, en, es)
+    # centre node touches all four elements; corner node 0 only element 0
+    assert sig[4, 0] == (1 + 2 + 3 + 4) / 4
+    assert sig[0, 0] == 1.0 and sig[8, 0] == 4.0
+    assert sig[1, 0] == (1 + 2) / 2
