@@ -1,0 +1,187 @@
+/*
+ * matamg: material-aware smoothed-aggregation AMG and AMG-preconditioned CG
+ * for the material-weighted Laplacian -div(sigma(x) grad u) = f on MI355X
+ * (gfx950).
+ *
+ * Method: Firmbach, Phillips, Glusa, Popp, Siefert, Mayr, "Smoothed
+ * aggregation algebraic multigrid for problems with heterogeneous and
+ * anisotropic materials".  Section numbers below refer to that paper.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - extern "C", no exceptions cross the boundary; every call returns an
+ *   amg_status and leaves a thread-local message for amg_last_error().
+ * - Pointers are borrowed for the duration of the call; the library copies
+ *   what it keeps.  `kind` says whether array arguments are host memory
+ *   (AMG_PTR_HOST) or device memory of the current HIP device
+ *   (AMG_PTR_DEVICE).  Host arrays are copied to the device inside the call.
+ * - `hip_stream` is a hipStream_t (NULL = the default stream).  All device
+ *   work of the call is ordered on it; calls that return sizes or statuses
+ *   synchronise it before returning.
+ * - Matrices are CSR with int32 row pointers (n+1) and int32 column indices
+ *   sorted ascending and unique within each row, FP64 values.  A must be
+ *   square and symmetric in pattern and value.
+ * - A hierarchy is owned by the library until amg_free().  Distinct
+ *   hierarchies may be used concurrently on distinct streams; one hierarchy
+ *   is not re-entrant.
+ */
+#ifndef MATAMG_AMG_H
+#define MATAMG_AMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMG_OK = 0,
+    AMG_ERR_INVALID_ARG = 1,        /* malformed CSR, bad sizes or options */
+    AMG_ERR_OUT_OF_MEMORY = 2,      /* device or host allocation failed */
+    AMG_ERR_HIP = 3,                /* a HIP runtime call failed */
+    AMG_ERR_NOT_SPD = 4,            /* sigma not SPD, or coarse Cholesky failed */
+    AMG_ERR_COARSENING_STAGNATED = 5, /* level cap reached above max_coarse, or no reduction */
+    AMG_ERR_NOT_CONVERGED = 6,      /* max_iter reached above tol */
+    AMG_ERR_BREAKDOWN = 7,          /* CG breakdown: p^T A p <= 0 or non-finite */
+    AMG_ERR_BUDGET = 8              /* serving: request larger than the HBM budget */
+} amg_status;
+
+typedef enum { AMG_PTR_HOST = 0, AMG_PTR_DEVICE = 1 } amg_ptr_kind;
+
+/* strength-of-connection measure (section 2.1 and section 3) */
+typedef enum {
+    AMG_SOC_MATERIAL = 0, /* material distance Laplacian (the paper's measure) */
+    AMG_SOC_DISTANCE = 1, /* Euclidean distance Laplacian */
+    AMG_SOC_SA = 2        /* classical |A_ij| / sqrt(|A_ii A_jj|) */
+} amg_soc;
+
+typedef enum { AMG_DROP_POINTWISE = 0 } amg_drop;
+typedef enum { AMG_PREC_FP64 = 0, AMG_PREC_FP32_HIER = 1 } amg_precision;
+typedef enum { AMG_SMOOTH_CHEBYSHEV = 0, AMG_SMOOTH_JACOBI = 1 } amg_smoother;
+
+/* Setup and solve options.  Defaults (amg_options_default) follow the
+ * numerical section: pointwise dropping, 2nd-order Chebyshev smoothing,
+ * direct coarse solve, coarsening to <= 5000 unknowns, at most 10 levels. */
+typedef struct {
+    int32_t dim;            /* spatial dimension of coords / tensors: 1, 2 or 3 */
+    double theta;           /* drop tolerance (0.08) */
+    int32_t soc;            /* amg_soc */
+    int32_t drop;           /* amg_drop */
+    int32_t smoother;       /* amg_smoother */
+    int32_t max_coarse;     /* stop coarsening at <= this many unknowns (5000) */
+    int32_t max_levels;     /* level cap, <= 16 (10) */
+    int32_t cheb_degree;    /* Chebyshev polynomial degree (2) */
+    double cheb_ratio;      /* eigen-interval [lambda/ratio, lambda] (30) */
+    double cheb_boost;      /* lambda = boost * power-method estimate (1.1) */
+    int32_t power_iters;    /* power-method steps for omega and Chebyshev (10) */
+    double omega_sym;       /* prolongator damping numerator (4/3) */
+    double jacobi_omega;    /* damped-Jacobi weight (2/3) */
+    int32_t jacobi_sweeps;  /* damped-Jacobi sweeps per smoothing (2) */
+    int32_t precision;      /* amg_precision */
+    uint64_t seed;          /* aggregation priorities and power-method starts */
+} amg_options;
+
+typedef struct amg_hierarchy amg_hierarchy;
+
+typedef struct {
+    int32_t iterations;     /* preconditioned CG steps taken */
+    double rel_res_true;    /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit */
+    double t_solve_s;       /* device-synchronised wall time of the solve */
+    int32_t status;         /* amg_status of the solve */
+} amg_solve_info;
+
+typedef struct {
+    int32_t levels;
+    int64_t n[16], nnz[16], nnz_p[16]; /* rows, nnz(A), nnz(P) per level */
+    int32_t mis_rounds[16];
+    double omega[16], lam_pf[16], lam_cheb[16];
+    double op_complexity;              /* sum nnz(A_l) / nnz(A_1) */
+    double vcycle_alg_bytes;           /* algorithmic HBM bytes of one V-cycle */
+    double t_setup_s;
+    int64_t device_bytes;              /* device memory held by the hierarchy */
+} amg_hierarchy_stats;
+
+/* Fill *o with the defaults listed above (dim = 3). */
+amg_status amg_options_default(amg_options* o);
+
+/*
+ * Build the multigrid hierarchy for A (sections 2 and 3):
+ *   level 1: Dirichlet rows (every stored off-diagonal exactly zero) are
+ *   isolated; nodal tensors are the Clement patch means of elem_sigma;
+ *   every level: material distance Laplacian strength, pointwise dropping,
+ *   distance-2 MIS aggregation, tentative and filtered-Jacobi-smoothed
+ *   prolongator (1-norm diagonal), Galerkin product P^T A P, aggregate-mean
+ *   coordinates and tensors; coarsest level: dense FP64 Cholesky.
+ *
+ * n          rows of A (> 0)
+ * rowptr,col,val  A in CSR (see conventions)
+ * nelem, nodes_per_elem, elem_nodes  element -> node connectivity,
+ *            int32 [nelem][nodes_per_elem], node ids in [0, n)
+ * elem_sigma FP64 [nelem][dim][dim] symmetric positive definite tensors
+ * coords     FP64 [n][dim] nodal coordinates
+ * opt        options (NULL = defaults with dim 3)
+ * out        receives the new hierarchy
+ * Errors: INVALID_ARG (bad sizes, unsorted/out-of-range columns, bad options),
+ * NOT_SPD (a nodal tensor is not SPD, or the coarse Cholesky fails),
+ * COARSENING_STAGNATED, OUT_OF_MEMORY, HIP.  On error *out is NULL.
+ */
+amg_status amg_setup(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                     int64_t nelem, int32_t nodes_per_elem, const int32_t* elem_nodes,
+                     const double* elem_sigma, const double* coords, const amg_options* opt,
+                     amg_ptr_kind kind, void* hip_stream, amg_hierarchy** out);
+
+/*
+ * Solve A x = b by CG preconditioned with one V-cycle (Algorithm "Vcycle",
+ * zero initial guess on every level) per step.  Stops when the recurrence
+ * residual satisfies ||r||/||b|| <= tol and the recomputed FP64 residual
+ * confirms it (otherwise the true residual replaces the recurrence one and
+ * the iteration continues).  b and x are FP64 [n]; x holds the initial guess
+ * on entry and the solution on exit.  The outer CG, its dot products and
+ * residual recomputation are FP64 in both precisions.
+ * Errors: NOT_CONVERGED, BREAKDOWN (x holds the last iterate), INVALID_ARG.
+ */
+amg_status amg_pcg_solve(amg_hierarchy* h, const double* b, double* x, double tol, int32_t max_iter,
+                         amg_ptr_kind kind, void* hip_stream, amg_solve_info* info);
+
+/* z = M^{-1} r: one V-cycle.  r, z FP64 [n] device pointers. */
+amg_status amg_vcycle(amg_hierarchy* h, const double* r, double* z, void* hip_stream);
+
+/* y = A_level x (FP64), device pointers; for kernel tests and benchmarks. */
+amg_status amg_level_spmv(amg_hierarchy* h, int32_t level, const double* x, double* y, void* hip_stream);
+
+amg_status amg_hierarchy_info(const amg_hierarchy* h, amg_hierarchy_stats* s);
+
+/* Copy level data to host memory (for parity checks):
+ * agg  int32 [n_level] aggregate id per node (-1: Dirichlet), levels < last
+ * mask uint8 [nnz_level] kept flag per stored entry of A_level, levels < last
+ * csr  which = 0: A_level, 1: P_level, 2: R_level; rowptr [rows+1], col, val
+ * aux  which = 0: coordinates [n][dim], 1: nodal tensors [n][dim(dim+1)/2]
+ *      (upper triangle row-wise), 2: Dirichlet flags as doubles (level 0),
+ *      3: strength values S per stored entry. */
+amg_status amg_get_aggregates(const amg_hierarchy* h, int32_t level, int32_t* agg);
+amg_status amg_get_soc_mask(const amg_hierarchy* h, int32_t level, uint8_t* mask);
+amg_status amg_get_level_csr(const amg_hierarchy* h, int32_t level, int32_t which, int32_t* rowptr,
+                             int32_t* col, double* val);
+amg_status amg_get_level_aux(const amg_hierarchy* h, int32_t level, int32_t which, double* out);
+
+/* Kernel timing for roofline measurements (benchmarks): while enabled, each
+ * launch of the finest level's smoother SpMV is bracketed by HIP events on the
+ * stream it runs on.  amg_kernel_timing(h, 1) clears earlier records.
+ * amg_kernel_timing_read synchronises those events and returns the summed
+ * duration, the number of timed launches and the algorithmic bytes one such
+ * launch moves (matrix values, column indices and row pointers once, the
+ * gathered iterate once, b, D^{-1} and the direction read, direction and
+ * iterate written). */
+amg_status amg_kernel_timing(amg_hierarchy* h, int32_t enable);
+amg_status amg_kernel_timing_read(amg_hierarchy* h, double* total_ms, int64_t* launches,
+                                  double* bytes_per_launch);
+
+void amg_free(amg_hierarchy* h);
+const char* amg_status_string(amg_status s);
+const char* amg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MATAMG_AMG_H */

@@ -1,0 +1,298 @@
+// extern "C" boundary: argument checks, error translation, data accessors.
+#include <cstring>
+#include <string>
+
+#include "hierarchy.h"
+
+struct amg_hierarchy {
+    std::unique_ptr<matamg::Hierarchy> h;
+};
+
+namespace matamg {
+
+thread_local std::string g_last_error;
+
+[[noreturn]] void fail(amg_status code, const std::string& msg) { throw Error{code, msg}; }
+
+}  // namespace matamg
+
+using namespace matamg;
+
+namespace {
+
+template <typename F>
+amg_status guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return AMG_ERR_OUT_OF_MEMORY;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return AMG_ERR_HIP;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return AMG_ERR_HIP;
+    }
+}
+
+amg_status check_options(const amg_options& o) {
+    if (o.dim < 1 || o.dim > 3) fail(AMG_ERR_INVALID_ARG, "dim must be 1, 2 or 3");
+    if (!(o.theta >= 0.0 && o.theta <= 1.0)) fail(AMG_ERR_INVALID_ARG, "theta must lie in [0, 1]");
+    if (o.soc < AMG_SOC_MATERIAL || o.soc > AMG_SOC_SA) fail(AMG_ERR_INVALID_ARG, "unknown strength measure");
+    if (o.drop != AMG_DROP_POINTWISE) fail(AMG_ERR_INVALID_ARG, "unknown dropping criterion");
+    if (o.smoother != AMG_SMOOTH_CHEBYSHEV && o.smoother != AMG_SMOOTH_JACOBI)
+        fail(AMG_ERR_INVALID_ARG, "unknown smoother");
+    if (o.max_coarse < 1) fail(AMG_ERR_INVALID_ARG, "max_coarse must be positive");
+    if (o.max_coarse > 20000) fail(AMG_ERR_INVALID_ARG, "max_coarse above 20000 (dense coarse solve)");
+    if (o.max_levels < 1 || o.max_levels > 16) fail(AMG_ERR_INVALID_ARG, "max_levels must lie in [1, 16]");
+    if (o.cheb_degree < 1 || o.cheb_degree > 8) fail(AMG_ERR_INVALID_ARG, "cheb_degree must lie in [1, 8]");
+    if (!(o.cheb_ratio > 1.0) || !(o.cheb_boost > 0.0)) fail(AMG_ERR_INVALID_ARG, "bad Chebyshev interval");
+    if (o.power_iters < 1 || o.power_iters > 1000) fail(AMG_ERR_INVALID_ARG, "power_iters must lie in [1, 1000]");
+    if (o.jacobi_sweeps < 1 || o.jacobi_sweeps > 8) fail(AMG_ERR_INVALID_ARG, "jacobi_sweeps must lie in [1, 8]");
+    if (o.precision != AMG_PREC_FP64 && o.precision != AMG_PREC_FP32_HIER)
+        fail(AMG_ERR_INVALID_ARG, "unknown precision");
+    return AMG_OK;
+}
+
+Hierarchy& H(amg_hierarchy* h) {
+    if (!h || !h->h) fail(AMG_ERR_INVALID_ARG, "null hierarchy");
+    return *h->h;
+}
+const Hierarchy& H(const amg_hierarchy* h) {
+    if (!h || !h->h) fail(AMG_ERR_INVALID_ARG, "null hierarchy");
+    return *h->h;
+}
+
+}  // namespace
+
+extern "C" {
+
+amg_status amg_options_default(amg_options* o) {
+    if (!o) return AMG_ERR_INVALID_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->dim = 3;
+    o->theta = 0.08;
+    o->soc = AMG_SOC_MATERIAL;
+    o->drop = AMG_DROP_POINTWISE;
+    o->smoother = AMG_SMOOTH_CHEBYSHEV;
+    o->max_coarse = 5000;
+    o->max_levels = 10;
+    o->cheb_degree = 2;
+    o->cheb_ratio = 30.0;
+    o->cheb_boost = 1.1;
+    o->power_iters = 10;
+    o->omega_sym = 4.0 / 3.0;
+    o->jacobi_omega = 2.0 / 3.0;
+    o->jacobi_sweeps = 2;
+    o->precision = AMG_PREC_FP64;
+    o->seed = 0;
+    return AMG_OK;
+}
+
+amg_status amg_setup(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val, int64_t nelem,
+                     int32_t nodes_per_elem, const int32_t* elem_nodes, const double* elem_sigma,
+                     const double* coords, const amg_options* opt, amg_ptr_kind kind, void* hip_stream,
+                     amg_hierarchy** out) {
+    return guarded([&]() -> amg_status {
+        if (!out) fail(AMG_ERR_INVALID_ARG, "out is null");
+        *out = nullptr;
+        amg_options o;
+        if (opt) o = *opt;
+        else amg_options_default(&o);
+        check_options(o);
+        if (n <= 0 || n >= (int64_t)1 << 31) fail(AMG_ERR_INVALID_ARG, "n must lie in [1, 2^31)");
+        if (!rowptr || !col || !val || !coords) fail(AMG_ERR_INVALID_ARG, "null CSR or coordinate array");
+        if (nelem < 0 || (nelem > 0 && (!elem_nodes || !elem_sigma || nodes_per_elem <= 0)))
+            fail(AMG_ERR_INVALID_ARG, "bad element arrays");
+        if (kind != AMG_PTR_HOST && kind != AMG_PTR_DEVICE) fail(AMG_ERR_INVALID_ARG, "bad pointer kind");
+        if (kind == AMG_PTR_HOST) {
+            if (rowptr[0] != 0) fail(AMG_ERR_INVALID_ARG, "rowptr[0] must be 0");
+            for (int64_t i = 0; i < n; ++i)
+                if (rowptr[i + 1] < rowptr[i]) fail(AMG_ERR_INVALID_ARG, "rowptr is not non-decreasing");
+        }
+        hipStream_t s = (hipStream_t)hip_stream;
+        auto h = build_hierarchy(n, rowptr, col, val, nelem, nodes_per_elem, elem_nodes, elem_sigma, coords, o,
+                                 kind == AMG_PTR_HOST, s);
+        auto* wrap = new amg_hierarchy{std::move(h)};
+        *out = wrap;
+        return AMG_OK;
+    });
+}
+
+amg_status amg_pcg_solve(amg_hierarchy* hh, const double* b, double* x, double tol, int32_t max_iter,
+                         amg_ptr_kind kind, void* hip_stream, amg_solve_info* info) {
+    return guarded([&]() -> amg_status {
+        Hierarchy& h = H(hh);
+        if (!b || !x) fail(AMG_ERR_INVALID_ARG, "null b or x");
+        if (!(tol > 0.0) || max_iter < 0) fail(AMG_ERR_INVALID_ARG, "tol must be positive, max_iter >= 0");
+        return pcg_solve(h, b, x, tol, max_iter, kind == AMG_PTR_HOST, (hipStream_t)hip_stream, info);
+    });
+}
+
+amg_status amg_vcycle(amg_hierarchy* hh, const double* r, double* z, void* hip_stream) {
+    return guarded([&]() -> amg_status {
+        Hierarchy& h = H(hh);
+        if (!r || !z) fail(AMG_ERR_INVALID_ARG, "null vector");
+        h.vcycle(r, z, h.dt(S_TMP), (hipStream_t)hip_stream);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_level_spmv(amg_hierarchy* hh, int32_t level, const double* x, double* y, void* hip_stream) {
+    return guarded([&]() -> amg_status {
+        Hierarchy& h = H(hh);
+        if (level < 0 || level >= h.nlev) fail(AMG_ERR_INVALID_ARG, "level out of range");
+        if (!x || !y) fail(AMG_ERR_INVALID_ARG, "null vector");
+        const DCsr& A = h.lev[level].A;
+        if (A.nblk <= 0) fail(AMG_ERR_INVALID_ARG, "level has no streaming layout");
+        spmv<double>(A, A.val.get(), x, y, (hipStream_t)hip_stream);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_hierarchy_info(const amg_hierarchy* hh, amg_hierarchy_stats* st) {
+    return guarded([&]() -> amg_status {
+        const Hierarchy& h = H(hh);
+        if (!st) fail(AMG_ERR_INVALID_ARG, "null stats");
+        std::memset(st, 0, sizeof(*st));
+        st->levels = h.nlev;
+        double tot = 0.0;
+        for (int l = 0; l < h.nlev; ++l) {
+            const Level& L = h.lev[l];
+            st->n[l] = L.A.n;
+            st->nnz[l] = L.A.nnz;
+            st->nnz_p[l] = (l + 1 < h.nlev) ? L.P.nnz : 0;
+            st->mis_rounds[l] = L.mis_rounds;
+            st->omega[l] = L.omega;
+            st->lam_pf[l] = L.lam_pf;
+            st->lam_cheb[l] = L.lam_cheb;
+            tot += (double)L.A.nnz;
+        }
+        st->op_complexity = tot / (double)h.lev[0].A.nnz;
+        st->vcycle_alg_bytes = h.vcycle_alg_bytes();
+        st->t_setup_s = h.t_setup;
+        st->device_bytes = h.mem.bytes;
+        return AMG_OK;
+    });
+}
+
+amg_status amg_get_aggregates(const amg_hierarchy* hh, int32_t level, int32_t* agg) {
+    return guarded([&]() -> amg_status {
+        const Hierarchy& h = H(hh);
+        if (level < 0 || level + 1 >= h.nlev || !agg) fail(AMG_ERR_INVALID_ARG, "level out of range");
+        MATAMG_HIP(hipMemcpy(agg, h.lev[level].agg.get(), sizeof(int) * (size_t)h.lev[level].A.n,
+                             hipMemcpyDeviceToHost));
+        return AMG_OK;
+    });
+}
+
+amg_status amg_get_soc_mask(const amg_hierarchy* hh, int32_t level, uint8_t* mask) {
+    return guarded([&]() -> amg_status {
+        const Hierarchy& h = H(hh);
+        if (level < 0 || level + 1 >= h.nlev || !mask) fail(AMG_ERR_INVALID_ARG, "level out of range");
+        MATAMG_HIP(hipMemcpy(mask, h.lev[level].mask.get(), (size_t)h.lev[level].A.nnz, hipMemcpyDeviceToHost));
+        return AMG_OK;
+    });
+}
+
+amg_status amg_get_level_csr(const amg_hierarchy* hh, int32_t level, int32_t which, int32_t* rowptr,
+                             int32_t* col, double* val) {
+    return guarded([&]() -> amg_status {
+        const Hierarchy& h = H(hh);
+        if (level < 0 || level >= h.nlev) fail(AMG_ERR_INVALID_ARG, "level out of range");
+        if (which < 0 || which > 2 || (which > 0 && level + 1 >= h.nlev))
+            fail(AMG_ERR_INVALID_ARG, "no such matrix on this level");
+        const Level& L = h.lev[level];
+        const DCsr& M = which == 0 ? L.A : (which == 1 ? L.P : L.R);
+        if (rowptr) MATAMG_HIP(hipMemcpy(rowptr, M.rowptr.get(), sizeof(int) * ((size_t)M.n + 1), hipMemcpyDeviceToHost));
+        if (col) MATAMG_HIP(hipMemcpy(col, M.col.get(), sizeof(int) * (size_t)M.nnz, hipMemcpyDeviceToHost));
+        if (val) MATAMG_HIP(hipMemcpy(val, M.val.get(), sizeof(double) * (size_t)M.nnz, hipMemcpyDeviceToHost));
+        return AMG_OK;
+    });
+}
+
+amg_status amg_get_level_aux(const amg_hierarchy* hh, int32_t level, int32_t which, double* out) {
+    return guarded([&]() -> amg_status {
+        const Hierarchy& h = H(hh);
+        if (level < 0 || level >= h.nlev || !out) fail(AMG_ERR_INVALID_ARG, "level out of range");
+        const Level& L = h.lev[level];
+        const int dim = h.opt.dim, ncomp = dim * (dim + 1) / 2;
+        if (which == 0) {
+            MATAMG_HIP(hipMemcpy(out, L.x.get(), sizeof(double) * (size_t)L.A.n * dim, hipMemcpyDeviceToHost));
+        } else if (which == 1) {
+            MATAMG_HIP(hipMemcpy(out, L.sig.get(), sizeof(double) * (size_t)L.A.n * ncomp, hipMemcpyDeviceToHost));
+        } else if (which == 2) {
+            if (!L.dir) fail(AMG_ERR_INVALID_ARG, "no Dirichlet flags on this level");
+            std::vector<uint8_t> d((size_t)L.A.n);
+            MATAMG_HIP(hipMemcpy(d.data(), L.dir.get(), d.size(), hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < d.size(); ++i) out[i] = d[i];
+        } else if (which == 3) {
+            if (!L.S) fail(AMG_ERR_INVALID_ARG, "no strength values on this level");
+            MATAMG_HIP(hipMemcpy(out, L.S.get(), sizeof(double) * (size_t)L.A.nnz, hipMemcpyDeviceToHost));
+        } else {
+            fail(AMG_ERR_INVALID_ARG, "unknown aux array");
+        }
+        return AMG_OK;
+    });
+}
+
+/* Kernel timing for roofline measurements: when enabled, every launch of the
+ * finest level's smoother SpMV is bracketed by HIP events on its stream. */
+amg_status amg_kernel_timing(amg_hierarchy* hh, int32_t enable) {
+    return guarded([&]() -> amg_status {
+        Hierarchy& h = H(hh);
+        for (auto e : h.timer.ev) (void)hipEventDestroy(e);
+        h.timer.ev.clear();
+        h.timer.enabled = enable != 0;
+        return AMG_OK;
+    });
+}
+
+amg_status amg_kernel_timing_read(amg_hierarchy* hh, double* total_ms, int64_t* launches, double* bytes_per_launch) {
+    return guarded([&]() -> amg_status {
+        Hierarchy& h = H(hh);
+        double tot = 0.0;
+        for (size_t i = 0; i + 1 < h.timer.ev.size(); i += 2) {
+            MATAMG_HIP(hipEventSynchronize(h.timer.ev[i + 1]));
+            float ms = 0.f;
+            MATAMG_HIP(hipEventElapsedTime(&ms, h.timer.ev[i], h.timer.ev[i + 1]));
+            tot += ms;
+        }
+        if (total_ms) *total_ms = tot;
+        if (launches) *launches = (int64_t)(h.timer.ev.size() / 2);
+        if (bytes_per_launch) {
+            // algorithmic bytes of one fine-level smoother step: val + col +
+            // rowptr + gathered x + (b, dinv, d) read + (d, x) written
+            const Level& L = h.lev[0];
+            const double s = h.fp32 ? 4.0 : 8.0;
+            *bytes_per_launch = (double)L.A.nnz * (s + 4.0) + 4.0 * (L.A.n + 1) + 6.0 * s * L.A.n;
+        }
+        return AMG_OK;
+    });
+}
+
+void amg_free(amg_hierarchy* h) { delete h; }
+
+const char* amg_status_string(amg_status s) {
+    switch (s) {
+        case AMG_OK: return "ok";
+        case AMG_ERR_INVALID_ARG: return "invalid argument";
+        case AMG_ERR_OUT_OF_MEMORY: return "out of memory";
+        case AMG_ERR_HIP: return "HIP runtime error";
+        case AMG_ERR_NOT_SPD: return "not symmetric positive definite";
+        case AMG_ERR_COARSENING_STAGNATED: return "coarsening stagnated";
+        case AMG_ERR_NOT_CONVERGED: return "not converged";
+        case AMG_ERR_BREAKDOWN: return "CG breakdown";
+        case AMG_ERR_BUDGET: return "request exceeds the memory budget";
+    }
+    return "unknown status";
+}
+
+const char* amg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

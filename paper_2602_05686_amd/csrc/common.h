@@ -1,0 +1,131 @@
+// Internal definitions shared by the HIP sources of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/amg.h"
+
+namespace matamg {
+
+// ---------------------------------------------------------------------------
+// errors: thrown inside the library, converted to amg_status at the boundary
+// ---------------------------------------------------------------------------
+struct Error {
+    amg_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(amg_status code, const std::string& msg);
+
+#define MATAMG_HIP(call)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            ::matamg::fail(e_ == hipErrorOutOfMemory ? AMG_ERR_OUT_OF_MEMORY : AMG_ERR_HIP,     \
+                           std::string(#call) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+#define MATAMG_LAUNCH_CHECK() MATAMG_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct MemCounter {
+    int64_t bytes = 0;
+    int64_t peak = 0;
+    void add(int64_t b) {
+        bytes += b;
+        if (bytes > peak) peak = bytes;
+    }
+};
+
+template <typename T>
+class DBuf {
+  public:
+    DBuf() = default;
+    DBuf(size_t n, MemCounter* mc = nullptr) { alloc(n, mc); }
+    ~DBuf() { release(); }
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept { swap(o); }
+    DBuf& operator=(DBuf&& o) noexcept {
+        if (this != &o) {
+            release();
+            swap(o);
+        }
+        return *this;
+    }
+    void alloc(size_t n, MemCounter* mc = nullptr) {
+        release();
+        n_ = n;
+        mc_ = mc;
+        if (n == 0) return;
+        hipError_t e = hipMalloc(&p_, n * sizeof(T));
+        if (e != hipSuccess) {
+            p_ = nullptr;
+            n_ = 0;
+            fail(AMG_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+        }
+        if (mc_) mc_->add((int64_t)(n * sizeof(T)));
+    }
+    void release() {
+        if (p_) {
+            (void)hipFree(p_);
+            if (mc_) mc_->add(-(int64_t)(n_ * sizeof(T)));
+        }
+        p_ = nullptr;
+        n_ = 0;
+    }
+    T* get() const { return p_; }
+    size_t size() const { return n_; }
+    explicit operator bool() const { return p_ != nullptr; }
+
+  private:
+    void swap(DBuf& o) {
+        std::swap(p_, o.p_);
+        std::swap(n_, o.n_);
+        std::swap(mc_, o.mc_);
+    }
+    T* p_ = nullptr;
+    size_t n_ = 0;
+    MemCounter* mc_ = nullptr;
+};
+
+// CSR matrix resident on the device
+struct DCsr {
+    int n = 0, m = 0;
+    int64_t nnz = 0;
+    DBuf<int> rowptr, col;
+    DBuf<double> val;
+    DBuf<float> val32;
+    // row blocks for the streaming SpMV: blk[b] .. blk[b+1] rows of block b
+    DBuf<int> blk;
+    int nblk = 0;
+};
+
+constexpr int kBlock = 256;          // threads per block in streaming kernels
+constexpr int kStreamCap = 2048;     // nnz staged in LDS per streaming block
+constexpr int kMaxRowsPerBlock = kBlock;
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// synchronous device->host copy of a small array on a stream
+template <typename T>
+void d2h(T* host, const T* dev, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    MATAMG_HIP(hipMemcpyAsync(host, dev, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    MATAMG_HIP(hipStreamSynchronize(s));
+}
+template <typename T>
+void h2d(T* dev, const T* host, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    MATAMG_HIP(hipMemcpyAsync(dev, host, n * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+}  // namespace matamg

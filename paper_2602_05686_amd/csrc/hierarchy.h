@@ -1,0 +1,72 @@
+// Multigrid hierarchy resident on one GPU, its setup driver, the V-cycle and
+// the preconditioned CG driver.
+#pragma once
+
+#include <array>
+#include <memory>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace matamg {
+
+struct Level {
+    DCsr A, P, R;  // operator; prolongator to / restriction from the next level
+    DBuf<double> dinv;
+    DBuf<float> dinv32;
+    DBuf<double> x, sig;     // nodal coordinates [n][dim], tensors [n][ncomp]
+    DBuf<uint8_t> dir, mask;
+    DBuf<double> S;
+    DBuf<int> agg;
+    int nc = 0, mis_rounds = 0;
+    double lam_pf = 0.0, omega = 0.0, lam_cheb = 0.0;
+    std::vector<double> c1, c2;  // smoother step coefficients
+    // V-cycle work vectors (b: right-hand side, x/x2: iterate double buffer,
+    // d: smoother direction, r: residual)
+    DBuf<double> b, xa, xb, d, r;
+    DBuf<float> fb, fxa, fxb, fd, fr;
+};
+
+struct KernelTimer {
+    bool enabled = false;
+    std::vector<hipEvent_t> ev;  // start/stop pairs
+    int64_t launches = 0;
+    double ms = 0.0;
+};
+
+struct Hierarchy {
+    amg_options opt{};
+    int nlev = 0;
+    std::array<Level, 16> lev;
+    int nL = 0;
+    DBuf<double> Ainv;  // dense inverse of the coarsest operator
+    MemCounter mem;
+    DBuf<double> scal;       // device scalars (see Scalar)
+    DBuf<double> partial;    // reduction partials
+    DBuf<unsigned> counter;  // reduction counters
+    DBuf<double> cr, cz, cp, cq, cx, cb;  // CG vectors (x, b used for host inputs)
+    double* hscal = nullptr; // pinned host mirror of scal
+    double t_setup = 0.0;
+    bool fp32 = false;
+    KernelTimer timer;
+
+    ~Hierarchy();
+    DotTarget dt(int slot) const;
+    void vcycle(const double* r, double* z, DotTarget rz, hipStream_t s);
+    template <typename T>
+    void vcycle_t(const double* r, double* z, DotTarget rz, hipStream_t s);
+    double vcycle_alg_bytes() const;
+};
+
+// device scalar slots
+enum Scalar { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_RR = 3, S_BB = 4, S_TMP = 5, S_NSCAL = 8 };
+
+std::unique_ptr<Hierarchy> build_hierarchy(int64_t n, const int* rowptr, const int* col, const double* val,
+                                           int64_t nelem, int npe, const int* elem_nodes,
+                                           const double* elem_sigma, const double* coords,
+                                           const amg_options& opt, bool host_ptrs, hipStream_t s);
+
+amg_status pcg_solve(Hierarchy& h, const double* b, double* x, double tol, int max_iter, bool host_ptrs,
+                     hipStream_t s, amg_solve_info* info);
+
+}  // namespace matamg

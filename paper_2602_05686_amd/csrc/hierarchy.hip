@@ -1,0 +1,595 @@
+// Setup driver (sections 2 and 3 of the paper, per level: strength of
+// connection, dropping, aggregation, prolongator smoothing, Galerkin
+// product, auxiliary transfer; dense factorisation on the coarsest level),
+// the V-cycle (Algorithm "Vcycle") and the outer preconditioned CG.
+#include <chrono>
+#include <cmath>
+
+#include "hierarchy.h"
+#include "setup_kernels.h"
+
+namespace matamg {
+
+namespace {
+
+uint64_t splitmix64_host(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+// one stream of draws per (purpose, level): aggregation priorities,
+// prolongator power method, smoother power method
+constexpr uint64_t kPurposeMis = 1, kPurposePf = 101, kPurposeCheb = 201;
+uint64_t stream_key(uint64_t seed, uint64_t purpose, int level) {
+    return splitmix64_host(seed + purpose + (uint64_t)level);
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void make_blocks(DCsr& A, MemCounter* mc, hipStream_t s) {
+    std::vector<int> rp((size_t)A.n + 1);
+    d2h(rp.data(), A.rowptr.get(), rp.size(), s);
+    std::vector<int> blk = stream_blocks(rp.data(), A.n);
+    A.nblk = (int)blk.size() - 1;
+    A.blk.alloc(blk.size(), mc);
+    h2d(A.blk.get(), blk.data(), blk.size(), s);
+    MATAMG_HIP(hipStreamSynchronize(s));
+}
+
+// reduction partials: one slot per block of the widest fused-reduction launch
+void ensure_partial(Hierarchy& h, int nblocks) {
+    const size_t need = (size_t)std::max(kMaxPartials, nblocks) + 1;
+    if (h.partial.size() < need) h.partial.alloc(need, &h.mem);
+}
+
+int read_flag(int* dflag, hipStream_t s) {
+    int v = 0;
+    d2h(&v, dflag, 1, s);
+    return v;
+}
+
+// lambda = ||dscale .* (A v)|| after `iters` normalised steps from a seeded start
+double power_method(const DCsr& A, const double* dscale, int iters, uint64_t key, Hierarchy& h, hipStream_t s) {
+    const int n = A.n;
+    DBuf<double> v((size_t)n, &h.mem), w((size_t)n, &h.mem);
+    fill_seeded_uniform(n, key, v.get(), s);
+    dot<double>(v.get(), v.get(), n, h.partial.get(), h.counter.get(), h.scal.get() + S_TMP, s);
+    scale_by_inv_norm(n, h.scal.get() + S_TMP, v.get(), v.get(), s);
+    for (int it = 0; it < iters; ++it) {
+        spmv_scale_norm(A, v.get(), dscale, w.get(), h.dt(S_TMP), s);
+        if (it + 1 < iters) scale_by_inv_norm(n, h.scal.get() + S_TMP, w.get(), v.get(), s);
+    }
+    double nrm2 = 0.0;
+    d2h(&nrm2, h.scal.get() + S_TMP, 1, s);
+    return iters > 0 ? std::sqrt(nrm2) : 0.0;
+}
+
+void smoother_coefficients(Level& L, const amg_options& o) {
+    L.c1.clear();
+    L.c2.clear();
+    if (o.smoother == AMG_SMOOTH_JACOBI) {
+        for (int k = 0; k < o.jacobi_sweeps; ++k) {
+            L.c1.push_back(0.0);
+            L.c2.push_back(o.jacobi_omega);
+        }
+        return;
+    }
+    const double beta = o.cheb_boost * L.lam_cheb;
+    const double alpha = beta / o.cheb_ratio;
+    const double theta = (beta + alpha) / 2.0, delta = (beta - alpha) / 2.0;
+    const double s1 = theta / delta;
+    double rho_old = 1.0 / s1;
+    L.c1.push_back(0.0);
+    L.c2.push_back(1.0 / theta);
+    for (int k = 1; k < o.cheb_degree; ++k) {
+        const double rho = 1.0 / (2.0 * s1 - rho_old);
+        L.c1.push_back(rho * rho_old);
+        L.c2.push_back(2.0 * rho / delta);
+        rho_old = rho;
+    }
+}
+
+template <typename T>
+void alloc_work(Level& L, int n, bool coarse_only, MemCounter* mc);
+
+template <>
+void alloc_work<double>(Level& L, int n, bool coarse_only, MemCounter* mc) {
+    L.b.alloc(n, mc);
+    L.xa.alloc(n, mc);
+    if (coarse_only) return;
+    L.xb.alloc(n, mc);
+    L.d.alloc(n, mc);
+    L.r.alloc(n, mc);
+}
+template <>
+void alloc_work<float>(Level& L, int n, bool coarse_only, MemCounter* mc) {
+    L.fb.alloc(n, mc);
+    L.fxa.alloc(n, mc);
+    if (coarse_only) return;
+    L.fxb.alloc(n, mc);
+    L.fd.alloc(n, mc);
+    L.fr.alloc(n, mc);
+}
+
+}  // namespace
+
+Hierarchy::~Hierarchy() {
+    if (hscal) (void)hipHostFree(hscal);
+    for (auto e : timer.ev) (void)hipEventDestroy(e);
+}
+
+DotTarget Hierarchy::dt(int slot) const { return DotTarget{partial.get(), counter.get(), scal.get() + slot}; }
+
+std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const int* col, const double* val,
+                                           int64_t nelem, int npe, const int* elem_nodes,
+                                           const double* elem_sigma, const double* coords,
+                                           const amg_options& opt, bool host_ptrs, hipStream_t s) {
+    const double t0 = now_s();
+    auto hp = std::make_unique<Hierarchy>();
+    Hierarchy& h = *hp;
+    h.opt = opt;
+    h.fp32 = opt.precision == AMG_PREC_FP32_HIER;
+    const int n = (int)n64;
+    const int dim = opt.dim;
+    const int ncomp = dim * (dim + 1) / 2;
+    MemCounter* mc = &h.mem;
+
+    h.scal.alloc(S_NSCAL, mc);
+    h.counter.alloc(1, mc);
+    MATAMG_HIP(hipMemsetAsync(h.counter.get(), 0, sizeof(unsigned), s));
+    MATAMG_HIP(hipMemsetAsync(h.scal.get(), 0, sizeof(double) * S_NSCAL, s));
+    MATAMG_HIP(hipHostMalloc((void**)&h.hscal, sizeof(double) * S_NSCAL, hipHostMallocDefault));
+    DBuf<int> flag(1, mc);
+    MATAMG_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int), s));
+
+    // ---- level 1 inputs on the device
+    Level& L0 = h.lev[0];
+    int nnz = 0;
+    if (host_ptrs) nnz = rowptr[n];
+    else d2h(&nnz, rowptr + n, 1, s);
+    if (nnz < 0) fail(AMG_ERR_INVALID_ARG, "rowptr[n] is negative");
+    L0.A.n = L0.A.m = n;
+    L0.A.nnz = nnz;
+    L0.A.rowptr.alloc((size_t)n + 1, mc);
+    L0.A.col.alloc((size_t)(nnz > 0 ? nnz : 1), mc);
+    L0.A.val.alloc((size_t)(nnz > 0 ? nnz : 1), mc);
+    L0.x.alloc((size_t)n * dim, mc);
+    const hipMemcpyKind kind = host_ptrs ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    MATAMG_HIP(hipMemcpyAsync(L0.A.rowptr.get(), rowptr, sizeof(int) * ((size_t)n + 1), kind, s));
+    MATAMG_HIP(hipMemcpyAsync(L0.A.col.get(), col, sizeof(int) * (size_t)nnz, kind, s));
+    MATAMG_HIP(hipMemcpyAsync(L0.A.val.get(), val, sizeof(double) * (size_t)nnz, kind, s));
+    MATAMG_HIP(hipMemcpyAsync(L0.x.get(), coords, sizeof(double) * (size_t)n * dim, kind, s));
+    validate_csr(n, L0.A.rowptr.get(), L0.A.col.get(), nnz, flag.get(), s);
+    if (read_flag(flag.get(), s)) fail(AMG_ERR_INVALID_ARG, "CSR columns unsorted, duplicated or out of range");
+
+    // ---- Clement nodal tensors
+    L0.sig.alloc((size_t)n * ncomp, mc);
+    {
+        DBuf<int> en;
+        DBuf<double> es;
+        const int* den = elem_nodes;
+        const double* des = elem_sigma;
+        if (host_ptrs && nelem > 0) {
+            en.alloc((size_t)nelem * npe, mc);
+            es.alloc((size_t)nelem * dim * dim, mc);
+            MATAMG_HIP(hipMemcpyAsync(en.get(), elem_nodes, sizeof(int) * (size_t)nelem * npe, kind, s));
+            MATAMG_HIP(hipMemcpyAsync(es.get(), elem_sigma, sizeof(double) * (size_t)nelem * dim * dim, kind, s));
+            den = en.get();
+            des = es.get();
+        }
+        Incidence inc;
+        build_node_elements(den, nelem, npe, n, inc, flag.get(), mc, s);
+        if (read_flag(flag.get(), s)) fail(AMG_ERR_INVALID_ARG, "element node id out of range");
+        clement(n, dim, inc, des, L0.sig.get(), s);
+        MATAMG_HIP(hipStreamSynchronize(s));
+    }
+
+    // ---- levels
+    int l = 0;
+    for (;; ++l) {
+        Level& L = h.lev[l];
+        const int nl = L.A.n;
+        const int64_t nzl = L.A.nnz;
+        L.dinv.alloc(nl, mc);
+        diag_inverse(nl, L.A.rowptr.get(), L.A.col.get(), L.A.val.get(), L.dinv.get(), s);
+        make_blocks(L.A, mc, s);
+        if (nl <= opt.max_coarse || l + 1 >= opt.max_levels) {
+            if (nl > opt.max_coarse)
+                fail(AMG_ERR_COARSENING_STAGNATED, "level cap reached with " + std::to_string(nl) + " unknowns");
+            break;
+        }
+        // strength of connection and dropping
+        L.dir.alloc(nl, mc);
+        if (l == 0) detect_dirichlet(nl, L.A.rowptr.get(), L.A.col.get(), L.A.val.get(), L.dir.get(), s);
+        else MATAMG_HIP(hipMemsetAsync(L.dir.get(), 0, nl, s));
+        DBuf<double> minv;
+        if (opt.soc == AMG_SOC_MATERIAL) {
+            minv.alloc((size_t)nl * ncomp, mc);
+            tensor_inverse(nl, dim, L.sig.get(), minv.get(), flag.get(), s);
+            if (read_flag(flag.get(), s)) fail(AMG_ERR_NOT_SPD, "nodal tensor not SPD on level " + std::to_string(l));
+        }
+        DBuf<double> lval((size_t)(nzl > 0 ? nzl : 1), mc), ldiag(nl, mc);
+        soc_values(nl, L.A.rowptr.get(), L.A.col.get(), L.A.val.get(), dim, L.x.get(), minv.get(), L.dir.get(),
+                   opt.soc, lval.get(), ldiag.get(), s);
+        L.S.alloc((size_t)(nzl > 0 ? nzl : 1), mc);
+        L.mask.alloc((size_t)(nzl > 0 ? nzl : 1), mc);
+        soc_mask(nl, L.A.rowptr.get(), L.A.col.get(), L.dir.get(), lval.get(), ldiag.get(), opt.theta, L.S.get(),
+                 L.mask.get(), s);
+        lval.release();
+        ldiag.release();
+        minv.release();
+
+        // distance-2 maximal independent set, synchronous rounds
+        {
+            DBuf<uint8_t> state(nl, mc);
+            DBuf<uint64_t> t1(nl, mc), t2(nl, mc);
+            DBuf<int> und(1, mc);
+            const uint64_t key = stream_key(opt.seed, kPurposeMis, l);
+            mis_init(nl, L.dir.get(), state.get(), s);
+            int rounds = 0;
+            for (;;) {
+                mis_round(nl, L.A.rowptr.get(), L.A.col.get(), L.mask.get(), key, state.get(), t1.get(), t2.get(),
+                          und.get(), s);
+                ++rounds;
+                if (read_flag(und.get(), s) == 0) break;
+                if (rounds > nl + 1) fail(AMG_ERR_HIP, "distance-2 MIS did not terminate");
+            }
+            L.mis_rounds = rounds;
+            t1.release();
+            t2.release();
+            DBuf<int> flags(nl, mc), rank((size_t)nl + 1, mc), tmp(scan_tmp_size(nl), mc), phase2(nl, mc);
+            agg_root_flags(nl, state.get(), flags.get(), s);
+            exclusive_scan(flags.get(), rank.get(), nl, tmp.get(), s);
+            int nagg = 0;
+            d2h(&nagg, rank.get() + nl, 1, s);
+            if (nagg <= 0 || nagg >= nl)
+                fail(AMG_ERR_COARSENING_STAGNATED,
+                     "aggregation did not reduce level " + std::to_string(l) + " (" + std::to_string(nagg) + " of " +
+                         std::to_string(nl) + ")");
+            L.nc = nagg;
+            L.agg.alloc(nl, mc);
+            agg_assign(nl, L.A.rowptr.get(), L.A.col.get(), L.mask.get(), L.dir.get(), state.get(), rank.get(),
+                       phase2.get(), L.agg.get(), s);
+        }
+
+        // filtered matrix, 1-norm diagonal, damping, smoothed prolongator
+        {
+            DCsr F;
+            F.n = F.m = nl;
+            DBuf<int> cnt(nl, mc), tmp(scan_tmp_size(nl), mc);
+            filter_count(nl, L.A.rowptr.get(), L.A.col.get(), L.mask.get(), cnt.get(), s);
+            F.rowptr.alloc((size_t)nl + 1, mc);
+            exclusive_scan(cnt.get(), F.rowptr.get(), nl, tmp.get(), s);
+            int fnnz = 0;
+            d2h(&fnnz, F.rowptr.get() + nl, 1, s);
+            F.nnz = fnnz;
+            F.col.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
+            F.val.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
+            DBuf<double> dt(nl, mc), dtinv(nl, mc);
+            filter_fill(nl, L.A.rowptr.get(), L.A.col.get(), L.A.val.get(), L.mask.get(), F.rowptr.get(),
+                        F.col.get(), F.val.get(), dt.get(), dtinv.get(), s);
+            make_blocks(F, mc, s);
+            ensure_partial(h, std::max(F.nblk, L.A.nblk));
+            L.lam_pf = power_method(F, dtinv.get(), opt.power_iters, stream_key(opt.seed, kPurposePf, l), h, s);
+            L.omega = L.lam_pf > 0.0 ? opt.omega_sym / L.lam_pf : 0.0;
+            DCsr Ph;
+            Ph.n = nl;
+            Ph.m = L.nc;
+            phat_counts(nl, L.agg.get(), cnt.get(), s);
+            Ph.rowptr.alloc((size_t)nl + 1, mc);
+            exclusive_scan(cnt.get(), Ph.rowptr.get(), nl, tmp.get(), s);
+            int pn = 0;
+            d2h(&pn, Ph.rowptr.get() + nl, 1, s);
+            Ph.nnz = pn;
+            Ph.col.alloc((size_t)(pn > 0 ? pn : 1), mc);
+            Ph.val.alloc((size_t)(pn > 0 ? pn : 1), mc);
+            phat_fill(nl, L.agg.get(), Ph.rowptr.get(), Ph.col.get(), Ph.val.get(), s);
+            spgemm(F, Ph, L.P, mc, s);
+            prolongator_finalize(nl, L.P.rowptr.get(), L.P.col.get(), L.P.val.get(), L.agg.get(), dt.get(),
+                                 L.omega, s);
+        }
+        transpose(L.P, L.R, mc, s);
+        Level& C = h.lev[l + 1];
+        {
+            DCsr AP;
+            spgemm(L.A, L.P, AP, mc, s);
+            spgemm(L.R, AP, C.A, mc, s);
+        }
+        C.A.n = C.A.m = L.nc;
+        // coarse coordinates and tensors: aggregate means
+        C.x.alloc((size_t)L.nc * dim, mc);
+        C.sig.alloc((size_t)L.nc * ncomp, mc);
+        {
+            Incidence mem;
+            build_aggregate_members(L.agg.get(), nl, L.nc, mem, mc, s);
+            coarse_aux(L.nc, dim, mem, L.x.get(), L.sig.get(), C.x.get(), C.sig.get(), s);
+            MATAMG_HIP(hipStreamSynchronize(s));
+        }
+        make_blocks(L.P, mc, s);
+        make_blocks(L.R, mc, s);
+        h.nlev = l + 2;
+    }
+    h.nlev = l + 1;
+    ensure_partial(h, h.lev[0].A.nblk);
+
+    // smoother spectral bounds and coefficients
+    for (int k = 0; k + 1 < h.nlev; ++k) {
+        Level& L = h.lev[k];
+        L.lam_cheb = power_method(L.A, L.dinv.get(), opt.power_iters, stream_key(opt.seed, kPurposeCheb, k), h, s);
+        smoother_coefficients(L, opt);
+    }
+
+    // coarsest level: dense inverse through the Cholesky factor
+    {
+        Level& C = h.lev[h.nlev - 1];
+        const int nc = C.A.n;
+        h.nL = nc;
+        h.Ainv.alloc((size_t)nc * nc, mc);
+        MATAMG_HIP(hipMemsetAsync(h.Ainv.get(), 0, sizeof(double) * (size_t)nc * nc, s));
+        densify(nc, C.A.rowptr.get(), C.A.col.get(), C.A.val.get(), h.Ainv.get(), s);
+        DBuf<double> work((size_t)nc * nc, mc);
+        if (!dense_spd_inverse(nc, h.Ainv.get(), work.get(), flag.get(), s))
+            fail(AMG_ERR_NOT_SPD, "coarsest operator is not positive definite (n=" + std::to_string(nc) + ")");
+    }
+
+    // work vectors and reduced-precision copies
+    for (int k = 0; k < h.nlev; ++k) {
+        Level& L = h.lev[k];
+        const int nl = L.A.n;
+        const bool coarsest = (k == h.nlev - 1);
+        alloc_work<double>(L, nl, coarsest, mc);
+        if (h.fp32) {
+            alloc_work<float>(L, nl, coarsest, mc);
+            if (!coarsest) {
+                L.A.val32.alloc((size_t)(L.A.nnz > 0 ? L.A.nnz : 1), mc);
+                cast_vec<double, float>(L.A.nnz, L.A.val.get(), L.A.val32.get(), s);
+                L.dinv32.alloc(nl, mc);
+                cast_vec<double, float>(nl, L.dinv.get(), L.dinv32.get(), s);
+                L.P.val32.alloc((size_t)(L.P.nnz > 0 ? L.P.nnz : 1), mc);
+                cast_vec<double, float>(L.P.nnz, L.P.val.get(), L.P.val32.get(), s);
+                L.R.val32.alloc((size_t)(L.R.nnz > 0 ? L.R.nnz : 1), mc);
+                cast_vec<double, float>(L.R.nnz, L.R.val.get(), L.R.val32.get(), s);
+            }
+        }
+    }
+    const size_t n0 = (size_t)h.lev[0].A.n;
+    h.cr.alloc(n0, mc);
+    h.cz.alloc(n0, mc);
+    h.cp.alloc(n0, mc);
+    h.cq.alloc(n0, mc);
+    MATAMG_HIP(hipStreamSynchronize(s));
+    h.t_setup = now_s() - t0;
+    return hp;
+}
+
+// ------------------------------------------------------------------ V-cycle
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+    static double* b(Level& L) { return L.b.get(); }
+    static double* xa(Level& L) { return L.xa.get(); }
+    static double* xb(Level& L) { return L.xb.get(); }
+    static double* d(Level& L) { return L.d.get(); }
+    static double* r(Level& L) { return L.r.get(); }
+    static const double* A(const DCsr& M) { return M.val.get(); }
+    static const double* dinv(Level& L) { return L.dinv.get(); }
+};
+template <>
+struct Vec<float> {
+    static float* b(Level& L) { return L.fb.get(); }
+    static float* xa(Level& L) { return L.fxa.get(); }
+    static float* xb(Level& L) { return L.fxb.get(); }
+    static float* d(Level& L) { return L.fd.get(); }
+    static float* r(Level& L) { return L.fr.get(); }
+    static const float* A(const DCsr& M) { return M.val32.get(); }
+    static const float* dinv(Level& L) { return L.dinv32.get(); }
+};
+
+template <typename T>
+void Hierarchy::vcycle_t(const double* r64, double* z64, DotTarget rz, hipStream_t s) {
+    using V = Vec<T>;
+    const int L = nlev;
+    if (L == 1) {
+        dense_gemv<double>(nL, Ainv.get(), r64, z64, s);
+        dot<double>(r64, z64, nL, rz.partial, rz.counter, rz.result, s);
+        return;
+    }
+    T* cur[16];
+    // restriction sweep
+    for (int l = 0; l + 1 < L; ++l) {
+        Level& Lv = lev[l];
+        const int n = Lv.A.n;
+        T* b;
+        const double* b64 = nullptr;
+        if constexpr (std::is_same<T, double>::value) {
+            b = (l == 0) ? const_cast<double*>(r64) : V::b(Lv);
+        } else {
+            b = V::b(Lv);
+            if (l == 0) b64 = r64;
+        }
+        T* x = V::xa(Lv);
+        T* y = V::xb(Lv);
+        const bool timed = timer.enabled && l == 0;
+        smooth_first<T>(n, b64, b, V::dinv(Lv), (T)Lv.c2[0], V::d(Lv), x, s);
+        for (size_t k = 1; k < Lv.c1.size(); ++k) {
+            if (timed) {
+                hipEvent_t e0, e1;
+                MATAMG_HIP(hipEventCreate(&e0));
+                MATAMG_HIP(hipEventCreate(&e1));
+                MATAMG_HIP(hipEventRecord(e0, s));
+                spmv_smooth<T>(Lv.A, V::A(Lv.A), x, b, V::dinv(Lv), V::d(Lv), (T)Lv.c1[k], (T)Lv.c2[k], y, nullptr,
+                               nullptr, DotTarget{}, s);
+                MATAMG_HIP(hipEventRecord(e1, s));
+                timer.ev.push_back(e0);
+                timer.ev.push_back(e1);
+            } else {
+                spmv_smooth<T>(Lv.A, V::A(Lv.A), x, b, V::dinv(Lv), V::d(Lv), (T)Lv.c1[k], (T)Lv.c2[k], y, nullptr,
+                               nullptr, DotTarget{}, s);
+            }
+            std::swap(x, y);
+        }
+        cur[l] = x;
+        spmv_resid<T>(Lv.A, V::A(Lv.A), x, b, V::r(Lv), s);
+        spmv<T>(Lv.R, V::A(Lv.R), V::r(Lv), V::b(lev[l + 1]), s);
+    }
+    // coarsest level
+    Level& Lc = lev[L - 1];
+    dense_gemv<T>(nL, Ainv.get(), V::b(Lc), V::xa(Lc), s);
+    cur[L - 1] = V::xa(Lc);
+    // prolongation sweep
+    for (int l = L - 2; l >= 0; --l) {
+        Level& Lv = lev[l];
+        T* b;
+        if constexpr (std::is_same<T, double>::value) b = (l == 0) ? const_cast<double*>(r64) : V::b(Lv);
+        else b = V::b(Lv);
+        T* x = cur[l];
+        T* y = (x == V::xa(Lv)) ? V::xb(Lv) : V::xa(Lv);
+        spmv_add<T>(Lv.P, V::A(Lv.P), cur[l + 1], x, x, s);
+        const size_t steps = Lv.c1.size();
+        for (size_t k = 0; k < steps; ++k) {
+            const bool last = (l == 0 && k + 1 == steps);
+            T* out = y;
+            double* out64 = nullptr;
+            if (last) {
+                if constexpr (std::is_same<T, double>::value) out = z64;
+                else out64 = z64;
+            }
+            const double* dv = last ? r64 : nullptr;
+            const bool timed = timer.enabled && l == 0;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timed) {
+                MATAMG_HIP(hipEventCreate(&e0));
+                MATAMG_HIP(hipEventCreate(&e1));
+                MATAMG_HIP(hipEventRecord(e0, s));
+            }
+            spmv_smooth<T>(Lv.A, V::A(Lv.A), x, b, V::dinv(Lv), V::d(Lv), (T)(k == 0 ? 0.0 : Lv.c1[k]), (T)Lv.c2[k],
+                           out, out64, dv, last ? rz : DotTarget{}, s);
+            if (timed) {
+                MATAMG_HIP(hipEventRecord(e1, s));
+                timer.ev.push_back(e0);
+                timer.ev.push_back(e1);
+            }
+            if (!last) std::swap(x, y);
+        }
+        cur[l] = x;
+    }
+}
+
+void Hierarchy::vcycle(const double* r, double* z, DotTarget rz, hipStream_t s) {
+    if (fp32) vcycle_t<float>(r, z, rz, s);
+    else vcycle_t<double>(r, z, rz, s);
+}
+
+// Algorithmic HBM bytes of one V-cycle in the implemented kernel schedule:
+// every streaming SpMV reads val, col and rowptr once and each listed vector
+// once; the coarse GEMV reads the dense inverse.
+double Hierarchy::vcycle_alg_bytes() const {
+    const double s = fp32 ? 4.0 : 8.0;
+    double bytes = 0.0;
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const Level& L = lev[l];
+        const double n = L.A.n, nnz = (double)L.A.nnz, nc = L.nc, nnzp = (double)L.P.nnz;
+        const double steps = (double)L.c1.size();
+        const double mat = nnz * (s + 4.0) + 4.0 * (n + 1);
+        // smoother SpMVs: (steps-1) pre + steps post; one residual SpMV
+        const double n_spmv = (steps - 1.0) + steps + 1.0;
+        bytes += n_spmv * mat;
+        bytes += nnzp * (s + 4.0) + 4.0 * (nc + 1);  // R r
+        bytes += nnzp * (s + 4.0) + 4.0 * (n + 1);   // x += P e
+        // vectors: first step reads b, dinv, writes d, x (4); each smoother
+        // SpMV reads x, b, dinv, d and writes d, x (6); residual reads x, b,
+        // writes r (3); restriction reads r, writes b_c; prolongation reads
+        // e_c, x, writes x
+        const double vec_n = 4.0 + 6.0 * ((steps - 1.0) + steps) + 3.0 + 1.0 + 2.0;
+        const double vec_c = 1.0 + 1.0;
+        bytes += vec_n * s * n + vec_c * s * nc;
+    }
+    bytes += 8.0 * (double)nL * nL + 2.0 * s * nL;
+    return bytes;
+}
+
+// ---------------------------------------------------------------------- PCG
+amg_status pcg_solve(Hierarchy& h, const double* b_in, double* x_io, double tol, int max_iter, bool host_ptrs,
+                     hipStream_t s, amg_solve_info* info) {
+    const double t0 = now_s();
+    const DCsr& A = h.lev[0].A;
+    const int n = A.n;
+    const double* b = b_in;
+    double* x = x_io;
+    if (host_ptrs) {
+        if (!h.cx) h.cx.alloc(n, &h.mem);
+        if (!h.cb) h.cb.alloc(n, &h.mem);
+        h2d(h.cb.get(), b_in, n, s);
+        h2d(h.cx.get(), x_io, n, s);
+        b = h.cb.get();
+        x = h.cx.get();
+    }
+    double* r = h.cr.get();
+    double* z = h.cz.get();
+    double* p = h.cp.get();
+    double* q = h.cq.get();
+    auto read_scal = [&]() {
+        MATAMG_HIP(hipMemcpyAsync(h.hscal, h.scal.get(), sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, s));
+        MATAMG_HIP(hipStreamSynchronize(s));
+    };
+    amg_status st = AMG_ERR_NOT_CONVERGED;
+    int iters = 0;
+    double rel_true = 0.0;
+    dot<double>(b, b, n, h.partial.get(), h.counter.get(), h.scal.get() + S_BB, s);
+    spmv_resid_norm(A, x, b, r, h.dt(S_RR), s);
+    read_scal();
+    const double bn = std::sqrt(h.hscal[S_BB]);
+    if (bn == 0.0) {
+        MATAMG_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+        st = AMG_OK;
+    } else if (std::sqrt(h.hscal[S_RR]) / bn <= tol) {
+        rel_true = std::sqrt(h.hscal[S_RR]) / bn;
+        st = AMG_OK;
+    } else {
+        int cur = S_RZ0, nxt = S_RZ1;
+        h.vcycle(r, z, h.dt(cur), s);
+        cg_direction(n, p, z, h.scal.get() + cur, nullptr, s);
+        for (int it = 1; it <= max_iter; ++it) {
+            spmv_dot(A, p, q, h.dt(S_PQ), s);
+            cg_update(n, x, r, p, q, h.scal.get() + cur, h.scal.get() + S_PQ, h.dt(S_RR), s);
+            read_scal();
+            const double pq = h.hscal[S_PQ], rzv = h.hscal[cur];
+            if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(rzv)) {
+                st = AMG_ERR_BREAKDOWN;
+                iters = it;
+                break;
+            }
+            iters = it;
+            double rel = std::sqrt(h.hscal[S_RR]) / bn;
+            rel_true = rel;
+            if (rel <= tol) {
+                spmv_resid_norm(A, x, b, q, h.dt(S_TMP), s);
+                read_scal();
+                rel_true = std::sqrt(h.hscal[S_TMP]) / bn;
+                if (rel_true <= tol) {
+                    st = AMG_OK;
+                    break;
+                }
+                MATAMG_HIP(hipMemcpyAsync(r, q, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            }
+            h.vcycle(r, z, h.dt(nxt), s);
+            cg_direction(n, p, z, h.scal.get() + nxt, h.scal.get() + cur, s);
+            std::swap(cur, nxt);
+        }
+    }
+    if (host_ptrs) d2h(x_io, h.cx.get(), n, s);
+    MATAMG_HIP(hipStreamSynchronize(s));
+    if (info) {
+        info->iterations = iters;
+        info->rel_res_true = rel_true;
+        info->t_solve_s = now_s() - t0;
+        info->status = st;
+    }
+    return st;
+}
+
+}  // namespace matamg

@@ -1,0 +1,265 @@
+// Dense FP64 kernels for the coarsest level: blocked right-looking Cholesky
+// A = L L^T, the triangular inverse Y = L^{-1} by block-row forward
+// substitution, and A^{-1} = Y^T Y.  The coarse solve of every V-cycle is then
+// a single dense GEMV, which streams the matrix at full bandwidth instead of
+// the sequential dependency chain of two triangular solves.
+//
+// All matrices are row-major n x n.  Tiles are 64 x 64; a 256-thread block
+// computes one tile as 16 x 16 threads holding 4 x 4 accumulators, staging
+// 64 x 16 slabs of both operands in LDS.
+#include "device_util.h"
+#include "kernels.h"
+
+namespace matamg {
+namespace {
+
+constexpr int NB = 64;
+constexpr int KS = 16;
+
+// element (i, k) of op(A) where op = transpose if tr
+__device__ __forceinline__ double ld_op(const double* A, int lda, bool tr, int i, int k, int mi, int mk) {
+    if (i >= mi || k >= mk) return 0.0;
+    return tr ? A[(size_t)k * lda + i] : A[(size_t)i * lda + k];
+}
+
+// acc += op(A)[0:64, 0:kk] * op(B)[0:kk, 0:64]; A is (rows x kk) after op,
+// B is (kk x cols) after op.  Out-of-range entries read as zero.
+__device__ void tile_mac(double acc[4][4], const double* A, int lda, bool ta, int rows, const double* B, int ldb,
+                         bool tb, int cols, int kk, double (*As)[KS + 1], double (*Bs)[NB + 1]) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int k0 = 0; k0 < kk; k0 += KS) {
+        // 64 x 16 slab of op(A): 1024 values, 4 per thread
+        for (int e = threadIdx.x; e < NB * KS; e += kBlock) {
+            int i = e / KS, k = e % KS;
+            As[i][k] = ld_op(A, lda, ta, i, k0 + k, rows, kk);
+        }
+        for (int e = threadIdx.x; e < NB * KS; e += kBlock) {
+            int k = e / NB, j = e % NB;
+            // element (k, j) of op(B): op(B) = B^T means B[j][k]
+            Bs[k][j] = (k0 + k < kk && j < cols) ? (tb ? B[(size_t)j * ldb + k0 + k] : B[(size_t)(k0 + k) * ldb + j])
+                                                  : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = As[ty * 4 + u][k];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) b[v] = Bs[k][tx * 4 + v];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+        __syncthreads();
+    }
+}
+
+// factor the diagonal tile kb in LDS; flag <- 1 if not positive definite
+__global__ __launch_bounds__(kBlock) void k_potrf_diag(double* A, int n, int kb, int* flag) {
+    __shared__ double T[NB][NB + 1];
+    const int o = kb * NB;
+    const int nb = min(NB, n - o);
+    for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+        int i = e / nb, j = e % nb;
+        T[i][j] = A[(size_t)(o + i) * n + o + j];
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (threadIdx.x == 0) {
+            double d = T[j][j];
+            if (!(d > 0.0) || !isfinite(d)) {
+                *flag = 1;
+                d = 1.0;
+            }
+            T[j][j] = sqrt(d);
+        }
+        __syncthreads();
+        const double ljj = T[j][j];
+        for (int i = j + 1 + threadIdx.x; i < nb; i += kBlock) T[i][j] = T[i][j] / ljj;
+        __syncthreads();
+        const int m = nb - j - 1;
+        for (int e = threadIdx.x; e < m * m; e += kBlock) {
+            int i = j + 1 + e / m, k = j + 1 + e % m;
+            if (k <= i) T[i][k] -= T[i][j] * T[k][j];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+        int i = e / nb, j = e % nb;
+        A[(size_t)(o + i) * n + o + j] = (j <= i) ? T[i][j] : 0.0;
+    }
+}
+
+// rows below the diagonal tile: X L_kk^T = B, one thread per row
+__global__ __launch_bounds__(kBlock) void k_trsm_panel(double* A, int n, int kb) {
+    __shared__ double L[NB][NB + 1];
+    const int o = kb * NB;
+    const int nb = min(NB, n - o);
+    for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+        int i = e / nb, j = e % nb;
+        L[i][j] = A[(size_t)(o + i) * n + o + j];
+    }
+    __syncthreads();
+    const int r = o + nb + blockIdx.x * kBlock + threadIdx.x;
+    if (r >= n) return;
+    double* row = A + (size_t)r * n + o;
+    double x[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) x[j] = (j < nb) ? row[j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j < nb) {
+            double s = x[j];
+            for (int k = 0; k < j; ++k) s -= x[k] * L[j][k];
+            x[j] = s / L[j][j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if (j < nb) row[j] = x[j];
+}
+
+__device__ __forceinline__ void tri_index(int b, int& I, int& J) {
+    int i = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= b) ++i;
+    while (i * (i + 1) / 2 > b) --i;
+    I = i;
+    J = b - i * (i + 1) / 2;
+}
+
+// trailing update A_IJ -= L_I,kb L_J,kb^T for kb < J <= I
+__global__ __launch_bounds__(kBlock) void k_syrk_update(double* A, int n, int kb) {
+    __shared__ double As[NB][KS + 1];
+    __shared__ double Bs[KS][NB + 1];
+    int ti, tj;
+    tri_index(blockIdx.x, ti, tj);
+    const int I = kb + 1 + ti, J = kb + 1 + tj;
+    const int o = kb * NB, kk = min(NB, n - o);
+    const int ri = I * NB, cj = J * NB;
+    const int rows = min(NB, n - ri), cols = min(NB, n - cj);
+    double acc[4][4] = {};
+    tile_mac(acc, A + (size_t)ri * n + o, n, false, rows, A + (size_t)cj * n + o, n, true, cols, kk, As, Bs);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
+            int i = ty * 4 + u, j = tx * 4 + v;
+            if (i < rows && j < cols && (I != J || j <= i)) A[(size_t)(ri + i) * n + cj + j] -= acc[u][v];
+        }
+}
+
+// block row I of Y = L^{-1}: T_IJ = delta_IJ - sum_{K=J}^{I-1} L_IK Y_KJ, J <= I
+__global__ __launch_bounds__(kBlock) void k_trinv_rhs(const double* L, double* Y, int n, int I) {
+    __shared__ double As[NB][KS + 1];
+    __shared__ double Bs[KS][NB + 1];
+    const int J = blockIdx.x;
+    const int ri = I * NB, cj = J * NB;
+    const int rows = min(NB, n - ri), cols = min(NB, n - cj);
+    double acc[4][4] = {};
+    for (int K = J; K < I; ++K) {
+        const int ok = K * NB, kk = min(NB, n - ok);
+        tile_mac(acc, L + (size_t)ri * n + ok, n, false, rows, Y + (size_t)ok * n + cj, n, false, cols, kk, As, Bs);
+    }
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
+            int i = ty * 4 + u, j = tx * 4 + v;
+            if (i < rows && j < cols) {
+                double delta = (I == J && i == j) ? 1.0 : 0.0;
+                Y[(size_t)(ri + i) * n + cj + j] = delta - acc[u][v];
+            }
+        }
+}
+
+// Y_IJ <- L_II^{-1} T_IJ for J <= I: one thread per column of block row I
+__global__ __launch_bounds__(kBlock) void k_trinv_solve(const double* L, double* Y, int n, int I) {
+    __shared__ double Ld[NB][NB + 1];
+    const int o = I * NB, nb = min(NB, n - o);
+    for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+        int i = e / nb, j = e % nb;
+        Ld[i][j] = L[(size_t)(o + i) * n + o + j];
+    }
+    __syncthreads();
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= o + nb) return;   // columns right of the diagonal block are zero
+    double x[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) x[i] = (i < nb) ? Y[(size_t)(o + i) * n + c] : 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        if (i < nb) {
+            double s = x[i];
+            for (int k = 0; k < i; ++k) s -= Ld[i][k] * x[k];
+            x[i] = s / Ld[i][i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+        if (i < nb) Y[(size_t)(o + i) * n + c] = x[i];
+}
+
+// Ainv_IJ = sum_{K >= max(I,J)} Y_KI^T Y_KJ
+__global__ __launch_bounds__(kBlock) void k_yty(const double* Y, double* Ainv, int n, int nt) {
+    __shared__ double As[NB][KS + 1];
+    __shared__ double Bs[KS][NB + 1];
+    const int I = blockIdx.x / nt, J = blockIdx.x % nt;
+    const int ri = I * NB, cj = J * NB;
+    const int rows = min(NB, n - ri), cols = min(NB, n - cj);
+    double acc[4][4] = {};
+    for (int K = max(I, J); K < nt; ++K) {
+        const int ok = K * NB, kk = min(NB, n - ok);
+        // op(A) = (Y_KI)^T: rows of op(A) are columns ri.. of Y
+        tile_mac(acc, Y + (size_t)ok * n + ri, n, true, rows, Y + (size_t)ok * n + cj, n, false, cols, kk, As, Bs);
+    }
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
+            int i = ty * 4 + u, j = tx * 4 + v;
+            if (i < rows && j < cols) Ainv[(size_t)(ri + i) * n + cj + j] = acc[u][v];
+        }
+}
+
+__global__ void k_zero_upper(double* A, int n) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(e / n), j = (int)(e % n);
+        if (j > i) A[e] = 0.0;
+    }
+}
+
+}  // namespace
+
+bool dense_spd_inverse(int n, double* A, double* work, int* flag, hipStream_t s) {
+    if (n <= 0) return true;
+    const int nt = ceil_div(n, NB);
+    MATAMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    // Cholesky, lower triangle in place
+    for (int kb = 0; kb < nt; ++kb) {
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(kBlock), 0, s, A, n, kb, flag);
+        const int below = n - (kb + 1) * NB;
+        if (below > 0) {
+            hipLaunchKernelGGL(k_trsm_panel, dim3(ceil_div(below, kBlock)), dim3(kBlock), 0, s, A, n, kb);
+            const int t = nt - kb - 1;
+            hipLaunchKernelGGL(k_syrk_update, dim3(t * (t + 1) / 2), dim3(kBlock), 0, s, A, n, kb);
+        }
+    }
+    hipLaunchKernelGGL(k_zero_upper, dim3(1024), dim3(kBlock), 0, s, A, n);
+    MATAMG_LAUNCH_CHECK();
+    int hflag = 0;
+    d2h(&hflag, flag, 1, s);
+    if (hflag) return false;
+    // Y = L^{-1}, block row by block row
+    MATAMG_HIP(hipMemsetAsync(work, 0, sizeof(double) * (size_t)n * n, s));
+    for (int I = 0; I < nt; ++I) {
+        hipLaunchKernelGGL(k_trinv_rhs, dim3(I + 1), dim3(kBlock), 0, s, A, work, n, I);
+        const int ncols = min(n, (I + 1) * NB);
+        hipLaunchKernelGGL(k_trinv_solve, dim3(ceil_div(ncols, kBlock)), dim3(kBlock), 0, s, A, work, n, I);
+    }
+    // A^{-1} = Y^T Y
+    hipLaunchKernelGGL(k_yty, dim3(nt * nt), dim3(kBlock), 0, s, work, A, n, nt);
+    MATAMG_LAUNCH_CHECK();
+    return true;
+}
+
+}  // namespace matamg

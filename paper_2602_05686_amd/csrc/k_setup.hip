@@ -1,0 +1,586 @@
+// Setup-phase kernels.  This file is compiled with -ffp-contract=off: the
+// strength-of-connection arithmetic, the Clement means and the aggregate
+// means are evaluated one IEEE-754 operation at a time in a fixed order, so
+// the drop masks and aggregates they decide are bit-reproducible and equal to
+// any other evaluation of the same operation sequence.
+//
+// Paper references: Clement interpolant and auxiliary transfer (section 3,
+// eq. auxiliary_transfer); distance Laplacian and pointwise dropping
+// (section 2.1); material distance (section 3); aggregation and tentative
+// prolongator (section 2); filtered matrix and 1-norm diagonal (section 2.2,
+// eqs. filtered_matrix and 1_norm_diagonal).
+#pragma clang fp contract(off)
+
+#include "device_util.h"
+#include "kernels.h"
+#include "setup_kernels.h"
+
+namespace matamg {
+namespace {
+
+inline int grid_for(int64_t n) {
+    int g = ceil_div(n > 0 ? n : 1, kBlock);
+    return g;
+}
+
+#define ROW_LOOP(i, n) for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (n); i += (int64_t)gridDim.x * kBlock)
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// --------------------------------------------------------------- incidence
+__global__ void k_count_elem_nodes(const int* en, int64_t total, int n, int* cnt, int* flag) {
+    ROW_LOOP(e, total) {
+        int i = en[e];
+        if (i < 0 || i >= n) {
+            *flag = 1;
+            continue;
+        }
+        atomicAdd(cnt + i, 1);
+    }
+}
+
+__global__ void k_fill_elem_nodes(const int* en, int64_t total, int npe, int n, const int* rowptr, int* fill,
+                                  int* items) {
+    ROW_LOOP(e, total) {
+        int i = en[e];
+        if (i < 0 || i >= n) continue;
+        int pos = rowptr[i] + atomicAdd(fill + i, 1);
+        items[pos] = (int)(e / npe);
+    }
+}
+
+__global__ void k_count_agg(const int* agg, int n, int* cnt) {
+    ROW_LOOP(i, n) {
+        int a = agg[i];
+        if (a >= 0) atomicAdd(cnt + a, 1);
+    }
+}
+
+__global__ void k_fill_agg(const int* agg, int n, const int* rowptr, int* fill, int* items) {
+    ROW_LOOP(i, n) {
+        int a = agg[i];
+        if (a < 0) continue;
+        int pos = rowptr[a] + atomicAdd(fill + a, 1);
+        items[pos] = (int)i;
+    }
+}
+
+// ascending order within each list (insertion sort; lists are short)
+__global__ void k_sort_lists(int nt, const int* rowptr, int* items) {
+    ROW_LOOP(t, nt) {
+        int lo = rowptr[t], hi = rowptr[t + 1];
+        for (int a = lo + 1; a < hi; ++a) {
+            int v = items[a], b = a - 1;
+            while (b >= lo && items[b] > v) {
+                items[b + 1] = items[b];
+                --b;
+            }
+            items[b + 1] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------- level 1
+__global__ void k_detect_dirichlet(int n, const int* rowptr, const int* col, const double* val, uint8_t* dir) {
+    ROW_LOOP(i, n) {
+        int any = 0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (col[k] != i && val[k] != 0.0) {
+                any = 1;
+                break;
+            }
+        dir[i] = any ? 0 : 1;
+    }
+}
+
+// nodal tensor = arithmetic mean of the incident element tensors, summed in
+// ascending element id, one divide per component
+__global__ void k_clement(int n, int dim, const int* rowptr, const int* elems, const double* es, double* sig) {
+    const int nc = dim * (dim + 1) / 2;
+    ROW_LOOP(i, n) {
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        const int lo = rowptr[i], hi = rowptr[i + 1];
+        for (int k = lo; k < hi; ++k) {
+            const double* s = es + (size_t)elems[k] * dim * dim;
+            int c = 0;
+            for (int p = 0; p < dim; ++p)
+                for (int q = p; q < dim; ++q) acc[c++] += s[p * dim + q];
+        }
+        const int cnt = hi - lo;
+        for (int c = 0; c < nc; ++c) sig[(size_t)i * nc + c] = cnt > 0 ? acc[c] / (double)cnt : acc[c];
+    }
+}
+
+// sigma^{-1} by adjugate / determinant
+__global__ void k_tensor_inverse(int n, int dim, const double* sig, double* minv, int* flag) {
+    const int nc = dim * (dim + 1) / 2;
+    ROW_LOOP(i, n) {
+        const double* s = sig + (size_t)i * nc;
+        double* m = minv + (size_t)i * nc;
+        bool ok;
+        if (dim == 1) {
+            ok = s[0] > 0.0;
+            m[0] = 1.0 / s[0];
+        } else if (dim == 2) {
+            double s00 = s[0], s01 = s[1], s11 = s[2];
+            double det = s00 * s11 - s01 * s01;
+            ok = (det > 0.0) && (s00 > 0.0);
+            m[0] = s11 / det;
+            m[1] = (-s01) / det;
+            m[2] = s00 / det;
+        } else {
+            double s00 = s[0], s01 = s[1], s02 = s[2], s11 = s[3], s12 = s[4], s22 = s[5];
+            double c00 = s11 * s22 - s12 * s12;
+            double c01 = s02 * s12 - s01 * s22;
+            double c02 = s01 * s12 - s02 * s11;
+            double c11 = s00 * s22 - s02 * s02;
+            double c12 = s01 * s02 - s00 * s12;
+            double c22 = s00 * s11 - s01 * s01;
+            double det = (s00 * c00 + s01 * c01) + s02 * c02;
+            ok = (det > 0.0) && (s00 > 0.0) && (c22 > 0.0);
+            m[0] = c00 / det;
+            m[1] = c01 / det;
+            m[2] = c02 / det;
+            m[3] = c11 / det;
+            m[4] = c12 / det;
+            m[5] = c22 / det;
+        }
+        if (!ok) *flag = 1;
+    }
+}
+
+__device__ __forceinline__ double quad_form(int dim, const double* m, const double* d) {
+    if (dim == 1) return d[0] * (m[0] * d[0]);
+    if (dim == 2) {
+        double t0 = m[0] * d[0] + m[1] * d[1];
+        double t1 = m[1] * d[0] + m[2] * d[1];
+        return d[0] * t0 + d[1] * t1;
+    }
+    double t0 = (m[0] * d[0] + m[1] * d[1]) + m[2] * d[2];
+    double t1 = (m[1] * d[0] + m[3] * d[1]) + m[4] * d[2];
+    double t2 = (m[2] * d[0] + m[4] * d[1]) + m[5] * d[2];
+    return (d[0] * t0 + d[1] * t1) + d[2] * t2;
+}
+
+// |L_ij| = 1 / max(q_i, q_j), L_ii summed in ascending column order
+__global__ void k_soc_values(int n, const int* rowptr, const int* col, const double* val, int dim,
+                             const double* x, const double* minv, const uint8_t* dir, int soc, double* lval,
+                             double* ldiag) {
+    const int nc = dim * (dim + 1) / 2;
+    const double ident[3][6] = {{1, 0, 0, 0, 0, 0}, {1, 0, 1, 0, 0, 0}, {1, 0, 0, 1, 0, 1}};
+    ROW_LOOP(i, n) {
+        double li = 0.0;
+        double adiag = 0.0;
+        const bool di = dir && dir[i];
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int j = col[k];
+            double l = 0.0;
+            if (j == i) {
+                adiag = fabs(val[k]);
+            } else if (!(di || (dir && dir[j]))) {
+                if (soc == AMG_SOC_SA) {
+                    l = fabs(val[k]);
+                } else {
+                    double d[3];
+                    for (int a = 0; a < dim; ++a) d[a] = x[(size_t)j * dim + a] - x[(size_t)i * dim + a];
+                    const double* mi = soc == AMG_SOC_MATERIAL ? minv + (size_t)i * nc : ident[dim - 1];
+                    const double* mj = soc == AMG_SOC_MATERIAL ? minv + (size_t)j * nc : ident[dim - 1];
+                    double qi = quad_form(dim, mi, d);
+                    double qj = quad_form(dim, mj, d);
+                    double q = qi > qj ? qi : qj;
+                    if (!(q > 0.0) || !isfinite(q)) {
+                        l = -1.0;   // coincident points: strong, not in L_ii
+                    } else {
+                        l = 1.0 / q;
+                        li += l;
+                    }
+                }
+            }
+            lval[k] = l;
+        }
+        ldiag[i] = (soc == AMG_SOC_SA) ? adiag : li;
+    }
+}
+
+// S_ij = l / sqrt(L_ii L_jj); keep iff l*l >= (theta*theta) * (L_ii * L_jj)
+__global__ void k_soc_mask(int n, const int* rowptr, const int* col, const uint8_t* dir, const double* lval,
+                           const double* ldiag, double th2, double* S, uint8_t* mask) {
+    ROW_LOOP(i, n) {
+        const bool di = dir && dir[i];
+        const double lii = ldiag[i];
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int j = col[k];
+            double sv;
+            uint8_t m;
+            if (j == i) {
+                sv = 1.0;
+                m = 1;
+            } else if (di || (dir && dir[j])) {
+                sv = 0.0;
+                m = 0;
+            } else if (lval[k] < 0.0) {
+                sv = 1.0;
+                m = 1;
+            } else {
+                const double l = lval[k];
+                const double prod = lii * ldiag[j];
+                sv = (prod > 0.0) ? l / sqrt(prod) : 1.0;
+                m = (l * l >= th2 * prod) ? 1 : 0;
+            }
+            if (S) S[k] = sv;
+            mask[k] = m;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------- MIS
+__device__ __forceinline__ uint64_t tuple_of(uint8_t state, uint64_t key, int i) {
+    const uint64_t prio = splitmix64(key ^ (uint64_t)i) >> 34;   // top 30 bits
+    return ((uint64_t)state << 62) | (prio << 32) | (uint64_t)(uint32_t)i;
+}
+
+__global__ void k_mis_init(int n, const uint8_t* dir, uint8_t* state) {
+    ROW_LOOP(i, n) state[i] = (dir && dir[i]) ? MIS_OUT : MIS_UND;
+}
+
+// T1(i) = max over i and its kept neighbours of T0
+__global__ void k_mis_hop0(int n, const int* rowptr, const int* col, const uint8_t* mask, uint64_t key,
+                           const uint8_t* state, uint64_t* t1) {
+    ROW_LOOP(i, n) {
+        uint64_t best = tuple_of(state[i], key, (int)i);
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int j = col[k];
+            if (j == i || !mask[k]) continue;
+            uint64_t t = tuple_of(state[j], key, j);
+            best = t > best ? t : best;
+        }
+        t1[i] = best;
+    }
+}
+
+__global__ void k_mis_hop1(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint64_t* t1,
+                           uint64_t* t2) {
+    ROW_LOOP(i, n) {
+        uint64_t best = t1[i];
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int j = col[k];
+            if (j == i || !mask[k]) continue;
+            uint64_t t = t1[j];
+            best = t > best ? t : best;
+        }
+        t2[i] = best;
+    }
+}
+
+__global__ void k_mis_update(int n, uint64_t key, const uint64_t* t2, uint8_t* state, int* undecided) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    int local = 0;
+    ROW_LOOP(i, n) {
+        uint8_t st = state[i];
+        if (st != MIS_UND) continue;
+        const uint64_t own = tuple_of(st, key, (int)i);
+        const uint64_t t = t2[i];
+        if (t == own) st = MIS_IN;
+        else if ((t >> 62) == MIS_IN) st = MIS_OUT;
+        state[i] = st;
+        local += (st == MIS_UND);
+    }
+    if (local) atomicAdd(&cnt, local);
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt) atomicAdd(undecided, cnt);
+}
+
+__global__ void k_root_flags(int n, const uint8_t* state, int* flags) {
+    ROW_LOOP(i, n) flags[i] = (state[i] == MIS_IN) ? 1 : 0;
+}
+
+__global__ void k_agg_phase2(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint8_t* dir,
+                             const uint8_t* state, const int* rank, int* phase2) {
+    ROW_LOOP(i, n) {
+        int a = -1;
+        if (state[i] == MIS_IN) {
+            a = rank[i];
+        } else if (!(dir && dir[i])) {
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                const int j = col[k];
+                if (j == i || !mask[k]) continue;
+                if (state[j] == MIS_IN) {
+                    a = rank[j];
+                    break;
+                }
+            }
+        }
+        phase2[i] = a;
+    }
+}
+
+// remaining nodes join the phase-2 aggregate with the most kept neighbours,
+// ties to the smallest aggregate id
+__global__ void k_agg_phase3(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint8_t* dir,
+                             const int* phase2, int* agg) {
+    ROW_LOOP(i, n) {
+        int a = phase2[i];
+        if (a < 0 && !(dir && dir[i])) {
+            int best = -1, bestcnt = 0;
+            const int lo = rowptr[i], hi = rowptr[i + 1];
+            for (int k = lo; k < hi; ++k) {
+                const int j = col[k];
+                if (j == i || !mask[k] || phase2[j] < 0) continue;
+                const int c = phase2[j];
+                int cnt = 0;
+                for (int k2 = lo; k2 < hi; ++k2) {
+                    const int j2 = col[k2];
+                    if (j2 == i || !mask[k2]) continue;
+                    if (phase2[j2] == c) cnt++;
+                }
+                if (cnt > bestcnt || (cnt == bestcnt && c < best)) {
+                    best = c;
+                    bestcnt = cnt;
+                }
+            }
+            a = best;
+        }
+        agg[i] = a;
+    }
+}
+
+// ------------------------------------------------------------- prolongator
+__global__ void k_filter_count(int n, const int* rowptr, const int* col, const uint8_t* mask, int* cnt) {
+    ROW_LOOP(i, n) {
+        int c = 0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (col[k] == i || mask[k]) c++;
+        cnt[i] = c;
+    }
+}
+
+__global__ void k_filter_fill(int n, const int* rowptr, const int* col, const double* val, const uint8_t* mask,
+                              const int* frowptr, int* fcol, double* fval, double* dt, double* dtinv) {
+    ROW_LOOP(i, n) {
+        int p = frowptr[i];
+        int diagpos = -1;
+        double lump = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int j = col[k];
+            if (j == i || mask[k]) {
+                if (j == i) diagpos = p;
+                fcol[p] = j;
+                fval[p] = val[k];
+                p++;
+            } else {
+                lump += val[k];
+            }
+        }
+        if (diagpos >= 0) fval[diagpos] = fval[diagpos] + lump;
+        double s = 0.0;
+        for (int q = frowptr[i]; q < p; ++q) s += fabs(fval[q]);
+        dt[i] = s;
+        dtinv[i] = s > 0.0 ? 1.0 / s : 0.0;
+    }
+}
+
+__global__ void k_phat_counts(int n, const int* agg, int* cnt) {
+    ROW_LOOP(i, n) cnt[i] = agg[i] >= 0 ? 1 : 0;
+}
+
+__global__ void k_phat_fill(int n, const int* agg, const int* prowptr, int* pcol, double* pval) {
+    ROW_LOOP(i, n) {
+        if (agg[i] >= 0) {
+            pcol[prowptr[i]] = agg[i];
+            pval[prowptr[i]] = 1.0;
+        }
+    }
+}
+
+// P = P^ - omega Dt^{-1} (A_F P^), on the pattern of A_F P^
+__global__ void k_prolongator_finalize(int n, const int* prowptr, const int* pcol, double* pval, const int* agg,
+                                       const double* dt, double omega) {
+    ROW_LOOP(i, n) {
+        const double di = dt[i];
+        for (int k = prowptr[i]; k < prowptr[i + 1]; ++k) {
+            const double delta = (pcol[k] == agg[i]) ? 1.0 : 0.0;
+            const double corr = (di > 0.0) ? (omega * pval[k]) / di : 0.0;
+            pval[k] = delta - corr;
+        }
+    }
+}
+
+// coarse coordinates / tensors: member sums in ascending node id, one divide
+__global__ void k_coarse_aux(int nc, int dim, const int* rowptr, const int* members, const double* x,
+                             const double* sig, double* xc, double* sigc) {
+    const int ncomp = dim * (dim + 1) / 2;
+    ROW_LOOP(j, nc) {
+        double ax[3] = {0, 0, 0}, as[6] = {0, 0, 0, 0, 0, 0};
+        const int lo = rowptr[j], hi = rowptr[j + 1];
+        for (int k = lo; k < hi; ++k) {
+            const int i = members[k];
+            for (int a = 0; a < dim; ++a) ax[a] += x[(size_t)i * dim + a];
+            for (int c = 0; c < ncomp; ++c) as[c] += sig[(size_t)i * ncomp + c];
+        }
+        const double cnt = (double)(hi - lo);
+        for (int a = 0; a < dim; ++a) xc[(size_t)j * dim + a] = ax[a] / cnt;
+        for (int c = 0; c < ncomp; ++c) sigc[(size_t)j * ncomp + c] = as[c] / cnt;
+    }
+}
+
+__global__ void k_diag_inverse(int n, const int* rowptr, const int* col, const double* val, double* dinv) {
+    ROW_LOOP(i, n) {
+        double d = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (col[k] == i) d = val[k];
+        dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
+    }
+}
+
+__global__ void k_densify(int n, const int* rowptr, const int* col, const double* val, double* D) {
+    ROW_LOOP(i, n) {
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) D[(size_t)i * n + col[k]] = val[k];
+    }
+}
+
+__global__ void k_validate_csr(int n, const int* rowptr, const int* col, int64_t nnz, int* flag) {
+    ROW_LOOP(i, n) {
+        const int lo = rowptr[i], hi = rowptr[i + 1];
+        if (lo < 0 || hi < lo || hi > nnz) {
+            *flag = 1;
+            continue;
+        }
+        for (int k = lo; k < hi; ++k) {
+            const int c = col[k];
+            if (c < 0 || c >= n || (k > lo && c <= col[k - 1])) {
+                *flag = 1;
+                break;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+#define LAUNCH(kern, n, ...)                                                              \
+    do {                                                                                  \
+        if ((n) > 0) {                                                                    \
+            hipLaunchKernelGGL(kern, dim3(grid_for(n)), dim3(kBlock), 0, s, __VA_ARGS__); \
+            MATAMG_LAUNCH_CHECK();                                                        \
+        }                                                                                 \
+    } while (0)
+
+static void finish_incidence(Incidence& out, DBuf<int>& cnt, int nt, MemCounter* mc, hipStream_t s) {
+    out.rowptr.alloc((size_t)nt + 1, mc);
+    DBuf<int> tmp(scan_tmp_size(nt), mc);
+    exclusive_scan(cnt.get(), out.rowptr.get(), nt, tmp.get(), s);
+    MATAMG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (size_t)(nt > 0 ? nt : 1), s));
+}
+
+void build_node_elements(const int* en, int64_t nelem, int npe, int n, Incidence& out, int* flag, MemCounter* mc,
+                         hipStream_t s) {
+    const int64_t total = nelem * npe;
+    DBuf<int> cnt((size_t)n, mc);
+    MATAMG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (size_t)n, s));
+    LAUNCH(k_count_elem_nodes, total, en, total, n, cnt.get(), flag);
+    finish_incidence(out, cnt, n, mc, s);
+    out.items.alloc((size_t)(total > 0 ? total : 1), mc);
+    LAUNCH(k_fill_elem_nodes, total, en, total, npe, n, out.rowptr.get(), cnt.get(), out.items.get());
+    LAUNCH(k_sort_lists, n, n, out.rowptr.get(), out.items.get());
+    out.ntarget = n;
+}
+
+void build_aggregate_members(const int* agg, int n, int nagg, Incidence& out, MemCounter* mc, hipStream_t s) {
+    DBuf<int> cnt((size_t)(nagg > 0 ? nagg : 1), mc);
+    MATAMG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (size_t)(nagg > 0 ? nagg : 1), s));
+    LAUNCH(k_count_agg, n, agg, n, cnt.get());
+    finish_incidence(out, cnt, nagg, mc, s);
+    out.items.alloc((size_t)(n > 0 ? n : 1), mc);
+    LAUNCH(k_fill_agg, n, agg, n, out.rowptr.get(), cnt.get(), out.items.get());
+    LAUNCH(k_sort_lists, nagg, nagg, out.rowptr.get(), out.items.get());
+    out.ntarget = nagg;
+}
+
+void detect_dirichlet(int n, const int* rowptr, const int* col, const double* val, uint8_t* dir, hipStream_t s) {
+    LAUNCH(k_detect_dirichlet, n, n, rowptr, col, val, dir);
+}
+
+void clement(int n, int dim, const Incidence& inc, const double* es, double* sig, hipStream_t s) {
+    LAUNCH(k_clement, n, n, dim, inc.rowptr.get(), inc.items.get(), es, sig);
+}
+
+void tensor_inverse(int n, int dim, const double* sig, double* minv, int* flag, hipStream_t s) {
+    LAUNCH(k_tensor_inverse, n, n, dim, sig, minv, flag);
+}
+
+void soc_values(int n, const int* rowptr, const int* col, const double* val, int dim, const double* x,
+                const double* minv, const uint8_t* dir, int soc, double* lval, double* ldiag, hipStream_t s) {
+    LAUNCH(k_soc_values, n, n, rowptr, col, val, dim, x, minv, dir, soc, lval, ldiag);
+}
+
+void soc_mask(int n, const int* rowptr, const int* col, const uint8_t* dir, const double* lval,
+              const double* ldiag, double theta, double* S, uint8_t* mask, hipStream_t s) {
+    const double th2 = theta * theta;
+    LAUNCH(k_soc_mask, n, n, rowptr, col, dir, lval, ldiag, th2, S, mask);
+}
+
+void mis_init(int n, const uint8_t* dir, uint8_t* state, hipStream_t s) { LAUNCH(k_mis_init, n, n, dir, state); }
+
+void mis_round(int n, const int* rowptr, const int* col, const uint8_t* mask, uint64_t key, uint8_t* state,
+               uint64_t* t1, uint64_t* t2, int* undecided, hipStream_t s) {
+    MATAMG_HIP(hipMemsetAsync(undecided, 0, sizeof(int), s));
+    LAUNCH(k_mis_hop0, n, n, rowptr, col, mask, key, state, t1);
+    LAUNCH(k_mis_hop1, n, n, rowptr, col, mask, t1, t2);
+    LAUNCH(k_mis_update, n, n, key, t2, state, undecided);
+}
+
+void agg_root_flags(int n, const uint8_t* state, int* flags, hipStream_t s) {
+    LAUNCH(k_root_flags, n, n, state, flags);
+}
+
+void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint8_t* dir,
+                const uint8_t* state, const int* root_rank, int* phase2, int* agg, hipStream_t s) {
+    LAUNCH(k_agg_phase2, n, n, rowptr, col, mask, dir, state, root_rank, phase2);
+    LAUNCH(k_agg_phase3, n, n, rowptr, col, mask, dir, phase2, agg);
+}
+
+void filter_count(int n, const int* rowptr, const int* col, const uint8_t* mask, int* cnt, hipStream_t s) {
+    LAUNCH(k_filter_count, n, n, rowptr, col, mask, cnt);
+}
+
+void filter_fill(int n, const int* rowptr, const int* col, const double* val, const uint8_t* mask,
+                 const int* frowptr, int* fcol, double* fval, double* dt, double* dtinv, hipStream_t s) {
+    LAUNCH(k_filter_fill, n, n, rowptr, col, val, mask, frowptr, fcol, fval, dt, dtinv);
+}
+
+void phat_counts(int n, const int* agg, int* cnt, hipStream_t s) { LAUNCH(k_phat_counts, n, n, agg, cnt); }
+
+void phat_fill(int n, const int* agg, const int* prowptr, int* pcol, double* pval, hipStream_t s) {
+    LAUNCH(k_phat_fill, n, n, agg, prowptr, pcol, pval);
+}
+
+void prolongator_finalize(int n, const int* prowptr, const int* pcol, double* pval, const int* agg,
+                          const double* dt, double omega, hipStream_t s) {
+    LAUNCH(k_prolongator_finalize, n, n, prowptr, pcol, pval, agg, dt, omega);
+}
+
+void coarse_aux(int nc, int dim, const Incidence& m, const double* x, const double* sig, double* xc, double* sigc,
+                hipStream_t s) {
+    LAUNCH(k_coarse_aux, nc, nc, dim, m.rowptr.get(), m.items.get(), x, sig, xc, sigc);
+}
+
+void diag_inverse(int n, const int* rowptr, const int* col, const double* val, double* dinv, hipStream_t s) {
+    LAUNCH(k_diag_inverse, n, n, rowptr, col, val, dinv);
+}
+
+void densify(int n, const int* rowptr, const int* col, const double* val, double* D, hipStream_t s) {
+    LAUNCH(k_densify, n, n, rowptr, col, val, D);
+}
+
+void validate_csr(int n, const int* rowptr, const int* col, int64_t nnz, int* flag, hipStream_t s) {
+    LAUNCH(k_validate_csr, n, n, rowptr, col, nnz, flag);
+}
+
+}  // namespace matamg

@@ -1,0 +1,496 @@
+// Solve-path kernels: streaming CSR SpMV with fused smoother / residual /
+// transfer epilogues, deterministic FP64 reductions, CG vector updates,
+// dense coarse-level GEMV, and the integer prefix scan used by setup.
+//
+// Streaming CSR layout: rows are cut into blocks of at most kStreamCap
+// stored entries and kMaxRowsPerBlock rows.  A 256-thread block first streams
+// its contiguous val/col range (fully coalesced) and stores val*x[col] in
+// LDS, then one thread per row sums its products in ascending stored order
+// and applies the epilogue.  A row longer than kStreamCap gets a block of its
+// own that reduces it with a fixed tree.  Every sum therefore has a fixed
+// order for a given matrix: results are bitwise reproducible run to run.
+#include "device_util.h"
+#include "kernels.h"
+
+namespace matamg {
+
+// ===================================================================== scan
+namespace {
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ int block_exclusive_scan(int v, int* sh, int* total) {
+    // inclusive scan within the wave
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    int wave_off = 0, tot = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        if (i < w) wave_off += sh[i];
+        tot += sh[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return wave_off + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_partials(const int* in, int64_t n, int* sums) {
+    __shared__ int sh[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    int tot;
+    (void)block_exclusive_scan(s, sh, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_sums(int* sums, int nb) {
+    __shared__ int sh[kBlock / 64];
+    int carry = 0;
+    for (int base = 0; base < nb; base += kBlock) {
+        int i = base + threadIdx.x;
+        int v = (i < nb) ? sums[i] : 0;
+        int tot;
+        int ex = block_exclusive_scan(v, sh, &tot);
+        if (i < nb) sums[i] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const int* in, int* out, int64_t n, const int* sums,
+                                                       int nb) {
+    __shared__ int sh[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        v[k] = (i < n) ? in[i] : 0;
+        s += v[k];
+    }
+    int tot;
+    int ex = block_exclusive_scan(s, sh, &tot) + sums[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = ex;
+        ex += v[k];
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = sums[nb];
+}
+}  // namespace
+
+size_t scan_tmp_size(int64_t n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanTile) + 1; }
+
+void exclusive_scan(const int* in, int* out, int64_t n, int* tmp, hipStream_t s) {
+    if (n <= 0) {
+        MATAMG_HIP(hipMemsetAsync(out, 0, sizeof(int), s));
+        return;
+    }
+    int nb = ceil_div(n, kScanTile);
+    hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(kBlock), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, tmp, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, in, out, n, tmp, nb);
+    MATAMG_LAUNCH_CHECK();
+}
+
+// ====================================================================== dot
+namespace {
+inline int vec_grid(int64_t n) {
+    int g = ceil_div(n > 0 ? n : 1, kBlock);
+    return g < 2048 ? g : 2048;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dot(const T* a, const T* b, int64_t n, DotTarget dt) {
+    __shared__ double sh[kBlock / 64];
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        v += (double)a[i] * (double)b[i];
+    double t = block_sum(v, sh);
+    finalize_sum(t, dt, sh);
+}
+}  // namespace
+
+template <typename T>
+void dot(const T* a, const T* b, int64_t n, double* partial, unsigned* counter, double* result, hipStream_t s) {
+    DotTarget dt{partial, counter, result};
+    hipLaunchKernelGGL(k_dot<T>, dim3(vec_grid(n)), dim3(kBlock), 0, s, a, b, n, dt);
+    MATAMG_LAUNCH_CHECK();
+}
+template void dot<double>(const double*, const double*, int64_t, double*, unsigned*, double*, hipStream_t);
+template void dot<float>(const float*, const float*, int64_t, double*, unsigned*, double*, hipStream_t);
+
+// =============================================================== streaming
+std::vector<int> stream_blocks(const int* rp, int n) {
+    std::vector<int> blk;
+    blk.reserve((size_t)n / 32 + 2);
+    blk.push_back(0);
+    int cur = 0, rows = 0;
+    for (int r = 0; r < n; ++r) {
+        int len = rp[r + 1] - rp[r];
+        if (len > kStreamCap) {
+            if (rows > 0) blk.push_back(r);
+            blk.push_back(r + 1);
+            cur = 0;
+            rows = 0;
+            continue;
+        }
+        if (rows > 0 && (cur + len > kStreamCap || rows == kMaxRowsPerBlock)) {
+            blk.push_back(r);
+            cur = 0;
+            rows = 0;
+        }
+        cur += len;
+        rows++;
+    }
+    if (blk.back() != n) blk.push_back(n);
+    return blk;
+}
+
+namespace {
+enum Mode { M_PLAIN = 0, M_RESID = 1, M_ADD = 2, M_SMOOTH = 3, M_DOTPQ = 4, M_RESNORM = 5, M_SCALENORM = 6 };
+
+template <typename T>
+struct SArgs {
+    const int* rowptr;
+    const int* col;
+    const T* val;
+    const int* blk;
+    const T* x;        // gathered operand
+    const T* b;        // right-hand side (RESID, SMOOTH, RESNORM)
+    const T* yin;      // ADD: base vector; SMOOTH: iterate at the row
+    const T* dinv;     // SMOOTH: inverse diagonal; SCALENORM: row scale
+    T* d;              // SMOOTH: direction (in/out)
+    T* y;              // output
+    double* y64;       // SMOOTH: FP64 output instead of y
+    const double* dotvec;  // SMOOTH: fused dot partner
+    T c1, c2;
+    DotTarget dt;
+};
+
+template <typename T, int MODE, bool HAS_DOT>
+__device__ __forceinline__ double epilogue(const SArgs<T>& a, int r, T s) {
+    double dp = 0.0;
+    if constexpr (MODE == M_PLAIN) {
+        a.y[r] = s;
+    } else if constexpr (MODE == M_RESID) {
+        a.y[r] = a.b[r] - s;
+    } else if constexpr (MODE == M_ADD) {
+        a.y[r] = a.yin[r] + s;
+    } else if constexpr (MODE == M_SMOOTH) {
+        T res = a.b[r] - s;
+        T dn = a.c1 * a.d[r] + a.c2 * (a.dinv[r] * res);
+        a.d[r] = dn;
+        T xn = a.yin[r] + dn;
+        if (a.y64) a.y64[r] = (double)xn;
+        else a.y[r] = xn;
+        if constexpr (HAS_DOT) dp = (double)xn * a.dotvec[r];
+    } else if constexpr (MODE == M_DOTPQ) {
+        a.y[r] = s;
+        dp = (double)a.x[r] * (double)s;
+    } else if constexpr (MODE == M_RESNORM) {
+        T v = a.b[r] - s;
+        a.y[r] = v;
+        dp = (double)v * (double)v;
+    } else if constexpr (MODE == M_SCALENORM) {
+        T v = a.dinv[r] * s;
+        a.y[r] = v;
+        dp = (double)v * (double)v;
+    }
+    return dp;
+}
+
+template <typename T, int MODE, bool HAS_DOT>
+__global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a) {
+    __shared__ T prod[kStreamCap];
+    __shared__ double sh[kBlock / 64];
+    __shared__ T shr[kBlock / 64];
+    const int r0 = a.blk[blockIdx.x], r1 = a.blk[blockIdx.x + 1];
+    const int k0 = a.rowptr[r0], k1 = a.rowptr[r1];
+    const int cnt = k1 - k0;
+    double dp = 0.0;
+    if (cnt <= kStreamCap) {
+        for (int t = threadIdx.x; t < cnt; t += kBlock) {
+            const int k = k0 + t;
+            prod[t] = a.val[k] * a.x[a.col[k]];
+        }
+        __syncthreads();
+        const int r = r0 + (int)threadIdx.x;
+        if (r < r1) {
+            const int s0 = a.rowptr[r] - k0, s1 = a.rowptr[r + 1] - k0;
+            T s = 0;
+            for (int k = s0; k < s1; ++k) s += prod[k];
+            dp = epilogue<T, MODE, HAS_DOT>(a, r, s);
+        }
+    } else {
+        // one long row: strided partial sums then a fixed tree
+        T s = 0;
+        for (int t = threadIdx.x; t < cnt; t += kBlock) {
+            const int k = k0 + t;
+            s += a.val[k] * a.x[a.col[k]];
+        }
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) shr[w] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            T t = shr[0];
+            for (int i = 1; i < kBlock / 64; ++i) t += shr[i];
+            dp = epilogue<T, MODE, HAS_DOT>(a, r0, t);
+        }
+    }
+    if constexpr (HAS_DOT) {
+        double t = block_sum(dp, sh);
+        finalize_sum(t, a.dt, sh);
+    }
+}
+
+template <typename T, int MODE, bool HAS_DOT>
+void launch_stream(const DCsr& A, const SArgs<T>& a, hipStream_t s) {
+    if (A.nblk <= 0) return;
+    hipLaunchKernelGGL((k_stream<T, MODE, HAS_DOT>), dim3(A.nblk), dim3(kBlock), 0, s, a);
+    MATAMG_LAUNCH_CHECK();
+}
+
+template <typename T>
+SArgs<T> base_args(const DCsr& A, const T* val, const T* x) {
+    SArgs<T> a{};
+    a.rowptr = A.rowptr.get();
+    a.col = A.col.get();
+    a.val = val;
+    a.blk = A.blk.get();
+    a.x = x;
+    return a;
+}
+}  // namespace
+
+template <typename T>
+void spmv(const DCsr& A, const T* val, const T* x, T* y, hipStream_t s) {
+    auto a = base_args<T>(A, val, x);
+    a.y = y;
+    launch_stream<T, M_PLAIN, false>(A, a, s);
+}
+
+template <typename T>
+void spmv_resid(const DCsr& A, const T* val, const T* x, const T* b, T* y, hipStream_t s) {
+    auto a = base_args<T>(A, val, x);
+    a.b = b;
+    a.y = y;
+    launch_stream<T, M_RESID, false>(A, a, s);
+}
+
+template <typename T>
+void spmv_add(const DCsr& A, const T* val, const T* x, const T* y_in, T* y, hipStream_t s) {
+    auto a = base_args<T>(A, val, x);
+    a.yin = y_in;
+    a.y = y;
+    launch_stream<T, M_ADD, false>(A, a, s);
+}
+
+template <typename T>
+void spmv_smooth(const DCsr& A, const T* val, const T* x, const T* b, const T* dinv, T* d, T c1, T c2, T* out,
+                 double* out64, const double* dotvec, DotTarget dt, hipStream_t s) {
+    auto a = base_args<T>(A, val, x);
+    a.b = b;
+    a.yin = x;
+    a.dinv = dinv;
+    a.d = d;
+    a.c1 = c1;
+    a.c2 = c2;
+    a.y = out;
+    a.y64 = out64;
+    a.dotvec = dotvec;
+    a.dt = dt;
+    if (dotvec) launch_stream<T, M_SMOOTH, true>(A, a, s);
+    else launch_stream<T, M_SMOOTH, false>(A, a, s);
+}
+
+void spmv_dot(const DCsr& A, const double* p, double* q, DotTarget dt, hipStream_t s) {
+    auto a = base_args<double>(A, A.val.get(), p);
+    a.y = q;
+    a.dt = dt;
+    launch_stream<double, M_DOTPQ, true>(A, a, s);
+}
+
+void spmv_resid_norm(const DCsr& A, const double* x, const double* b, double* y, DotTarget dt, hipStream_t s) {
+    auto a = base_args<double>(A, A.val.get(), x);
+    a.b = b;
+    a.y = y;
+    a.dt = dt;
+    launch_stream<double, M_RESNORM, true>(A, a, s);
+}
+
+void spmv_scale_norm(const DCsr& A, const double* x, const double* dscale, double* y, DotTarget dt,
+                     hipStream_t s) {
+    auto a = base_args<double>(A, A.val.get(), x);
+    a.dinv = dscale;
+    a.y = y;
+    a.dt = dt;
+    launch_stream<double, M_SCALENORM, true>(A, a, s);
+}
+
+#define INST(T)                                                                                        \
+    template void spmv<T>(const DCsr&, const T*, const T*, T*, hipStream_t);                          \
+    template void spmv_resid<T>(const DCsr&, const T*, const T*, const T*, T*, hipStream_t);          \
+    template void spmv_add<T>(const DCsr&, const T*, const T*, const T*, T*, hipStream_t);            \
+    template void spmv_smooth<T>(const DCsr&, const T*, const T*, const T*, const T*, T*, T, T, T*,   \
+                                 double*, const double*, DotTarget, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+// ================================================================= vectors
+namespace {
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_smooth_first(int64_t n, const double* b64, T* b, const T* dinv, T c2,
+                                                         T* d, T* x) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        T bi;
+        if (b64) {
+            bi = (T)b64[i];
+            b[i] = bi;
+        } else {
+            bi = b[i];
+        }
+        T di = c2 * (dinv[i] * bi);
+        d[i] = di;
+        x[i] = di;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_inv_norm(int64_t n, const double* nrm2, const double* in,
+                                                           double* out) {
+    const double inv = 1.0 / sqrt(*nrm2);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        out[i] = in[i] * inv;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, double* x, double* r, const double* p,
+                                                      const double* q, const double* rz, const double* pq,
+                                                      DotTarget dt) {
+    __shared__ double sh[kBlock / 64];
+    // a non-positive or non-finite curvature is a breakdown: leave x and r
+    // unchanged so the caller keeps the last iterate
+    const double pqv = *pq, rzv = *rz;
+    const double alpha = (pqv > 0.0 && isfinite(pqv) && isfinite(rzv)) ? rzv / pqv : 0.0;
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        x[i] = x[i] + alpha * p[i];
+        double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        v += ri * ri;
+    }
+    double t = block_sum(v, sh);
+    finalize_sum(t, dt, sh);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_direction(int64_t n, double* p, const double* z,
+                                                         const double* rz_new, const double* rz_old) {
+    const double beta = rz_old ? (*rz_new / *rz_old) : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = rz_old ? z[i] + beta * p[i] : z[i];
+}
+
+template <typename A, typename B>
+__global__ __launch_bounds__(kBlock) void k_cast(int64_t n, const A* in, B* out) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        out[i] = (B)in[i];
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seeded_uniform(int64_t n, uint64_t key, double* v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        uint64_t h = splitmix64(key ^ (uint64_t)i);
+        double u = (double)(h >> 11) * (1.0 / 9007199254740992.0);
+        v[i] = 2.0 * u - 1.0;
+    }
+}
+}  // namespace
+
+template <typename T>
+void smooth_first(int64_t n, const double* b64, T* b, const T* dinv, T c2, T* d, T* x, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_smooth_first<T>, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, b64, b, dinv, c2, d, x);
+    MATAMG_LAUNCH_CHECK();
+}
+template void smooth_first<double>(int64_t, const double*, double*, const double*, double, double*, double*,
+                                   hipStream_t);
+template void smooth_first<float>(int64_t, const double*, float*, const float*, float, float*, float*,
+                                  hipStream_t);
+
+void scale_by_inv_norm(int64_t n, const double* nrm2, const double* in, double* out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_scale_inv_norm, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, nrm2, in, out);
+    MATAMG_LAUNCH_CHECK();
+}
+
+void cg_update(int64_t n, double* x, double* r, const double* p, const double* q, const double* rz,
+               const double* pq, DotTarget rr, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, x, r, p, q, rz, pq, rr);
+    MATAMG_LAUNCH_CHECK();
+}
+
+void cg_direction(int64_t n, double* p, const double* z, const double* rz_new, const double* rz_old,
+                  hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_cg_direction, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, p, z, rz_new, rz_old);
+    MATAMG_LAUNCH_CHECK();
+}
+
+template <typename A, typename B>
+void cast_vec(int64_t n, const A* in, B* out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_cast<A, B>), dim3(vec_grid(n)), dim3(kBlock), 0, s, n, in, out);
+    MATAMG_LAUNCH_CHECK();
+}
+template void cast_vec<double, float>(int64_t, const double*, float*, hipStream_t);
+template void cast_vec<float, double>(int64_t, const float*, double*, hipStream_t);
+
+void fill_seeded_uniform(int64_t n, uint64_t key, double* v, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_seeded_uniform, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, key, v);
+    MATAMG_LAUNCH_CHECK();
+}
+
+// =================================================================== dense
+namespace {
+// one wavefront per row of the dense inverse; FP64 accumulation
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const double* M, const T* in, T* out) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const double* m = M + (size_t)row * n;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += m[j] * (double)in[j];
+    s = wave_sum(s);
+    if (lane == 0) out[row] = (T)s;
+}
+}  // namespace
+
+template <typename T>
+void dense_gemv(int n, const double* M, const T* in, T* out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_dense_gemv<T>, dim3(ceil_div(n, kBlock / 64)), dim3(kBlock), 0, s, n, M, in, out);
+    MATAMG_LAUNCH_CHECK();
+}
+template void dense_gemv<double>(int, const double*, const double*, double*, hipStream_t);
+template void dense_gemv<float>(int, const double*, const float*, float*, hipStream_t);
+
+}  // namespace matamg

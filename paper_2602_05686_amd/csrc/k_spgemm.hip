@@ -1,0 +1,414 @@
+// Sparse matrix-matrix product C = A * B (Galerkin product R (A P) and the
+// smoothed prolongator A_F P^) and the CSR transpose P -> R = P^T.
+//
+// One wavefront per output row.  The row's products are enumerated in the
+// canonical order (A's row ascending, then B's row order), 64 at a time: the
+// lanes scan the B-row lengths of up to 64 A-entries, then each product
+// index is mapped to its (A entry, B entry) pair by a binary search over the
+// scanned offsets.  Symbolic phase: product columns go into an open-addressed
+// hash set in LDS (1024 slots per wave, at most 512 distinct columns); rows
+// that overflow it are redone with a table in global memory sized from the
+// row's product count.  Numeric phase: the distinct columns are compacted and
+// rank-sorted (ascending output columns), and the products are accumulated
+// strictly in canonical order by one lane, so every entry is the same
+// sequence of IEEE additions as a serial row-by-row product.
+#pragma clang fp contract(off)
+
+#include "device_util.h"
+#include "kernels.h"
+#include "setup_kernels.h"
+
+namespace matamg {
+namespace {
+
+constexpr int kWaves = kBlock / 64;
+constexpr int kHS = 1024;     // LDS hash slots per wave
+constexpr int kDMax = 512;    // max distinct columns on the LDS path
+
+__device__ __forceinline__ unsigned hash_slot(int key, unsigned mask) {
+    return ((unsigned)key * 2654435761u) & mask;
+}
+
+// insert key; returns 1 if newly inserted, 0 if present, -1 if the table is full
+__device__ __forceinline__ int hash_insert(int* keys, unsigned mask, int key) {
+    unsigned h = hash_slot(key, mask);
+    for (unsigned probe = 0; probe <= mask; ++probe) {
+        int old = atomicCAS(keys + h, -1, key);
+        if (old == -1) return 1;
+        if (old == key) return 0;
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
+// Enumerate the products of row i of A*B in canonical order, 64 per step.
+// f(valid, colB, value, t0, total) is called by every lane for each step of
+// 64 products starting at t0; lanes past the end get valid = false.  All
+// cross-lane traffic uses shuffles, so every lane executes the same steps.
+template <bool NEED_VAL, typename F>
+__device__ void for_each_product(const int* arp, const int* acol, const double* aval, const int* brp,
+                                 const int* bcol, const double* bval, int i, F&& f) {
+    const int lane = threadIdx.x & 63;
+    const int a0 = arp[i], a1 = arp[i + 1];
+    for (int c0 = a0; c0 < a1; c0 += 64) {
+        const int ka = c0 + lane;
+        int blen = 0, bstart = 0;
+        double av = 0.0;
+        if (ka < a1) {
+            const int k = acol[ka];
+            bstart = brp[k];
+            blen = brp[k + 1] - bstart;
+            if (NEED_VAL) av = aval[ka];
+        }
+        int incl = blen;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        const int excl = incl - blen;
+        const int total = __shfl(incl, 63, 64);
+        for (int t0 = 0; t0 < total; t0 += 64) {
+            const int t = t0 + lane;
+            const bool valid = t < total;
+            // source = last lane whose exclusive offset is <= t (empty B rows
+            // share their offset with the next non-empty one, which wins)
+            int lo = 0, hi = 63;
+            for (int it = 0; it < 6; ++it) {
+                const int mid = (lo + hi + 1) >> 1;
+                const int om = __shfl(excl, mid, 64);
+                if (om <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const int sb = __shfl(bstart, lo, 64);
+            const int so = __shfl(excl, lo, 64);
+            const double sa = NEED_VAL ? __shfl(av, lo, 64) : 0.0;
+            int colB = 0;
+            double pv = 0.0;
+            if (valid) {
+                const int kb = sb + (t - so);
+                colB = bcol[kb];
+                if (NEED_VAL) pv = sa * bval[kb];
+            }
+            f(valid, colB, pv, t0, total);
+        }
+    }
+}
+
+__device__ __forceinline__ int ld_key(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// memory ordering between the phases of one wavefront's row: release and
+// acquire at agent scope also invalidate the vector L1, so values written
+// through L2 (atomics) are re-read from L2
+__device__ __forceinline__ void phase_fence() {
+    __builtin_amdgcn_wave_barrier();
+    __threadfence();
+    __builtin_amdgcn_wave_barrier();
+}
+
+// slot of a key known to be present; the probe count is bounded by the table size
+__device__ __forceinline__ unsigned hash_find_fresh(const int* keys, unsigned mask, int key) {
+    unsigned h = hash_slot(key, mask);
+    for (unsigned probe = 0; probe <= mask; ++probe) {
+        if (ld_key(keys + h) == key) return h;
+        h = (h + 1) & mask;
+    }
+    return 0;
+}
+
+template <bool GLOBAL>
+__global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int* rows, const int* arp,
+                                                            const int* acol, const int* brp, const int* bcol,
+                                                            int* cnt, int* gkeys, const int64_t* goff) {
+    __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kHS];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ridx = blockIdx.x * kWaves + w;
+    if (ridx >= nrows) return;
+    const int i = rows ? rows[ridx] : ridx;
+    int* keys;
+    unsigned mask;
+    if (GLOBAL) {
+        const int64_t o = goff[ridx];
+        keys = gkeys + o;
+        mask = (unsigned)(goff[ridx + 1] - o) - 1;
+    } else {
+        keys = skeys[w];
+        mask = kHS - 1;
+    }
+    for (unsigned h = lane; h <= mask; h += 64) keys[h] = -1;
+    phase_fence();
+    int added = 0;
+    int full = 0;
+    for_each_product<false>(arp, acol, nullptr, brp, bcol, nullptr, i,
+                            [&](bool valid, int c, double, int, int) {
+                                if (valid) {
+                                    const int r = hash_insert(keys, mask, c);
+                                    if (r > 0) added++;
+                                    if (r < 0) full = 1;
+                                }
+                            });
+    for (int off = 32; off > 0; off >>= 1) {
+        added += __shfl_down(added, off, 64);
+        full |= __shfl_down(full, off, 64);
+    }
+    if (lane == 0) {
+        if (!GLOBAL && (full || added > kDMax)) cnt[i] = -1;
+        else cnt[i] = added;
+    }
+}
+
+template <bool GLOBAL>
+__global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int* rows, const int* arp,
+                                                           const int* acol, const double* aval, const int* brp,
+                                                           const int* bcol, const double* bval, const int* crp,
+                                                           int* ccol, double* cval, const int* skip, int* gkeys,
+                                                           int* gvals, double* gacc, const int64_t* goff) {
+    __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kHS];
+    __shared__ int svals[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kHS];
+    __shared__ double sacc[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kDMax];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ridx = blockIdx.x * kWaves + w;
+    if (ridx >= nrows) return;
+    const int i = rows ? rows[ridx] : ridx;
+    if (!GLOBAL && skip && skip[i]) return;
+    int *keys, *vals;
+    double* acc;
+    unsigned mask;
+    if (GLOBAL) {
+        const int64_t o = goff[ridx];
+        keys = gkeys + o;
+        vals = gvals + o;
+        acc = gacc + o;
+        mask = (unsigned)(goff[ridx + 1] - o) - 1;
+    } else {
+        keys = skeys[w];
+        vals = svals[w];
+        acc = sacc[w];
+        mask = kHS - 1;
+    }
+    for (unsigned h = lane; h <= mask; h += 64) {
+        keys[h] = -1;
+        vals[h] = 0;
+    }
+    phase_fence();
+    for_each_product<false>(arp, acol, nullptr, brp, bcol, nullptr, i,
+                            [&](bool valid, int c, double, int, int) {
+                                if (valid) (void)hash_insert(keys, mask, c);
+                            });
+    phase_fence();
+    // compact the occupied slots into the output column range (arbitrary order)
+    const int base = crp[i];
+    const int d = crp[i + 1] - base;
+    int* cl = ccol + base;
+    int filled = 0;
+    for (unsigned h0 = 0; h0 <= mask; h0 += 64) {
+        const unsigned h = h0 + lane;
+        const int key = (h <= mask) ? ld_key(keys + h) : -1;
+        const bool occ = key >= 0;
+        const uint64_t bal = __ballot(occ);
+        const int before = __popcll(bal & ((1ull << lane) - 1ull));
+        if (occ && filled + before < d) cl[filled + before] = key;
+        filled += __popcll(bal);
+    }
+    phase_fence();
+    // rank of each column among the row's columns = its output position
+    for (int e = lane; e < d; e += 64) {
+        const int c = cl[e];
+        int r = 0;
+        for (int q = 0; q < d; ++q) r += (cl[q] < c);
+        vals[hash_find_fresh(keys, mask, c)] = r;
+    }
+    phase_fence();
+    for (unsigned h = lane; h <= mask; h += 64) {
+        const int key = ld_key(keys + h);
+        const int r = vals[h];
+        if (key >= 0 && r >= 0 && r < d) cl[r] = key;
+    }
+    for (int e = lane; e < d; e += 64) acc[e] = 0.0;
+    phase_fence();
+    // accumulate in canonical product order; one lane performs every addition
+    for_each_product<true>(arp, acol, aval, brp, bcol, bval, i,
+                           [&](bool valid, int c, double pv, int t0, int total) {
+                               int r = valid ? vals[hash_find_fresh(keys, mask, c)] : 0;
+                               r = (r >= 0 && r < d) ? r : 0;
+                               const int m = min(64, total - t0);
+                               for (int q = 0; q < m; ++q) {
+                                   const int rq = __shfl(r, q, 64);
+                                   const double vq = __shfl(pv, q, 64);
+                                   if (lane == 0) acc[rq] += vq;
+                               }
+                           });
+    phase_fence();
+    for (int e = lane; e < d; e += 64) cval[base + e] = acc[e];
+}
+
+// product-count upper bound of each listed row, as a hash table size (power of two >= 2*m)
+__global__ void k_row_table_size(int nrows, const int* rows, const int* arp, const int* acol, const int* brp,
+                                 int ncols, int64_t* size) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += gridDim.x * blockDim.x) {
+        const int i = rows[r];
+        int64_t m = 0;
+        for (int k = arp[i]; k < arp[i + 1]; ++k) m += brp[acol[k] + 1] - brp[acol[k]];
+        if (m > ncols) m = ncols;
+        int64_t t = 64;
+        while (t < 2 * m) t <<= 1;
+        size[r] = t;
+    }
+}
+
+__global__ void k_overflow_flags(int n, const int* cnt, int* flags) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        flags[i] = cnt[i] < 0 ? 1 : 0;
+}
+
+__global__ void k_overflow_list(int n, const int* flags, const int* pos, int* list) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        if (flags[i]) list[pos[i]] = i;
+}
+
+__global__ void k_scan64(int n, const int64_t* in, int64_t* out) {
+    // small serial exclusive scan (overflow rows are few)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int64_t s = 0;
+        for (int i = 0; i < n; ++i) {
+            out[i] = s;
+            s += in[i];
+        }
+        out[n] = s;
+    }
+}
+
+// ---------------------------------------------------------------- transpose
+__global__ void k_col_counts(int64_t nnz, const int* col, int* cnt) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(cnt + col[k], 1);
+}
+
+__global__ void k_transpose_fill(int n, const int* rp, const int* col, const double* val, const int* trp,
+                                 int* fill, int* tcol, double* tval) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            const int c = col[k];
+            const int p = trp[c] + atomicAdd(fill + c, 1);
+            tcol[p] = i;
+            tval[p] = val[k];
+        }
+    }
+}
+
+__global__ void k_sort_pairs(int n, const int* rp, int* col, double* val) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int lo = rp[i], hi = rp[i + 1];
+        for (int a = lo + 1; a < hi; ++a) {
+            const int c = col[a];
+            const double v = val[a];
+            int b = a - 1;
+            while (b >= lo && col[b] > c) {
+                col[b + 1] = col[b];
+                val[b + 1] = val[b];
+                --b;
+            }
+            col[b + 1] = c;
+            val[b + 1] = v;
+        }
+    }
+}
+
+inline int g1(int64_t n) {
+    int g = ceil_div(n > 0 ? n : 1, kBlock);
+    return g < 65535 ? g : 65535;
+}
+
+}  // namespace
+
+void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s) {
+    const int n = A.n;
+    C.n = n;
+    C.m = B.m;
+    const int nn = n > 0 ? n : 1;
+    DBuf<int> cnt((size_t)nn, mc), flags((size_t)nn, mc), pos((size_t)n + 1, mc);
+    DBuf<int> tmp(scan_tmp_size(n), mc);
+    const int nb = ceil_div(nn, kWaves);
+    if (n > 0) {
+        hipLaunchKernelGGL((k_spgemm_symbolic<false>), dim3(nb), dim3(kBlock), 0, s, n, (const int*)nullptr,
+                           A.rowptr.get(), A.col.get(), B.rowptr.get(), B.col.get(), cnt.get(), (int*)nullptr,
+                           (const int64_t*)nullptr);
+        hipLaunchKernelGGL(k_overflow_flags, dim3(g1(n)), dim3(kBlock), 0, s, n, cnt.get(), flags.get());
+        MATAMG_LAUNCH_CHECK();
+    }
+    exclusive_scan(flags.get(), pos.get(), n, tmp.get(), s);
+    int novf = 0;
+    d2h(&novf, pos.get() + n, 1, s);
+    DBuf<int> list;
+    DBuf<int64_t> tsize, toff;
+    DBuf<int> gkeys, gvals;
+    DBuf<double> gacc;
+    if (novf > 0) {
+        // rows with more distinct columns than the LDS table holds
+        list.alloc((size_t)novf, mc);
+        hipLaunchKernelGGL(k_overflow_list, dim3(g1(n)), dim3(kBlock), 0, s, n, flags.get(), pos.get(), list.get());
+        tsize.alloc((size_t)novf, mc);
+        toff.alloc((size_t)novf + 1, mc);
+        hipLaunchKernelGGL(k_row_table_size, dim3(g1(novf)), dim3(kBlock), 0, s, novf, list.get(), A.rowptr.get(),
+                           A.col.get(), B.rowptr.get(), B.m, tsize.get());
+        hipLaunchKernelGGL(k_scan64, dim3(1), dim3(1), 0, s, novf, tsize.get(), toff.get());
+        int64_t tot = 0;
+        d2h(&tot, toff.get() + novf, 1, s);
+        gkeys.alloc((size_t)tot, mc);
+        gvals.alloc((size_t)tot, mc);
+        gacc.alloc((size_t)tot, mc);
+        hipLaunchKernelGGL((k_spgemm_symbolic<true>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
+                           list.get(), A.rowptr.get(), A.col.get(), B.rowptr.get(), B.col.get(), cnt.get(),
+                           gkeys.get(), toff.get());
+        MATAMG_LAUNCH_CHECK();
+    }
+    C.rowptr.alloc((size_t)n + 1, mc);
+    exclusive_scan(cnt.get(), C.rowptr.get(), n, tmp.get(), s);
+    int nnz = 0;
+    d2h(&nnz, C.rowptr.get() + n, 1, s);
+    C.nnz = nnz;
+    C.col.alloc((size_t)(nnz > 0 ? nnz : 1), mc);
+    C.val.alloc((size_t)(nnz > 0 ? nnz : 1), mc);
+    if (n > 0) {
+        hipLaunchKernelGGL((k_spgemm_numeric<false>), dim3(nb), dim3(kBlock), 0, s, n, (const int*)nullptr,
+                           A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(), B.val.get(),
+                           C.rowptr.get(), C.col.get(), C.val.get(), (const int*)flags.get(), (int*)nullptr,
+                           (int*)nullptr, (double*)nullptr, (const int64_t*)nullptr);
+        MATAMG_LAUNCH_CHECK();
+    }
+    if (novf > 0) {
+        hipLaunchKernelGGL((k_spgemm_numeric<true>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
+                           list.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(),
+                           B.val.get(), C.rowptr.get(), C.col.get(), C.val.get(), (const int*)nullptr, gkeys.get(),
+                           gvals.get(), gacc.get(), toff.get());
+        MATAMG_LAUNCH_CHECK();
+    }
+    MATAMG_HIP(hipStreamSynchronize(s));
+}
+
+void transpose(const DCsr& A, DCsr& T, MemCounter* mc, hipStream_t s) {
+    const int n = A.n, m = A.m;
+    T.n = m;
+    T.m = n;
+    T.nnz = A.nnz;
+    DBuf<int> cnt((size_t)(m > 0 ? m : 1), mc);
+    MATAMG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (size_t)(m > 0 ? m : 1), s));
+    if (A.nnz > 0)
+        hipLaunchKernelGGL(k_col_counts, dim3(g1(A.nnz)), dim3(kBlock), 0, s, A.nnz, A.col.get(), cnt.get());
+    T.rowptr.alloc((size_t)m + 1, mc);
+    DBuf<int> tmp(scan_tmp_size(m), mc);
+    exclusive_scan(cnt.get(), T.rowptr.get(), m, tmp.get(), s);
+    MATAMG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (size_t)(m > 0 ? m : 1), s));
+    T.col.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), mc);
+    T.val.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), mc);
+    if (n > 0)
+        hipLaunchKernelGGL(k_transpose_fill, dim3(g1(n)), dim3(kBlock), 0, s, n, A.rowptr.get(), A.col.get(),
+                           A.val.get(), T.rowptr.get(), cnt.get(), T.col.get(), T.val.get());
+    if (m > 0)
+        hipLaunchKernelGGL(k_sort_pairs, dim3(g1(m)), dim3(kBlock), 0, s, m, T.rowptr.get(), T.col.get(),
+                           T.val.get());
+    MATAMG_LAUNCH_CHECK();
+}
+
+}  // namespace matamg

@@ -1,0 +1,185 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Bars: drop masks, aggregates, coordinates / tensors and every sparsity
+pattern bitwise on every level; prolongator and coarse-operator values to
+round-off (1e-10 of the row scale); FP64 solution within 1e-6 relative error
+of the oracle's and iteration count within +-1; FP32-hierarchy form reaching
+a true FP64 relative residual <= 1e-8.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads.q1 import (config1_checkerboard_2d, layered_stack_3d, poisson_box, rotated_anisotropic_3d,
+                          two_domain_2d)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def amg():
+    import torch
+
+    import paper_2602_05686_amd as amg
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    amg.load()
+    return amg
+
+
+def banner(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    "checker64": (lambda: config1_checkerboard_2d(), dict(max_coarse=100)),
+    "layered16": (lambda: layered_stack_3d(n=16, repeats=4), dict(max_coarse=100)),
+    "aniso16": (lambda: rotated_anisotropic_3d(n=16, block=8), dict(max_coarse=100)),
+    "twodomain64": (lambda: two_domain_2d(n=64, kappa=1e4), dict(max_coarse=50)),
+    "layered24_tall": (lambda: layered_stack_3d(n=24, repeats=3, stretch=0.1), dict(max_coarse=200)),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request, amg):
+    prob_fn, kw = CASES[request.param]
+    prob = prob_fn()
+    banner(f"{request.param}: n={prob.n} nnz={prob.nnz}")
+    orc = oracle.Hierarchy(prob, **kw)
+    h = amg.Hierarchy.from_problem(prob, **kw)
+    return request.param, prob, orc, h, kw
+
+
+def test_hierarchy_bitwise(case):
+    name, prob, orc, h, kw = case
+    st = h.stats()
+    assert st["levels"] == orc.nlev
+    for l in range(orc.nlev):
+        rp, ci, va = h.level_csr(l, "A")
+        orp, oci, ova = orc.level_csr(l, "A")
+        assert np.array_equal(rp, orp) and np.array_equal(ci, oci), f"{name}: A pattern differs on level {l}"
+        scale = np.max(np.abs(ova))
+        assert np.max(np.abs(va - ova)) <= 1e-10 * scale, f"{name}: A values differ on level {l}"
+        assert np.array_equal(h.level_aux(l, "x"), orc.get(l, "x")), f"{name}: coordinates differ on level {l}"
+        assert np.array_equal(h.level_aux(l, "sig"), orc.get(l, "sig")), f"{name}: tensors differ on level {l}"
+        if l + 1 < orc.nlev:
+            assert np.array_equal(h.soc_mask(l), orc.get(l, "mask")), f"{name}: mask differs on level {l}"
+            assert np.array_equal(h.aggregates(l), orc.get(l, "agg")), f"{name}: aggregates differ on level {l}"
+            assert st["mis_rounds"][l] == orc.info(l)["mis_rounds"]
+            prp, pci, pva = h.level_csr(l, "P")
+            orp, oci, ova = orc.level_csr(l, "P")
+            assert np.array_equal(prp, orp) and np.array_equal(pci, oci), f"{name}: P pattern on level {l}"
+            assert np.max(np.abs(pva - ova)) <= 1e-10, f"{name}: P values on level {l}"
+            rrp, rci, rva = h.level_csr(l, "R")
+            orp, oci, ova = orc.level_csr(l, "R")
+            assert np.array_equal(rrp, orp) and np.array_equal(rci, oci)
+            assert np.max(np.abs(rva - ova)) <= 1e-10, f"{name}: R values on level {l}"
+            assert st["omega"][l] == pytest.approx(orc.info(l)["omega"], rel=1e-10)
+            assert st["lam_cheb"][l] == pytest.approx(orc.info(l)["lam_cheb"], rel=1e-10)
+    if orc.nlev > 1:
+        assert np.array_equal(h.level_aux(0, "dirichlet"), prob.dirichlet)
+        S = h.level_aux(0, "S")
+        assert np.allclose(S, orc.get(0, "S"), rtol=1e-15, atol=0)
+
+
+def test_fp64_solve_matches_oracle(case):
+    name, prob, orc, h, kw = case
+    banner(f"{name}: FP64 PCG")
+    xo, io = orc.pcg(prob.b)
+    x, info = h.solve(prob.b)
+    assert info["status"] == "OK" and info["rel_res"] <= 1e-8
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"{name}: iters gpu={info['iterations']} oracle={io['iterations']} rel_err={err:.3e}")
+    assert err <= 1e-6
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    r = prob.b - oracle.spmv(prob.rowptr, prob.col, prob.val, x)
+    assert np.linalg.norm(r) / np.linalg.norm(prob.b) <= 1e-8
+
+
+def test_vcycle_matches_oracle(case, amg):
+    import torch
+
+    name, prob, orc, h, kw = case
+    banner(f"{name}: V-cycle")
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal(prob.n)
+    zo = orc.vcycle(r)
+    rt = torch.from_numpy(r).cuda()
+    zt = torch.zeros_like(rt)
+    h.vcycle(rt, zt)
+    torch.cuda.synchronize()
+    z = zt.cpu().numpy()
+    assert np.linalg.norm(z - zo) <= 1e-9 * np.linalg.norm(zo)
+
+
+def test_fp32_hierarchy_form(case, amg):
+    name, prob, orc, h, kw = case
+    banner(f"{name}: FP32-hierarchy PCG")
+    h32 = amg.Hierarchy.from_problem(prob, precision="fp32", **kw)
+    xo, io = orc.pcg(prob.b)
+    x, info = h32.solve(prob.b)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"{name}: fp32 iters={info['iterations']} (fp64 oracle {io['iterations']}) rel_err={err:.3e}")
+    assert info["status"] == "OK" and info["rel_res"] <= 1e-8
+    r = prob.b - oracle.spmv(prob.rowptr, prob.col, prob.val, x)
+    assert np.linalg.norm(r) / np.linalg.norm(prob.b) <= 1e-8
+
+
+def test_determinism(amg):
+    prob = rotated_anisotropic_3d(n=12, block=4)
+    banner("determinism: aniso12")
+    h1 = amg.Hierarchy.from_problem(prob, max_coarse=50)
+    h2 = amg.Hierarchy.from_problem(prob, max_coarse=50)
+    for l in range(h1.stats()["levels"]):
+        a1, a2 = h1.level_csr(l, "A"), h2.level_csr(l, "A")
+        assert all(np.array_equal(u, v) for u, v in zip(a1, a2))
+    x1, _ = h1.solve(prob.b)
+    x2, _ = h1.solve(prob.b)
+    x3, _ = h2.solve(prob.b)
+    assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
+
+
+def test_single_level_direct(amg):
+    prob = poisson_box((10, 10), dirichlet="x0")
+    banner("single level")
+    h = amg.Hierarchy.from_problem(prob, max_coarse=1000)
+    assert h.stats()["levels"] == 1
+    x, info = h.solve(prob.b, tol=1e-10)
+    assert info["status"] == "OK" and info["iterations"] == 1
+
+
+def test_error_paths(amg):
+    banner("error paths")
+    prob = poisson_box((6, 6), dirichlet="x0")
+    # unsorted columns
+    col = prob.col.copy()
+    col[[3, 4]] = col[[4, 3]]
+    with pytest.raises(amg.AmgError) as e:
+        amg.Hierarchy(prob.rowptr, col, prob.val, prob.elem_nodes, prob.elem_sigma, prob.coords,
+                      amg.options(dim=2, max_coarse=5))
+    assert e.value.status == "INVALID_ARG"
+    # non-SPD tensors
+    bad = -prob.elem_sigma
+    with pytest.raises(amg.AmgError) as e:
+        amg.Hierarchy(prob.rowptr, prob.col, prob.val, prob.elem_nodes, bad, prob.coords,
+                      amg.options(dim=2, max_coarse=5))
+    assert e.value.status == "NOT_SPD"
+    # level cap above max_coarse
+    with pytest.raises(amg.AmgError) as e:
+        amg.Hierarchy.from_problem(prob, max_coarse=2, max_levels=2)
+    assert e.value.status == "COARSENING_STAGNATED"
+    # bad options
+    with pytest.raises(amg.AmgError) as e:
+        amg.Hierarchy.from_problem(prob, theta=2.0)
+    assert e.value.status == "INVALID_ARG"
+    # not converged within max_iter
+    h = amg.Hierarchy.from_problem(prob, max_coarse=5)
+    x, info = h.solve(prob.b, max_iter=1, tol=1e-14, raise_on_error=False)
+    assert info["status"] == "NOT_CONVERGED"
+    # zero right-hand side
+    x, info = h.solve(np.zeros(prob.n))
+    assert info["status"] == "OK" and np.all(x == 0)
