@@ -104,6 +104,8 @@ static uint64_t stream_key(uint64_t seed, uint64_t purpose, int level)
     return splitmix64(seed + purpose + (uint64_t)level);
 }
 #define PURPOSE_MIS 1ull
+/* 2^-46 = 64 * DBL_EPSILON: relative size of round-off noise in a row sum */
+#define ROW_NOISE 1.4210854715202004e-14
 #define PURPOSE_PF 101ull
 #define PURPOSE_CHEB 201ull
 
@@ -593,7 +595,8 @@ static double power_method(const Csr *a, const double *dscale, int iters, uint64
  * every dropped off-diagonal into the diagonal: (A_F)_ii = A_ii + sum of the
  * dropped A_ik (ascending column).  A Dirichlet row keeps only its diagonal
  * (its off-diagonals are zero by definition).
- * 1-norm diagonal Dt_ii = sum_j |(A_F)_ij|.  omega = omega_sym / lambda with
+ * 1-norm diagonal Dt_ii = sum_j |(A_F)_ij| (zero for an empty filtered row,
+ * see below).  omega = omega_sym / lambda with
  * lambda from the power method on Dt^{-1} A_F.  P = P^ - omega Dt^{-1} A_F P^;
  * the pattern is the symbolic product (zeros kept).
  */
@@ -639,7 +642,13 @@ static int build_prolongator(Level *L, const OrcOptions *opt, int level)
     for (int i = 0; i < n; ++i) {
         double s = 0.0;
         for (int k = F.rowptr[i]; k < F.rowptr[i + 1]; ++k) s += fabs(F.val[k]);
-        dt[i] = s;
+        /* A filtered row that keeps only its diagonal has (A_F)_ii = sum_k A_ik,
+         * which is exactly zero on rows with zero row sum and round-off noise
+         * in floating point.  Such a row is empty: its 1-norm is taken as zero
+         * (no smoothing) when it is below 2^-46 times the row's 1-norm in A. */
+        double rowabs = 0.0;
+        for (int k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) rowabs += fabs(A->val[k]);
+        dt[i] = (s > ROW_NOISE * rowabs) ? s : 0.0;
     }
     {
         double *dtinv = (double *)malloc(sizeof(double) * (size_t)n);

@@ -48,10 +48,12 @@ def test_prolongator_formula(checker):
     AF[np.arange(n), np.arange(n)] = A.diagonal() + (A - np.diag(A.diagonal())).sum(1) - AF.sum(1)
     assert np.allclose(AF.sum(1), A.sum(1), rtol=0, atol=1e-12 * np.abs(A).max())
     Dt = np.abs(AF).sum(1)
+    Dt[Dt <= 2.0**-46 * np.abs(A).sum(1)] = 0.0   # empty filtered rows are not smoothed
+    Dtinv = np.where(Dt > 0, 1.0 / np.where(Dt > 0, Dt, 1.0), 0.0)
     Phat = np.zeros((n, nc))
     Phat[agg >= 0, agg[agg >= 0]] = 1.0
     omega = h.info(0)["omega"]
-    Pref = Phat - omega * (AF / Dt[:, None]) @ Phat
+    Pref = Phat - omega * (AF * Dtinv[:, None]) @ Phat
     P = dense(*h.level_csr(0, "P"), nc)
     assert np.allclose(P, Pref, rtol=0, atol=1e-13)
     # rows of P-hat sum to one on non-Dirichlet rows; Dirichlet rows are empty
@@ -64,6 +66,32 @@ def test_prolongator_formula(checker):
     # 1-norm diagonal: rho(Dt^{-1} A_F) <= 1 (Gershgorin), so the estimate is <= 1
     assert h.info(0)["lam_pf"] <= 1.0 + 1e-12
     assert omega == pytest.approx((4.0 / 3.0) / h.info(0)["lam_pf"], rel=1e-15)
+
+
+def test_empty_filtered_rows_keep_the_tentative_prolongator():
+    """A node whose off-diagonals are all dropped has a filtered row equal to
+    its lumped diagonal, the row sum of A.  On zero-sum rows that is zero in
+    exact arithmetic (round-off in floating point): the row is not smoothed and
+    P's row equals the tentative prolongator's row exactly."""
+    prob = rotated_anisotropic_3d(n=16, block=8)
+    h = oracle.Hierarchy(prob, max_coarse=100)
+    seen = 0
+    for l in range(h.nlev - 1):
+        rp, ci, va = h.level_csr(l, "A")
+        mask = h.get(l, "mask")
+        agg = h.get(l, "agg")
+        prp, pci, pva = h.level_csr(l, "P")
+        for i in range(len(rp) - 1):
+            lo, hi = rp[i], rp[i + 1]
+            off = ci[lo:hi] != i
+            if mask[lo:hi][off].any() or agg[i] < 0:
+                continue
+            if abs(va[lo:hi].sum()) > 2.0**-46 * np.abs(va[lo:hi]).sum():
+                continue
+            seen += 1
+            assert list(pci[prp[i]:prp[i + 1]]) == [agg[i]]
+            assert list(pva[prp[i]:prp[i + 1]]) == [1.0]
+    assert seen > 0
 
 
 def test_galerkin_product_and_spd(aniso):
@@ -80,7 +108,11 @@ def test_galerkin_product_and_spd(aniso):
         assert np.allclose(Ac, Ac.T, rtol=0, atol=1e-12 * np.abs(ref).max())
         assert np.linalg.eigvalsh(0.5 * (Ac + Ac.T)).min() > 0
         # the stored pattern is the symbolic product: every structurally reachable entry
-        sym = ((np.abs(P.T) > 0).astype(int) @ (np.abs(A) > 0).astype(int) @ (np.abs(P) > 0).astype(int)) > 0
+        prp, pci, _ = h.level_csr(l, "P")
+        Ppat = dense(prp, pci, np.ones(len(pci)), inf["nc"]) > 0
+        arp, aci, _ = h.level_csr(l, "A")
+        Apat = dense(arp, aci, np.ones(len(aci)), inf["n"]) > 0
+        sym = (Ppat.T.astype(int) @ Apat.astype(int) @ Ppat.astype(int)) > 0
         stored = dense(h.get(l + 1, "A_rowptr"), h.get(l + 1, "A_col"),
                        np.ones(h.info(l + 1)["nnz"]), inf["nc"]) > 0
         assert np.array_equal(stored, sym)
