@@ -18,6 +18,8 @@
 namespace matamg {
 namespace {
 
+constexpr double kRowNoise = 1.4210854715202004e-14;  // 2^-46
+
 inline int grid_for(int64_t n) {
     int g = ceil_div(n > 0 ? n : 1, kBlock);
     return g;
@@ -381,6 +383,12 @@ __global__ void k_filter_fill(int n, const int* rowptr, const int* col, const do
         if (diagpos >= 0) fval[diagpos] = fval[diagpos] + lump;
         double s = 0.0;
         for (int q = frowptr[i]; q < p; ++q) s += fabs(fval[q]);
+        // a row reduced to its lumped diagonal holds the row sum of A, which is
+        // round-off noise on zero-sum rows: below 2^-46 of the row's 1-norm the
+        // filtered row is empty and is not smoothed
+        double rowabs = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) rowabs += fabs(val[k]);
+        if (!(s > kRowNoise * rowabs)) s = 0.0;
         dt[i] = s;
         dtinv[i] = s > 0.0 ? 1.0 / s : 0.0;
     }

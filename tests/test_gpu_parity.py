@@ -42,6 +42,19 @@ CASES = {
     "twodomain64": (lambda: two_domain_2d(n=64, kappa=1e4), dict(max_coarse=50)),
     "layered24_tall": (lambda: layered_stack_3d(n=24, repeats=3, stretch=0.1), dict(max_coarse=200)),
 }
+# Tall elements with a 1e10 contrast make the coarsest operator ill conditioned
+# (cond ~ 3e11): two stable coarse solvers agree only to ~cond*eps, and two CG
+# runs that both reach 1e-8 differ by up to ~1e-5.  That case is compared at
+# tol 1e-10, where both solutions are accurate to well below 1e-6.
+SOLVE_TOL = {"layered24_tall": 1e-10}
+
+
+def coarse_condition(orc):
+    rp, ci, va = orc.level_csr(orc.nlev - 1, "A")
+    n = len(rp) - 1
+    D = np.zeros((n, n))
+    D[np.repeat(np.arange(n), np.diff(rp)), ci] = va
+    return np.linalg.cond(D)
 
 
 @pytest.fixture(scope="module", params=sorted(CASES))
@@ -89,9 +102,10 @@ def test_hierarchy_bitwise(case):
 def test_fp64_solve_matches_oracle(case):
     name, prob, orc, h, kw = case
     banner(f"{name}: FP64 PCG")
-    xo, io = orc.pcg(prob.b)
-    x, info = h.solve(prob.b)
-    assert info["status"] == "OK" and info["rel_res"] <= 1e-8
+    tol = SOLVE_TOL.get(name, 1e-8)
+    xo, io = orc.pcg(prob.b, tol=tol)
+    x, info = h.solve(prob.b, tol=tol)
+    assert info["status"] == "OK" and info["rel_res"] <= tol
     err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
     print(f"{name}: iters gpu={info['iterations']} oracle={io['iterations']} rel_err={err:.3e}")
     assert err <= 1e-6
@@ -113,7 +127,9 @@ def test_vcycle_matches_oracle(case, amg):
     h.vcycle(rt, zt)
     torch.cuda.synchronize()
     z = zt.cpu().numpy()
-    assert np.linalg.norm(z - zo) <= 1e-9 * np.linalg.norm(zo)
+    # the coarse solve's forward error bounds the agreement: ~cond(A_L) * eps
+    bound = max(1e-9, 10 * np.finfo(float).eps * coarse_condition(orc))
+    assert np.linalg.norm(z - zo) <= bound * np.linalg.norm(zo)
 
 
 def test_fp32_hierarchy_form(case, amg):
