@@ -33,28 +33,12 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;
 }
 
-// Store this block's partial; the last block to arrive sums all partials in
-// index order (fixed tree for a fixed grid) and writes *result.
-__device__ __forceinline__ void finalize_sum(double block_total, const DotTarget& dt, double* sh) {
-    __shared__ int s_last;
-    if (threadIdx.x == 0) {
-        dt.partial[blockIdx.x] = block_total;
-        __threadfence();
-        unsigned t = atomicAdd(dt.counter, 1u);
-        s_last = (t == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        double v = 0.0;
-        for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x)
-            v += __hip_atomic_load(dt.partial + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        v = block_sum(v, sh);
-        if (threadIdx.x == 0) {
-            *dt.result = v;
-            __hip_atomic_store(dt.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+// Store this block's partial sum (valid on thread 0).  A second, one-block
+// kernel (finish_sum) adds the partials in index order; the kernel boundary
+// makes them visible without device-scope fences, and the order is fixed
+// for a fixed grid.
+__device__ __forceinline__ void store_partial(double block_total, const DotTarget& dt) {
+    if (threadIdx.x == 0) dt.partial[blockIdx.x] = block_total;
 }
 
 }  // namespace matamg

@@ -117,15 +117,30 @@ __global__ __launch_bounds__(kBlock) void k_dot(const T* a, const T* b, int64_t 
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
         v += (double)a[i] * (double)b[i];
     double t = block_sum(v, sh);
-    finalize_sum(t, dt, sh);
+    store_partial(t, dt);
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish_sum(int nb, const double* partial, double* result) {
+    __shared__ double sh[kBlock / 64];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kBlock) v += partial[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) *result = v;
 }
 }  // namespace
+
+void finish_sum(const DotTarget& dt, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(kBlock), 0, s, nblocks, (const double*)dt.partial, dt.result);
+    MATAMG_LAUNCH_CHECK();
+}
 
 template <typename T>
 void dot(const T* a, const T* b, int64_t n, double* partial, unsigned* counter, double* result, hipStream_t s) {
     DotTarget dt{partial, counter, result};
-    hipLaunchKernelGGL(k_dot<T>, dim3(vec_grid(n)), dim3(kBlock), 0, s, a, b, n, dt);
+    const int g = vec_grid(n);
+    hipLaunchKernelGGL(k_dot<T>, dim3(g), dim3(kBlock), 0, s, a, b, n, dt);
     MATAMG_LAUNCH_CHECK();
+    finish_sum(dt, g, s);
 }
 template void dot<double>(const double*, const double*, int64_t, double*, unsigned*, double*, hipStream_t);
 template void dot<float>(const float*, const float*, int64_t, double*, unsigned*, double*, hipStream_t);
@@ -210,19 +225,46 @@ __device__ __forceinline__ double epilogue(const SArgs<T>& a, int r, T s) {
     return dp;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup g runs
+// on XCD g % 8).  Remapping so that each XCD walks one contiguous eighth of
+// the row blocks keeps the gathered neighbours of consecutive blocks in that
+// XCD's L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int nblk) {
+    const int per = (nblk + kXcds - 1) / kXcds;
+    return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+}
+inline int xcd_grid(int nblk) { return ((nblk + kXcds - 1) / kXcds) * kXcds; }
+
+constexpr int kPerThread = kStreamCap / kBlock;
+
 template <typename T, int MODE, bool HAS_DOT>
-__global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a) {
+__global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a, int nblk) {
     __shared__ T prod[kStreamCap];
     __shared__ double sh[kBlock / 64];
     __shared__ T shr[kBlock / 64];
-    const int r0 = a.blk[blockIdx.x], r1 = a.blk[blockIdx.x + 1];
+    const int bid = xcd_block(nblk);
+    if (bid >= nblk) return;
+    const int r0 = a.blk[bid], r1 = a.blk[bid + 1];
     const int k0 = a.rowptr[r0], k1 = a.rowptr[r1];
     const int cnt = k1 - k0;
     double dp = 0.0;
     if (cnt <= kStreamCap) {
-        for (int t = threadIdx.x; t < cnt; t += kBlock) {
-            const int k = k0 + t;
-            prod[t] = a.val[k] * a.x[a.col[k]];
+        // issue every load of this thread's share before using any of them
+        int c[kPerThread];
+        T v[kPerThread];
+#pragma unroll
+        for (int u = 0; u < kPerThread; ++u) {
+            const int t = (int)threadIdx.x + u * kBlock;
+            if (t < cnt) {
+                c[u] = __builtin_nontemporal_load(a.col + k0 + t);
+                v[u] = __builtin_nontemporal_load(a.val + k0 + t);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPerThread; ++u) {
+            const int t = (int)threadIdx.x + u * kBlock;
+            if (t < cnt) prod[t] = v[u] * a.x[c[u]];
         }
         __syncthreads();
         const int r = r0 + (int)threadIdx.x;
@@ -251,15 +293,16 @@ __global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a) {
     }
     if constexpr (HAS_DOT) {
         double t = block_sum(dp, sh);
-        finalize_sum(t, a.dt, sh);
+        if (threadIdx.x == 0) a.dt.partial[bid] = t;
     }
 }
 
 template <typename T, int MODE, bool HAS_DOT>
 void launch_stream(const DCsr& A, const SArgs<T>& a, hipStream_t s) {
     if (A.nblk <= 0) return;
-    hipLaunchKernelGGL((k_stream<T, MODE, HAS_DOT>), dim3(A.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_stream<T, MODE, HAS_DOT>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a, A.nblk);
     MATAMG_LAUNCH_CHECK();
+    if constexpr (HAS_DOT) finish_sum(a.dt, A.nblk, s);
 }
 
 template <typename T>
@@ -391,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, double* x, doub
         v += ri * ri;
     }
     double t = block_sum(v, sh);
-    finalize_sum(t, dt, sh);
+    store_partial(t, dt);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_direction(int64_t n, double* p, const double* z,
@@ -442,8 +485,10 @@ void scale_by_inv_norm(int64_t n, const double* nrm2, const double* in, double* 
 
 void cg_update(int64_t n, double* x, double* r, const double* p, const double* q, const double* rz,
                const double* pq, DotTarget rr, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, x, r, p, q, rz, pq, rr);
+    const int g = vec_grid(n);
+    hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, n, x, r, p, q, rz, pq, rr);
     MATAMG_LAUNCH_CHECK();
+    finish_sum(rr, g, s);
 }
 
 void cg_direction(int64_t n, double* p, const double* z, const double* rz_new, const double* rz_old,

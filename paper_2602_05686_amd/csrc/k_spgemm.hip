@@ -98,20 +98,30 @@ __device__ __forceinline__ int ld_key(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// memory ordering between the phases of one wavefront's row: release and
-// acquire at agent scope also invalidate the vector L1, so values written
-// through L2 (atomics) are re-read from L2
+// Memory ordering between the phases of one wavefront's row.  The LDS path
+// only needs its LDS operations completed and not reordered (workgroup
+// scope).  The global-memory path (rare, long rows) uses an agent-scope fence
+// so values written through L2 by atomics are re-read from L2.
+template <bool GLOBAL>
 __device__ __forceinline__ void phase_fence() {
     __builtin_amdgcn_wave_barrier();
-    __threadfence();
+    if constexpr (GLOBAL) __threadfence();
+    else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
 }
 
+template <bool GLOBAL>
+__device__ __forceinline__ int key_at(const int* keys, unsigned h) {
+    if constexpr (GLOBAL) return ld_key(keys + h);
+    else return keys[h];
+}
+
 // slot of a key known to be present; the probe count is bounded by the table size
+template <bool GLOBAL>
 __device__ __forceinline__ unsigned hash_find_fresh(const int* keys, unsigned mask, int key) {
     unsigned h = hash_slot(key, mask);
     for (unsigned probe = 0; probe <= mask; ++probe) {
-        if (ld_key(keys + h) == key) return h;
+        if (key_at<GLOBAL>(keys, h) == key) return h;
         h = (h + 1) & mask;
     }
     return 0;
@@ -137,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int
         mask = kHS - 1;
     }
     for (unsigned h = lane; h <= mask; h += 64) keys[h] = -1;
-    phase_fence();
+    phase_fence<GLOBAL>();
     int added = 0;
     int full = 0;
     for_each_product<false>(arp, acol, nullptr, brp, bcol, nullptr, i,
@@ -191,12 +201,12 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
         keys[h] = -1;
         vals[h] = 0;
     }
-    phase_fence();
+    phase_fence<GLOBAL>();
     for_each_product<false>(arp, acol, nullptr, brp, bcol, nullptr, i,
                             [&](bool valid, int c, double, int, int) {
                                 if (valid) (void)hash_insert(keys, mask, c);
                             });
-    phase_fence();
+    phase_fence<GLOBAL>();
     // compact the occupied slots into the output column range (arbitrary order)
     const int base = crp[i];
     const int d = crp[i + 1] - base;
@@ -204,33 +214,33 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
     int filled = 0;
     for (unsigned h0 = 0; h0 <= mask; h0 += 64) {
         const unsigned h = h0 + lane;
-        const int key = (h <= mask) ? ld_key(keys + h) : -1;
+        const int key = (h <= mask) ? key_at<GLOBAL>(keys, h) : -1;
         const bool occ = key >= 0;
         const uint64_t bal = __ballot(occ);
         const int before = __popcll(bal & ((1ull << lane) - 1ull));
         if (occ && filled + before < d) cl[filled + before] = key;
         filled += __popcll(bal);
     }
-    phase_fence();
+    phase_fence<GLOBAL>();
     // rank of each column among the row's columns = its output position
     for (int e = lane; e < d; e += 64) {
         const int c = cl[e];
         int r = 0;
         for (int q = 0; q < d; ++q) r += (cl[q] < c);
-        vals[hash_find_fresh(keys, mask, c)] = r;
+        vals[hash_find_fresh<GLOBAL>(keys, mask, c)] = r;
     }
-    phase_fence();
+    phase_fence<GLOBAL>();
     for (unsigned h = lane; h <= mask; h += 64) {
-        const int key = ld_key(keys + h);
+        const int key = key_at<GLOBAL>(keys, h);
         const int r = vals[h];
         if (key >= 0 && r >= 0 && r < d) cl[r] = key;
     }
     for (int e = lane; e < d; e += 64) acc[e] = 0.0;
-    phase_fence();
+    phase_fence<GLOBAL>();
     // accumulate in canonical product order; one lane performs every addition
     for_each_product<true>(arp, acol, aval, brp, bcol, bval, i,
                            [&](bool valid, int c, double pv, int t0, int total) {
-                               int r = valid ? vals[hash_find_fresh(keys, mask, c)] : 0;
+                               int r = valid ? vals[hash_find_fresh<GLOBAL>(keys, mask, c)] : 0;
                                r = (r >= 0 && r < d) ? r : 0;
                                const int m = min(64, total - t0);
                                for (int q = 0; q < m; ++q) {
@@ -239,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
                                    if (lane == 0) acc[rq] += vq;
                                }
                            });
-    phase_fence();
+    phase_fence<GLOBAL>();
     for (int e = lane; e < d; e += 64) cval[base + e] = acc[e];
 }
 

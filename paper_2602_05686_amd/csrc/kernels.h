@@ -21,12 +21,14 @@ void dot(const T* a, const T* b, int64_t n, double* partial, unsigned* counter, 
 // row blocks for the streaming CSR kernels, computed from a host row pointer
 std::vector<int> stream_blocks(const int* rowptr_host, int n);
 
-// dot-fusion target: partial sums and a counter for the last-block finalisation
+// dot-fusion target: per-block partial sums, reduced by finish_sum into *result
 struct DotTarget {
     double* partial = nullptr;
     unsigned* counter = nullptr;
     double* result = nullptr;
 };
+// *dt.result = sum of dt.partial[0..nblocks) in index order (one block)
+void finish_sum(const DotTarget& dt, int nblocks, hipStream_t s);
 
 // y = A x
 template <typename T>
