@@ -112,6 +112,7 @@ struct DCsr {
 constexpr int kBlock = 256;          // threads per block in streaming kernels
 constexpr int kStreamCap = 2048;     // nnz staged in LDS per streaming block
 constexpr int kMaxRowsPerBlock = kBlock;
+constexpr int kLongRow = 96;         // rows longer than this are reduced by a whole block
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 

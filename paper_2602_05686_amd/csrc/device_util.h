@@ -7,6 +7,17 @@
 
 namespace matamg {
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup g runs on
+// XCD g % 8).  Remapping so that each XCD walks one contiguous eighth of the
+// row blocks keeps the gathered neighbours of consecutive blocks in that
+// XCD's L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int nblk) {
+    const int per = (nblk + kXcds - 1) / kXcds;
+    return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+}
+inline int xcd_grid(int nblk) { return ((nblk + kXcds - 1) / kXcds) * kXcds; }
+
 __device__ __forceinline__ double wave_sum(double v) {
     // lane 0 ends with the sum; the combination tree depends only on lane ids
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);

@@ -212,12 +212,10 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
             if (read_flag(flag.get(), s)) fail(AMG_ERR_NOT_SPD, "nodal tensor not SPD on level " + std::to_string(l));
         }
         DBuf<double> lval((size_t)(nzl > 0 ? nzl : 1), mc), ldiag(nl, mc);
-        soc_values(nl, L.A.rowptr.get(), L.A.col.get(), L.A.val.get(), dim, L.x.get(), minv.get(), L.dir.get(),
-                   opt.soc, lval.get(), ldiag.get(), s);
+        soc_values(L.A, dim, L.x.get(), minv.get(), L.dir.get(), opt.soc, lval.get(), ldiag.get(), s);
         L.S.alloc((size_t)(nzl > 0 ? nzl : 1), mc);
         L.mask.alloc((size_t)(nzl > 0 ? nzl : 1), mc);
-        soc_mask(nl, L.A.rowptr.get(), L.A.col.get(), L.dir.get(), lval.get(), ldiag.get(), opt.theta, L.S.get(),
-                 L.mask.get(), s);
+        soc_mask(L.A, L.dir.get(), lval.get(), ldiag.get(), opt.theta, L.S.get(), L.mask.get(), s);
         lval.release();
         ldiag.release();
         minv.release();
@@ -231,8 +229,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
             mis_init(nl, L.dir.get(), state.get(), s);
             int rounds = 0;
             for (;;) {
-                mis_round(nl, L.A.rowptr.get(), L.A.col.get(), L.mask.get(), key, state.get(), t1.get(), t2.get(),
-                          und.get(), s);
+                mis_round(L.A, L.mask.get(), key, state.get(), t1.get(), t2.get(), und.get(), s);
                 ++rounds;
                 if (read_flag(und.get(), s) == 0) break;
                 if (rounds > nl + 1) fail(AMG_ERR_HIP, "distance-2 MIS did not terminate");
@@ -260,7 +257,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
             DCsr F;
             F.n = F.m = nl;
             DBuf<int> cnt(nl, mc), tmp(scan_tmp_size(nl), mc);
-            filter_count(nl, L.A.rowptr.get(), L.A.col.get(), L.mask.get(), cnt.get(), s);
+            filter_count(L.A, L.mask.get(), cnt.get(), s);
             F.rowptr.alloc((size_t)nl + 1, mc);
             exclusive_scan(cnt.get(), F.rowptr.get(), nl, tmp.get(), s);
             int fnnz = 0;
@@ -269,8 +266,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
             F.col.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
             F.val.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
             DBuf<double> dt(nl, mc), dtinv(nl, mc);
-            filter_fill(nl, L.A.rowptr.get(), L.A.col.get(), L.A.val.get(), L.mask.get(), F.rowptr.get(),
-                        F.col.get(), F.val.get(), dt.get(), dtinv.get(), s);
+            filter_fill(L.A, L.mask.get(), F.rowptr.get(), F.col.get(), F.val.get(), dt.get(), dtinv.get(), s);
             make_blocks(F, mc, s);
             ensure_partial(h, std::max(F.nblk, L.A.nblk));
             L.lam_pf = power_method(F, dtinv.get(), opt.power_iters, stream_key(opt.seed, kPurposePf, l), h, s);

@@ -156,6 +156,36 @@ __global__ void k_tensor_inverse(int n, int dim, const double* sig, double* minv
     }
 }
 
+
+// ------------------------------------------------------- streamed row blocks
+// The kernels below walk the same row blocks as the streaming SpMV: a block
+// stages its contiguous range of stored entries through LDS with coalesced
+// loads, works per entry in parallel, and finishes per row with one thread
+// per row in ascending stored order.  A long row has a block of its own.
+struct RowBlock {
+    int r0, r1, k0, k1, cnt;
+    bool longrow;
+};
+
+__device__ __forceinline__ RowBlock row_block(const int* rowptr, const int* blk, int bid) {
+    RowBlock rb;
+    rb.r0 = blk[bid];
+    rb.r1 = blk[bid + 1];
+    rb.k0 = rowptr[rb.r0];
+    rb.k1 = rowptr[rb.r1];
+    rb.cnt = rb.k1 - rb.k0;
+    rb.longrow = (rb.r1 - rb.r0 == 1) && rb.cnt > kLongRow;
+    return rb;
+}
+
+// rowof[t] = row of stored entry k0 + t, for a block of short rows
+__device__ __forceinline__ void fill_row_ids(const int* rowptr, const RowBlock& rb, int* rowof) {
+    const int r = rb.r0 + (int)threadIdx.x;
+    if (r < rb.r1)
+        for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) rowof[k - rb.k0] = r;
+    __syncthreads();
+}
+
 __device__ __forceinline__ double quad_form(int dim, const double* m, const double* d) {
     if (dim == 1) return d[0] * (m[0] * d[0]);
     if (dim == 2) {
@@ -169,74 +199,135 @@ __device__ __forceinline__ double quad_form(int dim, const double* m, const doub
     return (d[0] * t0 + d[1] * t1) + d[2] * t2;
 }
 
-// |L_ij| = 1 / max(q_i, q_j), L_ii summed in ascending column order
-__global__ void k_soc_values(int n, const int* rowptr, const int* col, const double* val, int dim,
-                             const double* x, const double* minv, const uint8_t* dir, int soc, double* lval,
-                             double* ldiag) {
-    const int nc = dim * (dim + 1) / 2;
-    const double ident[3][6] = {{1, 0, 0, 0, 0, 0}, {1, 0, 1, 0, 0, 0}, {1, 0, 0, 1, 0, 1}};
-    ROW_LOOP(i, n) {
-        double li = 0.0;
-        double adiag = 0.0;
-        const bool di = dir && dir[i];
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            const int j = col[k];
-            double l = 0.0;
-            if (j == i) {
-                adiag = fabs(val[k]);
-            } else if (!(di || (dir && dir[j]))) {
-                if (soc == AMG_SOC_SA) {
-                    l = fabs(val[k]);
-                } else {
-                    double d[3];
-                    for (int a = 0; a < dim; ++a) d[a] = x[(size_t)j * dim + a] - x[(size_t)i * dim + a];
-                    const double* mi = soc == AMG_SOC_MATERIAL ? minv + (size_t)i * nc : ident[dim - 1];
-                    const double* mj = soc == AMG_SOC_MATERIAL ? minv + (size_t)j * nc : ident[dim - 1];
-                    double qi = quad_form(dim, mi, d);
-                    double qj = quad_form(dim, mj, d);
-                    double q = qi > qj ? qi : qj;
-                    if (!(q > 0.0) || !isfinite(q)) {
-                        l = -1.0;   // coincident points: strong, not in L_ii
-                    } else {
-                        l = 1.0 / q;
-                        li += l;
-                    }
-                }
-            }
-            lval[k] = l;
+struct SocArgs {
+    const int* rowptr;
+    const int* col;
+    const double* val;
+    const int* blk;
+    int nblk, dim, soc;
+    const double* x;
+    const double* minv;
+    const uint8_t* dir;
+    double* lval;
+    double* ldiag;
+};
+
+// |L_ij| = 1 / max(q_i, q_j) for a stored off-diagonal between non-Dirichlet
+// nodes (q = d^T sigma^{-1} d from either end); 0 on the diagonal and on
+// Dirichlet edges; -1 for coincident points; |A_ij| for the classical measure
+__device__ __forceinline__ double edge_l(const SocArgs& a, int i, int k) {
+    const int j = a.col[k];
+    if (j == i) return 0.0;
+    if (a.dir && (a.dir[i] || a.dir[j])) return 0.0;
+    if (a.soc == AMG_SOC_SA) return fabs(a.val[k]);
+    const int dim = a.dim, nc = dim * (dim + 1) / 2;
+    double d[3];
+    for (int c = 0; c < dim; ++c) d[c] = a.x[(size_t)j * dim + c] - a.x[(size_t)i * dim + c];
+    double qi, qj;
+    if (a.soc == AMG_SOC_MATERIAL) {
+        qi = quad_form(dim, a.minv + (size_t)i * nc, d);
+        qj = quad_form(dim, a.minv + (size_t)j * nc, d);
+    } else {
+        const double id[6] = {1.0, 0.0, dim == 2 ? 1.0 : 0.0, 1.0, 0.0, 1.0};
+        const double id2[3] = {1.0, 0.0, 1.0};
+        const double* m = dim == 3 ? id : (dim == 2 ? id2 : id);
+        qi = quad_form(dim, m, d);
+        qj = qi;
+    }
+    const double q = qi > qj ? qi : qj;
+    if (!(q > 0.0) || !isfinite(q)) return -1.0;
+    return 1.0 / q;
+}
+
+// the row's L_ii: ascending sum of the positive |L_ij| (or |A_ii| for the classical measure)
+__device__ __forceinline__ double row_diag(const SocArgs& a, int i, const double* l, int base) {
+    const int lo = a.rowptr[i], hi = a.rowptr[i + 1];
+    if (a.soc == AMG_SOC_SA) {
+        double ad = 0.0;
+        for (int k = lo; k < hi; ++k)
+            if (a.col[k] == i) ad = fabs(a.val[k]);
+        return ad;
+    }
+    double li = 0.0;
+    for (int k = lo; k < hi; ++k) {
+        const double v = l[k - base];
+        if (v > 0.0) li += v;
+    }
+    return li;
+}
+
+__global__ __launch_bounds__(kBlock) void k_soc_values(SocArgs a) {
+    __shared__ double lv[kStreamCap];
+    __shared__ int rowof[kStreamCap];
+    const int bid = xcd_block(a.nblk);
+    if (bid >= a.nblk) return;
+    const RowBlock rb = row_block(a.rowptr, a.blk, bid);
+    if (!rb.longrow) {
+        fill_row_ids(a.rowptr, rb, rowof);
+        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) {
+            const double l = edge_l(a, rowof[t], rb.k0 + t);
+            a.lval[rb.k0 + t] = l;
+            lv[t] = l;
         }
-        ldiag[i] = (soc == AMG_SOC_SA) ? adiag : li;
+        __syncthreads();
+        const int r = rb.r0 + (int)threadIdx.x;
+        if (r < rb.r1) a.ldiag[r] = row_diag(a, r, lv, rb.k0);
+    } else {
+        const int i = rb.r0;
+        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) a.lval[rb.k0 + t] = edge_l(a, i, rb.k0 + t);
+        __threadfence_block();
+        __syncthreads();
+        if (threadIdx.x == 0) a.ldiag[i] = row_diag(a, i, a.lval, 0);
     }
 }
 
+struct MaskArgs {
+    const int* rowptr;
+    const int* col;
+    const int* blk;
+    int nblk;
+    const uint8_t* dir;
+    const double* lval;
+    const double* ldiag;
+    double th2;
+    double* S;
+    uint8_t* mask;
+};
+
 // S_ij = l / sqrt(L_ii L_jj); keep iff l*l >= (theta*theta) * (L_ii * L_jj)
-__global__ void k_soc_mask(int n, const int* rowptr, const int* col, const uint8_t* dir, const double* lval,
-                           const double* ldiag, double th2, double* S, uint8_t* mask) {
-    ROW_LOOP(i, n) {
-        const bool di = dir && dir[i];
-        const double lii = ldiag[i];
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            const int j = col[k];
-            double sv;
-            uint8_t m;
-            if (j == i) {
-                sv = 1.0;
-                m = 1;
-            } else if (di || (dir && dir[j])) {
-                sv = 0.0;
-                m = 0;
-            } else if (lval[k] < 0.0) {
-                sv = 1.0;
-                m = 1;
-            } else {
-                const double l = lval[k];
-                const double prod = lii * ldiag[j];
-                sv = (prod > 0.0) ? l / sqrt(prod) : 1.0;
-                m = (l * l >= th2 * prod) ? 1 : 0;
-            }
-            if (S) S[k] = sv;
-            mask[k] = m;
-        }
+__device__ __forceinline__ void mask_entry(const MaskArgs& a, int i, int k) {
+    const int j = a.col[k];
+    double sv;
+    uint8_t m;
+    if (j == i) {
+        sv = 1.0;
+        m = 1;
+    } else if (a.dir && (a.dir[i] || a.dir[j])) {
+        sv = 0.0;
+        m = 0;
+    } else if (a.lval[k] < 0.0) {
+        sv = 1.0;
+        m = 1;
+    } else {
+        const double l = a.lval[k];
+        const double prod = a.ldiag[i] * a.ldiag[j];
+        sv = (prod > 0.0) ? l / sqrt(prod) : 1.0;
+        m = (l * l >= a.th2 * prod) ? 1 : 0;
+    }
+    if (a.S) a.S[k] = sv;
+    a.mask[k] = m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_soc_mask(MaskArgs a) {
+    __shared__ int rowof[kStreamCap];
+    const int bid = xcd_block(a.nblk);
+    if (bid >= a.nblk) return;
+    const RowBlock rb = row_block(a.rowptr, a.blk, bid);
+    if (!rb.longrow) {
+        fill_row_ids(a.rowptr, rb, rowof);
+        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) mask_entry(a, rowof[t], rb.k0 + t);
+    } else {
+        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) mask_entry(a, rb.r0, rb.k0 + t);
     }
 }
 
@@ -250,32 +341,53 @@ __global__ void k_mis_init(int n, const uint8_t* dir, uint8_t* state) {
     ROW_LOOP(i, n) state[i] = (dir && dir[i]) ? MIS_OUT : MIS_UND;
 }
 
-// T1(i) = max over i and its kept neighbours of T0
-__global__ void k_mis_hop0(int n, const int* rowptr, const int* col, const uint8_t* mask, uint64_t key,
-                           const uint8_t* state, uint64_t* t1) {
-    ROW_LOOP(i, n) {
-        uint64_t best = tuple_of(state[i], key, (int)i);
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            const int j = col[k];
-            if (j == i || !mask[k]) continue;
-            uint64_t t = tuple_of(state[j], key, j);
-            best = t > best ? t : best;
+// T_out(i) = max over i and its kept neighbours of T_in, where T_in is the
+// packed tuple of the node state (FIRST) or the previous hop's result
+template <bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_mis_hop(const int* rowptr, const int* col, const uint8_t* mask,
+                                                    const int* blk, int nblk, uint64_t key, const uint8_t* state,
+                                                    const uint64_t* tin, uint64_t* tout) {
+    __shared__ uint64_t tv[kStreamCap];
+    __shared__ uint64_t tred[kBlock / 64];
+    const int bid = xcd_block(nblk);
+    if (bid >= nblk) return;
+    const RowBlock rb = row_block(rowptr, blk, bid);
+    auto tuple_at = [&](int j) -> uint64_t { return FIRST ? tuple_of(state[j], key, j) : tin[j]; };
+    if (!rb.longrow) {
+        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) {
+            const int k = rb.k0 + t;
+            tv[t] = mask[k] ? tuple_at(col[k]) : 0ull;   // the diagonal's own tuple is harmless
         }
-        t1[i] = best;
-    }
-}
-
-__global__ void k_mis_hop1(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint64_t* t1,
-                           uint64_t* t2) {
-    ROW_LOOP(i, n) {
-        uint64_t best = t1[i];
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            const int j = col[k];
-            if (j == i || !mask[k]) continue;
-            uint64_t t = t1[j];
-            best = t > best ? t : best;
+        __syncthreads();
+        const int r = rb.r0 + (int)threadIdx.x;
+        if (r < rb.r1) {
+            uint64_t best = tuple_at(r);
+            for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+                const uint64_t v = tv[k - rb.k0];
+                best = v > best ? v : best;
+            }
+            tout[r] = best;
         }
-        t2[i] = best;
+    } else {
+        uint64_t best = 0ull;
+        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) {
+            const int k = rb.k0 + t;
+            if (mask[k]) {
+                const uint64_t v = tuple_at(col[k]);
+                best = v > best ? v : best;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t o = __shfl_down(best, off, 64);
+            best = o > best ? o : best;
+        }
+        if ((threadIdx.x & 63) == 0) tred[threadIdx.x >> 6] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t b = tuple_at(rb.r0);
+            for (int w = 0; w < kBlock / 64; ++w) b = tred[w] > b ? tred[w] : b;
+            tout[rb.r0] = b;
+        }
     }
 }
 
@@ -354,43 +466,92 @@ __global__ void k_agg_phase3(int n, const int* rowptr, const int* col, const uin
 }
 
 // ------------------------------------------------------------- prolongator
-__global__ void k_filter_count(int n, const int* rowptr, const int* col, const uint8_t* mask, int* cnt) {
-    ROW_LOOP(i, n) {
+// ------------------------------------------------------------- prolongator
+__global__ __launch_bounds__(kBlock) void k_filter_count(const int* rowptr, const int* col, const uint8_t* mask,
+                                                         const int* blk, int nblk, int* cnt) {
+    __shared__ int cs[kStreamCap];
+    __shared__ uint8_t ms[kStreamCap];
+    __shared__ int red[kBlock / 64];
+    const int bid = xcd_block(nblk);
+    if (bid >= nblk) return;
+    const RowBlock rb = row_block(rowptr, blk, bid);
+    if (!rb.longrow) {
+        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) {
+            cs[t] = col[rb.k0 + t];
+            ms[t] = mask[rb.k0 + t];
+        }
+        __syncthreads();
+        const int r = rb.r0 + (int)threadIdx.x;
+        if (r < rb.r1) {
+            int c = 0;
+            for (int k = rowptr[r] - rb.k0; k < rowptr[r + 1] - rb.k0; ++k) c += (cs[k] == r || ms[k]) ? 1 : 0;
+            cnt[r] = c;
+        }
+    } else {
         int c = 0;
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
-            if (col[k] == i || mask[k]) c++;
-        cnt[i] = c;
+        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) {
+            const int k = rb.k0 + t;
+            c += (col[k] == rb.r0 || mask[k]) ? 1 : 0;
+        }
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) cnt[rb.r0] = red[0] + red[1] + red[2] + red[3];
     }
 }
 
-__global__ void k_filter_fill(int n, const int* rowptr, const int* col, const double* val, const uint8_t* mask,
-                              const int* frowptr, int* fcol, double* fval, double* dt, double* dtinv) {
-    ROW_LOOP(i, n) {
-        int p = frowptr[i];
-        int diagpos = -1;
-        double lump = 0.0;
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            const int j = col[k];
-            if (j == i || mask[k]) {
-                if (j == i) diagpos = p;
-                fcol[p] = j;
-                fval[p] = val[k];
-                p++;
-            } else {
-                lump += val[k];
-            }
+// filtered row (kept entries in order, lumped diagonal), its 1-norm, and the
+// empty-row rule: a row reduced to its lumped diagonal holds the row sum of
+// A, which is round-off noise on zero-sum rows; below 2^-46 of the row's
+// 1-norm the filtered row is empty and is not smoothed
+__device__ __forceinline__ void filter_row(int i, const int* cs, const double* vs, const uint8_t* ms, int lo, int hi,
+                                           int p, int* fcol, double* fval, double* dt, double* dtinv) {
+    const int p0 = p;
+    int diagpos = -1;
+    double lump = 0.0, rowabs = 0.0;
+    for (int k = lo; k < hi; ++k) {
+        const int j = cs[k];
+        const double v = vs[k];
+        rowabs += fabs(v);
+        if (j == i || ms[k]) {
+            if (j == i) diagpos = p;
+            fcol[p] = j;
+            fval[p] = v;
+            p++;
+        } else {
+            lump += v;
         }
-        if (diagpos >= 0) fval[diagpos] = fval[diagpos] + lump;
-        double s = 0.0;
-        for (int q = frowptr[i]; q < p; ++q) s += fabs(fval[q]);
-        // a row reduced to its lumped diagonal holds the row sum of A, which is
-        // round-off noise on zero-sum rows: below 2^-46 of the row's 1-norm the
-        // filtered row is empty and is not smoothed
-        double rowabs = 0.0;
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) rowabs += fabs(val[k]);
-        if (!(s > kRowNoise * rowabs)) s = 0.0;
-        dt[i] = s;
-        dtinv[i] = s > 0.0 ? 1.0 / s : 0.0;
+    }
+    if (diagpos >= 0) fval[diagpos] = fval[diagpos] + lump;
+    double s = 0.0;
+    for (int q = p0; q < p; ++q) s += fabs(fval[q]);
+    if (!(s > kRowNoise * rowabs)) s = 0.0;
+    dt[i] = s;
+    dtinv[i] = s > 0.0 ? 1.0 / s : 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_filter_fill(const int* rowptr, const int* col, const double* val,
+                                                        const uint8_t* mask, const int* blk, int nblk,
+                                                        const int* frowptr, int* fcol, double* fval, double* dt,
+                                                        double* dtinv) {
+    __shared__ int cs[kStreamCap];
+    __shared__ double vs[kStreamCap];
+    __shared__ uint8_t ms[kStreamCap];
+    const int bid = xcd_block(nblk);
+    if (bid >= nblk) return;
+    const RowBlock rb = row_block(rowptr, blk, bid);
+    if (!rb.longrow) {
+        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) {
+            cs[t] = col[rb.k0 + t];
+            vs[t] = val[rb.k0 + t];
+            ms[t] = mask[rb.k0 + t];
+        }
+        __syncthreads();
+        const int r = rb.r0 + (int)threadIdx.x;
+        if (r < rb.r1)
+            filter_row(r, cs, vs, ms, rowptr[r] - rb.k0, rowptr[r + 1] - rb.k0, frowptr[r], fcol, fval, dt, dtinv);
+    } else if (threadIdx.x == 0) {
+        filter_row(rb.r0, col + rb.k0, val + rb.k0, mask + rb.k0, 0, rb.cnt, frowptr[rb.r0], fcol, fval, dt, dtinv);
     }
 }
 
@@ -523,24 +684,37 @@ void tensor_inverse(int n, int dim, const double* sig, double* minv, int* flag, 
     LAUNCH(k_tensor_inverse, n, n, dim, sig, minv, flag);
 }
 
-void soc_values(int n, const int* rowptr, const int* col, const double* val, int dim, const double* x,
-                const double* minv, const uint8_t* dir, int soc, double* lval, double* ldiag, hipStream_t s) {
-    LAUNCH(k_soc_values, n, n, rowptr, col, val, dim, x, minv, dir, soc, lval, ldiag);
+void soc_values(const DCsr& A, int dim, const double* x, const double* minv, const uint8_t* dir, int soc,
+                double* lval, double* ldiag, hipStream_t s) {
+    if (A.nblk <= 0) return;
+    SocArgs a{A.rowptr.get(), A.col.get(), A.val.get(), A.blk.get(), A.nblk, dim, soc, x, minv, dir, lval, ldiag};
+    hipLaunchKernelGGL(k_soc_values, dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a);
+    MATAMG_LAUNCH_CHECK();
 }
 
-void soc_mask(int n, const int* rowptr, const int* col, const uint8_t* dir, const double* lval,
-              const double* ldiag, double theta, double* S, uint8_t* mask, hipStream_t s) {
-    const double th2 = theta * theta;
-    LAUNCH(k_soc_mask, n, n, rowptr, col, dir, lval, ldiag, th2, S, mask);
+void soc_mask(const DCsr& A, const uint8_t* dir, const double* lval, const double* ldiag, double theta, double* S,
+              uint8_t* mask, hipStream_t s) {
+    if (A.nblk <= 0) return;
+    MaskArgs a{A.rowptr.get(), A.col.get(), A.blk.get(), A.nblk, dir, lval, ldiag, theta * theta, S, mask};
+    hipLaunchKernelGGL(k_soc_mask, dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a);
+    MATAMG_LAUNCH_CHECK();
 }
 
 void mis_init(int n, const uint8_t* dir, uint8_t* state, hipStream_t s) { LAUNCH(k_mis_init, n, n, dir, state); }
 
-void mis_round(int n, const int* rowptr, const int* col, const uint8_t* mask, uint64_t key, uint8_t* state,
-               uint64_t* t1, uint64_t* t2, int* undecided, hipStream_t s) {
+void mis_round(const DCsr& A, const uint8_t* mask, uint64_t key, uint8_t* state, uint64_t* t1, uint64_t* t2,
+               int* undecided, hipStream_t s) {
+    const int n = A.n;
     MATAMG_HIP(hipMemsetAsync(undecided, 0, sizeof(int), s));
-    LAUNCH(k_mis_hop0, n, n, rowptr, col, mask, key, state, t1);
-    LAUNCH(k_mis_hop1, n, n, rowptr, col, mask, t1, t2);
+    if (A.nblk > 0) {
+        hipLaunchKernelGGL((k_mis_hop<true>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, A.rowptr.get(),
+                           A.col.get(), mask, A.blk.get(), A.nblk, key, (const uint8_t*)state, (const uint64_t*)nullptr,
+                           t1);
+        hipLaunchKernelGGL((k_mis_hop<false>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, A.rowptr.get(),
+                           A.col.get(), mask, A.blk.get(), A.nblk, key, (const uint8_t*)state, (const uint64_t*)t1,
+                           t2);
+        MATAMG_LAUNCH_CHECK();
+    }
     LAUNCH(k_mis_update, n, n, key, t2, state, undecided);
 }
 
@@ -554,13 +728,19 @@ void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, c
     LAUNCH(k_agg_phase3, n, n, rowptr, col, mask, dir, phase2, agg);
 }
 
-void filter_count(int n, const int* rowptr, const int* col, const uint8_t* mask, int* cnt, hipStream_t s) {
-    LAUNCH(k_filter_count, n, n, rowptr, col, mask, cnt);
+void filter_count(const DCsr& A, const uint8_t* mask, int* cnt, hipStream_t s) {
+    if (A.nblk <= 0) return;
+    hipLaunchKernelGGL(k_filter_count, dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, A.rowptr.get(), A.col.get(), mask,
+                       A.blk.get(), A.nblk, cnt);
+    MATAMG_LAUNCH_CHECK();
 }
 
-void filter_fill(int n, const int* rowptr, const int* col, const double* val, const uint8_t* mask,
-                 const int* frowptr, int* fcol, double* fval, double* dt, double* dtinv, hipStream_t s) {
-    LAUNCH(k_filter_fill, n, n, rowptr, col, val, mask, frowptr, fcol, fval, dt, dtinv);
+void filter_fill(const DCsr& A, const uint8_t* mask, const int* frowptr, int* fcol, double* fval, double* dt,
+                 double* dtinv, hipStream_t s) {
+    if (A.nblk <= 0) return;
+    hipLaunchKernelGGL(k_filter_fill, dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, A.rowptr.get(), A.col.get(),
+                       A.val.get(), mask, A.blk.get(), A.nblk, frowptr, fcol, fval, dt, dtinv);
+    MATAMG_LAUNCH_CHECK();
 }
 
 void phat_counts(int n, const int* agg, int* cnt, hipStream_t s) { LAUNCH(k_phat_counts, n, n, agg, cnt); }

@@ -3,11 +3,12 @@
 // dense coarse-level GEMV, and the integer prefix scan used by setup.
 //
 // Streaming CSR layout: rows are cut into blocks of at most kStreamCap
-// stored entries and kMaxRowsPerBlock rows.  A 256-thread block first streams
+// stored entries and kMaxRowsPerBlock rows; a row longer than kLongRow gets a
+// block of its own.  A 256-thread block first streams
 // its contiguous val/col range (fully coalesced) and stores val*x[col] in
 // LDS, then one thread per row sums its products in ascending stored order
-// and applies the epilogue.  A row longer than kStreamCap gets a block of its
-// own that reduces it with a fixed tree.  Every sum therefore has a fixed
+// and applies the epilogue.  A long row is reduced by the whole block: strided
+// partial sums and a fixed tree.  Every sum therefore has a fixed
 // order for a given matrix: results are bitwise reproducible run to run.
 #include "device_util.h"
 #include "kernels.h"
@@ -153,7 +154,7 @@ std::vector<int> stream_blocks(const int* rp, int n) {
     int cur = 0, rows = 0;
     for (int r = 0; r < n; ++r) {
         int len = rp[r + 1] - rp[r];
-        if (len > kStreamCap) {
+        if (len > kLongRow) {
             if (rows > 0) blk.push_back(r);
             blk.push_back(r + 1);
             cur = 0;
@@ -225,17 +226,6 @@ __device__ __forceinline__ double epilogue(const SArgs<T>& a, int r, T s) {
     return dp;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup g runs
-// on XCD g % 8).  Remapping so that each XCD walks one contiguous eighth of
-// the row blocks keeps the gathered neighbours of consecutive blocks in that
-// XCD's L2.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_block(int nblk) {
-    const int per = (nblk + kXcds - 1) / kXcds;
-    return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
-}
-inline int xcd_grid(int nblk) { return ((nblk + kXcds - 1) / kXcds) * kXcds; }
-
 constexpr int kPerThread = kStreamCap / kBlock;
 
 template <typename T, int MODE, bool HAS_DOT>
@@ -249,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a, int nblk) {
     const int k0 = a.rowptr[r0], k1 = a.rowptr[r1];
     const int cnt = k1 - k0;
     double dp = 0.0;
-    if (cnt <= kStreamCap) {
+    if (!(r1 - r0 == 1 && cnt > kLongRow)) {
         // issue every load of this thread's share before using any of them
         int c[kPerThread];
         T v[kPerThread];
@@ -275,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a, int nblk) {
             dp = epilogue<T, MODE, HAS_DOT>(a, r, s);
         }
     } else {
-        // one long row: strided partial sums then a fixed tree
+        // one long row (a block of its own): strided partial sums, fixed tree
         T s = 0;
         for (int t = threadIdx.x; t < cnt; t += kBlock) {
             const int k = k0 + t;

@@ -94,19 +94,36 @@ __device__ void for_each_product(const int* arp, const int* acol, const double* 
     }
 }
 
-__device__ __forceinline__ int ld_key(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// number of products of row i (sum of the B-row lengths over A's row), on every lane
+__device__ __forceinline__ int row_products(const int* arp, const int* acol, const int* brp, int i) {
+    const int lane = threadIdx.x & 63;
+    int m = 0;
+    for (int ka = arp[i] + lane; ka < arp[i + 1]; ka += 64) {
+        const int k = acol[ka];
+        m += brp[k + 1] - brp[k];
+    }
+    for (int off = 32; off > 0; off >>= 1) m += __shfl_xor(m, off, 64);
+    return m;
 }
 
-// Memory ordering between the phases of one wavefront's row.  The LDS path
-// only needs its LDS operations completed and not reordered (workgroup
-// scope).  The global-memory path (rare, long rows) uses an agent-scope fence
-// so values written through L2 by atomics are re-read from L2.
+// LDS table size for a row with m products: a power of two >= 2m, 64..kHS
+__device__ __forceinline__ unsigned lds_table_mask(int m) {
+    unsigned t = 64;
+    while (t < 2u * (unsigned)m && t < (unsigned)kHS) t <<= 1;
+    return t - 1;
+}
+
+__device__ __forceinline__ int ld_key(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Memory ordering between the phases of one wavefront's row.  A row's hash
+// table (LDS, or global memory for long rows) is private to one wavefront,
+// which runs on one CU: workgroup scope orders its accesses.
 template <bool GLOBAL>
 __device__ __forceinline__ void phase_fence() {
     __builtin_amdgcn_wave_barrier();
-    if constexpr (GLOBAL) __threadfence();
-    else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -144,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int
         mask = (unsigned)(goff[ridx + 1] - o) - 1;
     } else {
         keys = skeys[w];
-        mask = kHS - 1;
+        mask = lds_table_mask(row_products(arp, acol, brp, i));
     }
     for (unsigned h = lane; h <= mask; h += 64) keys[h] = -1;
     phase_fence<GLOBAL>();
@@ -195,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
         keys = skeys[w];
         vals = svals[w];
         acc = sacc[w];
-        mask = kHS - 1;
+        mask = lds_table_mask(row_products(arp, acol, brp, i));
     }
     for (unsigned h = lane; h <= mask; h += 64) {
         keys[h] = -1;

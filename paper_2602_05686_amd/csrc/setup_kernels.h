@@ -27,23 +27,23 @@ void clement(int n, int dim, const Incidence& inc, const double* elem_sigma, dou
 void tensor_inverse(int n, int dim, const double* sig, double* minv, int* flag, hipStream_t s);
 // lval[k] = |L_ij| (0 for diagonal / Dirichlet edges, -1 for coincident
 // points), ldiag[i] = sum of lval over the row (ascending)
-void soc_values(int n, const int* rowptr, const int* col, const double* val, int dim, const double* x,
-                const double* minv, const uint8_t* dir, int soc, double* lval, double* ldiag, hipStream_t s);
-void soc_mask(int n, const int* rowptr, const int* col, const uint8_t* dir, const double* lval,
-              const double* ldiag, double theta, double* S, uint8_t* mask, hipStream_t s);
+void soc_values(const DCsr& A, int dim, const double* x, const double* minv, const uint8_t* dir, int soc,
+                double* lval, double* ldiag, hipStream_t s);
+void soc_mask(const DCsr& A, const uint8_t* dir, const double* lval, const double* ldiag, double theta, double* S,
+              uint8_t* mask, hipStream_t s);
 
 void mis_init(int n, const uint8_t* dir, uint8_t* state, hipStream_t s);
 // one synchronous round; *undecided (device) receives the number of nodes still undecided
-void mis_round(int n, const int* rowptr, const int* col, const uint8_t* mask, uint64_t key, uint8_t* state,
-               uint64_t* t1, uint64_t* t2, int* undecided, hipStream_t s);
+void mis_round(const DCsr& A, const uint8_t* mask, uint64_t key, uint8_t* state, uint64_t* t1, uint64_t* t2,
+               int* undecided, hipStream_t s);
 void agg_root_flags(int n, const uint8_t* state, int* flags, hipStream_t s);
 void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint8_t* dir,
                 const uint8_t* state, const int* root_rank, int* phase2, int* agg, hipStream_t s);
 
 // filtered matrix A_F (diagonal + kept entries, lumped diagonal) and its 1-norm diagonal
-void filter_count(int n, const int* rowptr, const int* col, const uint8_t* mask, int* cnt, hipStream_t s);
-void filter_fill(int n, const int* rowptr, const int* col, const double* val, const uint8_t* mask,
-                 const int* frowptr, int* fcol, double* fval, double* dt, double* dtinv, hipStream_t s);
+void filter_count(const DCsr& A, const uint8_t* mask, int* cnt, hipStream_t s);
+void filter_fill(const DCsr& A, const uint8_t* mask, const int* frowptr, int* fcol, double* fval, double* dt,
+                 double* dtinv, hipStream_t s);
 void phat_counts(int n, const int* agg, int* cnt, hipStream_t s);
 void phat_fill(int n, const int* agg, const int* prowptr, int* pcol, double* pval, hipStream_t s);
 void prolongator_finalize(int n, const int* prowptr, const int* pcol, double* pval, const int* agg,
