@@ -12,8 +12,8 @@ products, coarse factorisation) followed by amg_pcg_solve to a true relative
 residual of 1e-8.  value = DOF * steps / time.  The JSON line also carries
 solve-only throughput, the FP32-hierarchy form against the FP64 form, the
 V-cycle's algorithmic HBM bandwidth, the roofline of the dominant kernel
-(the finest level's fused Chebyshev SpMV, timed with HIP events on its
-stream) and the CPU oracle timed on a bounded sample of the same recipe.
+(the finest level's fused Chebyshev SpMV: back-to-back launches between
+HIP events on its stream) and the CPU oracle timed on a bounded sample of the same recipe.
 """
 
 import argparse
@@ -44,21 +44,23 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(n_sample, repeats, stretch):
-    """The oracle as it stands, single-threaded, on a smaller stack of the same recipe."""
+def cpu_baseline(prob, iterations, sample_iters):
+    """The oracle as it stands, single-threaded, on a bounded sample of the
+    same workload: its full setup plus `sample_iters` PCG iterations; the
+    solve is scaled to the GPU run's iteration count."""
     import oracle
-    from workloads.q1 import layered_stack_3d
 
-    prob = layered_stack_3d(n=n_sample, repeats=repeats, stretch=stretch)
     t0 = time.perf_counter()
     h = oracle.Hierarchy(prob)
     t1 = time.perf_counter()
-    x, info = h.pcg(prob.b)
+    _, info = h.pcg(prob.b, maxit=sample_iters)
     t2 = time.perf_counter()
-    return dict(value=prob.n / (t2 - t0), unit="DOF/s", cores=1, kind="oracle",
-                sample=(f"layered stack {n_sample}^3 hexes ({prob.n} DOF), {repeats} repeats, "
-                        f"{stretch:g}:1 flat, full setup + PCG to 1e-8 ({info['iterations']} iterations), "
-                        f"setup {t1 - t0:.2f}s solve {t2 - t1:.2f}s"),
+    t_iter = (t2 - t1) / max(info["iterations"], 1)
+    t_est = (t1 - t0) + t_iter * iterations
+    return dict(value=prob.n / t_est, unit="DOF/s", cores=1, kind="oracle",
+                sample=(f"same workload ({prob.n} DOF): full oracle setup ({t1 - t0:.1f}s) + "
+                        f"{info['iterations']} PCG iterations ({t2 - t1:.1f}s, {t_iter * 1e3:.0f} ms/iteration); "
+                        f"solve scaled to the GPU run's {iterations} iterations"),
                 host_cpu=cpu_model(), host_threads=os.cpu_count())
 
 
@@ -71,7 +73,9 @@ def main():
     ap.add_argument("--repeats", type=int, default=20)
     ap.add_argument("--stretch", type=float, default=10.0)
     ap.add_argument("--vcycles", type=int, default=50)
-    ap.add_argument("--cpu-sample", type=int, default=48, help="hexes per side of the oracle sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=5, help="oracle PCG iterations in the CPU sample (0: skip)")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="one setup, a few V-cycles and a 1 GiB device copy (for counter collection), no JSON")
     ap.add_argument("--no-fp32", action="store_true")
     args = ap.parse_args()
 
@@ -108,6 +112,22 @@ def main():
         x.zero_()
         _, info = h.solve(d["b"], x)
         return h, info
+
+    if args.profile_kernels:
+        # copy calibration: a plain copy of 1 GiB (read 1 GiB, write 1 GiB)
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        h = amg.Hierarchy(d["rowptr"], d["col"], d["val"], d["en"], d["es"], d["xc"], opts64)
+        r = torch.randn(n, dtype=torch.float64, device=dev)
+        z = torch.zeros_like(r)
+        for _ in range(3):
+            h.vcycle(r, z)
+        torch.cuda.synchronize()
+        h.close()
+        log("profile run done")
+        return
 
     log(f"warmup {args.warmup} step(s)")
     for _ in range(args.warmup):
@@ -155,13 +175,8 @@ def main():
     torch.cuda.synchronize()
     t_vc_ms = e0.elapsed_time(e1) / args.vcycles
     vc_gbs = st["vcycle_alg_bytes"] / (t_vc_ms * 1e-3) / 1e9
-    h.kernel_timing(True)
-    for _ in range(args.vcycles):
-        h.vcycle(r, z)
-    torch.cuda.synchronize()
-    kt = h.kernel_timing_read()
-    h.kernel_timing(False)
-    avg_ms = kt["total_ms"] / max(kt["launches"], 1)
+    kt = h.time_smoother(level=0, reps=args.vcycles)
+    avg_ms = kt["avg_ms"]
     achieved = kt["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
     log(f"V-cycle {t_vc_ms:.3f} ms = {vc_gbs:.0f} GB/s algorithmic; fine smoother SpMV {avg_ms * 1e3:.1f} us "
         f"= {achieved:.0f} GB/s")
@@ -183,8 +198,8 @@ def main():
 
     cpu = None
     if args.cpu_sample > 0:
-        log(f"oracle sample {args.cpu_sample}^3")
-        cpu = cpu_baseline(args.cpu_sample, args.repeats, args.stretch)
+        log(f"oracle sample: setup + {args.cpu_sample} PCG iterations")
+        cpu = cpu_baseline(prob, infos[-1]["iterations"], args.cpu_sample)
 
     out = {
         "metric": "DOF/s to rel-res 1e-8 (setup + AMG-PCG solve)",
@@ -214,7 +229,7 @@ def main():
                    "frac_of_peak": vc_gbs / HBM_PEAK_GBS},
         "roofline": {"bound": "hbm", "kernel": "k_stream<double, SMOOTH> on the finest level",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_us": avg_ms * 1e3, "launches": kt["launches"],
+                     "traffic": None, "avg_launch_us": avg_ms * 1e3, "launches": args.vcycles,
                      "alg_bytes_per_launch": kt["bytes_per_launch"]},
         "fp32_form": fp32,
         "cpu_baseline": cpu,

@@ -165,17 +165,17 @@ amg_status amg_get_level_csr(const amg_hierarchy* h, int32_t level, int32_t whic
                              int32_t* col, double* val);
 amg_status amg_get_level_aux(const amg_hierarchy* h, int32_t level, int32_t which, double* out);
 
-/* Kernel timing for roofline measurements (benchmarks): while enabled, each
- * launch of the finest level's smoother SpMV is bracketed by HIP events on the
- * stream it runs on.  amg_kernel_timing(h, 1) clears earlier records.
- * amg_kernel_timing_read synchronises those events and returns the summed
- * duration, the number of timed launches and the algorithmic bytes one such
- * launch moves (matrix values, column indices and row pointers once, the
- * gathered iterate once, b, D^{-1} and the direction read, direction and
- * iterate written). */
-amg_status amg_kernel_timing(amg_hierarchy* h, int32_t enable);
-amg_status amg_kernel_timing_read(amg_hierarchy* h, double* total_ms, int64_t* launches,
-                                  double* bytes_per_launch);
+/* Roofline timing of the dominant kernel (benchmarks): runs `reps`
+ * back-to-back launches of the level's fused smoother step (the Chebyshev
+ * SpMV with its vector epilogue) on the hierarchy's own work vectors between
+ * two HIP events recorded on `hip_stream`, and returns the average launch
+ * duration in ms and the algorithmic bytes one launch moves: matrix values,
+ * column indices and row pointers once, the gathered iterate once, b, D^{-1}
+ * and the direction read, the direction and the new iterate written.
+ * Overwrites the level's work vectors.  Errors: INVALID_ARG (no smoother on
+ * that level, reps < 1). */
+amg_status amg_time_smoother(amg_hierarchy* h, int32_t level, int32_t reps, void* hip_stream, double* avg_ms,
+                             double* bytes_per_launch);
 
 void amg_free(amg_hierarchy* h);
 const char* amg_status_string(amg_status s);

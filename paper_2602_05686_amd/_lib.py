@@ -27,8 +27,8 @@ PRECISION = {"fp64": 0, "fp32": 1}
 
 EXPORTED = [
     "amg_options_default", "amg_setup", "amg_pcg_solve", "amg_vcycle", "amg_level_spmv", "amg_hierarchy_info",
-    "amg_get_aggregates", "amg_get_soc_mask", "amg_get_level_csr", "amg_get_level_aux", "amg_kernel_timing",
-    "amg_kernel_timing_read", "amg_free", "amg_status_string", "amg_last_error",
+    "amg_get_aggregates", "amg_get_soc_mask", "amg_get_level_csr", "amg_get_level_aux", "amg_time_smoother",
+    "amg_free", "amg_status_string", "amg_last_error",
 ]
 
 
@@ -105,8 +105,7 @@ def load():
     L.amg_get_soc_mask.argtypes = [P, i32, P]
     L.amg_get_level_csr.argtypes = [P, i32, i32, P, P, P]
     L.amg_get_level_aux.argtypes = [P, i32, i32, P]
-    L.amg_kernel_timing.argtypes = [P, i32]
-    L.amg_kernel_timing_read.argtypes = [P, ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(f64)]
+    L.amg_time_smoother.argtypes = [P, i32, i32, P, ctypes.POINTER(f64), ctypes.POINTER(f64)]
     L.amg_free.argtypes = [P]
     L.amg_free.restype = None
     L.amg_status_string.argtypes = [i32]
@@ -223,14 +222,12 @@ class Hierarchy:
     def level_spmv(self, level, x, y, stream=None):
         check(load().amg_level_spmv(self._h, level, _dp(x), _dp(y), _stream(stream)), "amg_level_spmv")
 
-    def kernel_timing(self, enable: bool):
-        check(load().amg_kernel_timing(self._h, 1 if enable else 0), "amg_kernel_timing")
-
-    def kernel_timing_read(self):
-        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
-        check(load().amg_kernel_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)),
-              "amg_kernel_timing_read")
-        return dict(total_ms=ms.value, launches=n.value, bytes_per_launch=b.value)
+    def time_smoother(self, level=0, reps=50, stream=None):
+        """Average duration (ms) of the level's fused smoother step and its algorithmic bytes."""
+        ms, b = ctypes.c_double(), ctypes.c_double()
+        check(load().amg_time_smoother(self._h, level, reps, _stream(stream), ctypes.byref(ms), ctypes.byref(b)),
+              "amg_time_smoother")
+        return dict(avg_ms=ms.value, bytes_per_launch=b.value)
 
     # ------------------------------------------------------------ queries
     def stats(self):

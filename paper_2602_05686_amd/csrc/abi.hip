@@ -241,37 +241,13 @@ amg_status amg_get_level_aux(const amg_hierarchy* hh, int32_t level, int32_t whi
     });
 }
 
-/* Kernel timing for roofline measurements: when enabled, every launch of the
- * finest level's smoother SpMV is bracketed by HIP events on its stream. */
-amg_status amg_kernel_timing(amg_hierarchy* hh, int32_t enable) {
+amg_status amg_time_smoother(amg_hierarchy* hh, int32_t level, int32_t reps, void* hip_stream, double* avg_ms,
+                             double* bytes_per_launch) {
     return guarded([&]() -> amg_status {
         Hierarchy& h = H(hh);
-        for (auto e : h.timer.ev) (void)hipEventDestroy(e);
-        h.timer.ev.clear();
-        h.timer.enabled = enable != 0;
-        return AMG_OK;
-    });
-}
-
-amg_status amg_kernel_timing_read(amg_hierarchy* hh, double* total_ms, int64_t* launches, double* bytes_per_launch) {
-    return guarded([&]() -> amg_status {
-        Hierarchy& h = H(hh);
-        double tot = 0.0;
-        for (size_t i = 0; i + 1 < h.timer.ev.size(); i += 2) {
-            MATAMG_HIP(hipEventSynchronize(h.timer.ev[i + 1]));
-            float ms = 0.f;
-            MATAMG_HIP(hipEventElapsedTime(&ms, h.timer.ev[i], h.timer.ev[i + 1]));
-            tot += ms;
-        }
-        if (total_ms) *total_ms = tot;
-        if (launches) *launches = (int64_t)(h.timer.ev.size() / 2);
-        if (bytes_per_launch) {
-            // algorithmic bytes of one fine-level smoother step: val + col +
-            // rowptr + gathered x + (b, dinv, d) read + (d, x) written
-            const Level& L = h.lev[0];
-            const double s = h.fp32 ? 4.0 : 8.0;
-            *bytes_per_launch = (double)L.A.nnz * (s + 4.0) + 4.0 * (L.A.n + 1) + 6.0 * s * L.A.n;
-        }
+        if (level < 0 || level + 1 >= h.nlev) fail(AMG_ERR_INVALID_ARG, "level has no smoother");
+        if (reps < 1 || !avg_ms) fail(AMG_ERR_INVALID_ARG, "reps must be positive");
+        *avg_ms = h.time_smoother(level, reps, (hipStream_t)hip_stream, bytes_per_launch);
         return AMG_OK;
     });
 }

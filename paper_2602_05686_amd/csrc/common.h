@@ -104,15 +104,19 @@ struct DCsr {
     DBuf<int> rowptr, col;
     DBuf<double> val;
     DBuf<float> val32;
-    // row blocks for the streaming SpMV: blk[b] .. blk[b+1] rows of block b
+    // row blocks for the streaming SpMV: blk[b] .. blk[b+1] rows of block b;
+    // `group` threads reduce each row (1 for short rows, 8 when rows are long)
     DBuf<int> blk;
     int nblk = 0;
+    int group = 1;
 };
 
 constexpr int kBlock = 256;          // threads per block in streaming kernels
 constexpr int kStreamCap = 2048;     // nnz staged in LDS per streaming block
 constexpr int kMaxRowsPerBlock = kBlock;
-constexpr int kLongRow = 96;         // rows longer than this are reduced by a whole block
+constexpr int kLongRow = 96;         // single-thread rows: longer rows get a whole block
+// rows longer than this are reduced by a whole block, for `group` threads per row
+constexpr int long_row_limit(int group) { return group == 1 ? kLongRow : (32 * group < kStreamCap ? 32 * group : kStreamCap); }
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 

@@ -27,13 +27,6 @@ struct Level {
     DBuf<float> fb, fxa, fxb, fd, fr;
 };
 
-struct KernelTimer {
-    bool enabled = false;
-    std::vector<hipEvent_t> ev;  // start/stop pairs
-    int64_t launches = 0;
-    double ms = 0.0;
-};
-
 struct Hierarchy {
     amg_options opt{};
     int nlev = 0;
@@ -48,7 +41,6 @@ struct Hierarchy {
     double* hscal = nullptr; // pinned host mirror of scal
     double t_setup = 0.0;
     bool fp32 = false;
-    KernelTimer timer;
 
     ~Hierarchy();
     DotTarget dt(int slot) const;
@@ -56,6 +48,7 @@ struct Hierarchy {
     template <typename T>
     void vcycle_t(const double* r, double* z, DotTarget rz, hipStream_t s);
     double vcycle_alg_bytes() const;
+    double time_smoother(int level, int reps, hipStream_t s, double* bytes_per_launch);
 };
 
 // device scalar slots

@@ -32,7 +32,10 @@ double now_s() {
 void make_blocks(DCsr& A, MemCounter* mc, hipStream_t s) {
     std::vector<int> rp((size_t)A.n + 1);
     d2h(rp.data(), A.rowptr.get(), rp.size(), s);
-    std::vector<int> blk = stream_blocks(rp.data(), A.n);
+    int max_len = 0;
+    for (int i = 0; i < A.n; ++i) max_len = std::max(max_len, rp[i + 1] - rp[i]);
+    A.group = stream_group(max_len);
+    std::vector<int> blk = stream_blocks(rp.data(), A.n, A.group);
     A.nblk = (int)blk.size() - 1;
     A.blk.alloc(blk.size(), mc);
     h2d(A.blk.get(), blk.data(), blk.size(), s);
@@ -116,9 +119,75 @@ void alloc_work<float>(Level& L, int n, bool coarse_only, MemCounter* mc) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ V-cycle
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+    static double* b(Level& L) { return L.b.get(); }
+    static double* xa(Level& L) { return L.xa.get(); }
+    static double* xb(Level& L) { return L.xb.get(); }
+    static double* d(Level& L) { return L.d.get(); }
+    static double* r(Level& L) { return L.r.get(); }
+    static const double* A(const DCsr& M) { return M.val.get(); }
+    static const double* dinv(Level& L) { return L.dinv.get(); }
+};
+template <>
+struct Vec<float> {
+    static float* b(Level& L) { return L.fb.get(); }
+    static float* xa(Level& L) { return L.fxa.get(); }
+    static float* xb(Level& L) { return L.fxb.get(); }
+    static float* d(Level& L) { return L.fd.get(); }
+    static float* r(Level& L) { return L.fr.get(); }
+    static const float* A(const DCsr& M) { return M.val32.get(); }
+    static const float* dinv(Level& L) { return L.dinv32.get(); }
+};
+
 Hierarchy::~Hierarchy() {
     if (hscal) (void)hipHostFree(hscal);
-    for (auto e : timer.ev) (void)hipEventDestroy(e);
+}
+
+// Steady-state duration of one smoother step on `level` (the fused
+// Chebyshev SpMV that dominates the V-cycle): `reps` back-to-back launches
+// between two events on the stream, on the level's own work vectors.
+double Hierarchy::time_smoother(int level, int reps, hipStream_t s, double* bytes_per_launch) {
+    Level& L = lev[level];
+    const int n = L.A.n;
+    hipEvent_t e0, e1;
+    MATAMG_HIP(hipEventCreate(&e0));
+    MATAMG_HIP(hipEventCreate(&e1));
+    const double c1 = L.c1.size() > 1 ? L.c1[1] : 0.0, c2 = L.c2.size() > 1 ? L.c2[1] : L.c2[0];
+    double ms_total = 0.0;
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        using V = Vec<T>;
+        T* x = V::xa(L);
+        T* y = V::xb(L);
+        MATAMG_HIP(hipMemsetAsync(V::b(L), 0, sizeof(T) * n, s));
+        MATAMG_HIP(hipMemsetAsync(x, 0, sizeof(T) * n, s));
+        MATAMG_HIP(hipMemsetAsync(V::d(L), 0, sizeof(T) * n, s));
+        spmv_smooth<T>(L.A, V::A(L.A), x, V::b(L), V::dinv(L), V::d(L), (T)c1, (T)c2, y, nullptr, nullptr,
+                       DotTarget{}, s);
+        MATAMG_HIP(hipEventRecord(e0, s));
+        for (int k = 0; k < reps; ++k) {
+            spmv_smooth<T>(L.A, V::A(L.A), x, V::b(L), V::dinv(L), V::d(L), (T)c1, (T)c2, y, nullptr, nullptr,
+                           DotTarget{}, s);
+            std::swap(x, y);
+        }
+        MATAMG_HIP(hipEventRecord(e1, s));
+        MATAMG_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        MATAMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ms_total = ms;
+    };
+    if (fp32) run(float{});
+    else run(double{});
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const double sz = fp32 ? 4.0 : 8.0;
+    // val + col + rowptr once, the gathered iterate once, b, D^{-1}, d read, d and x written
+    if (bytes_per_launch) *bytes_per_launch = (double)L.A.nnz * (sz + 4.0) + 4.0 * (L.A.n + 1) + 6.0 * sz * L.A.n;
+    return ms_total / reps;
 }
 
 DotTarget Hierarchy::dt(int slot) const { return DotTarget{partial.get(), counter.get(), scal.get() + slot}; }
@@ -361,30 +430,6 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
     return hp;
 }
 
-// ------------------------------------------------------------------ V-cycle
-template <typename T>
-struct Vec;
-template <>
-struct Vec<double> {
-    static double* b(Level& L) { return L.b.get(); }
-    static double* xa(Level& L) { return L.xa.get(); }
-    static double* xb(Level& L) { return L.xb.get(); }
-    static double* d(Level& L) { return L.d.get(); }
-    static double* r(Level& L) { return L.r.get(); }
-    static const double* A(const DCsr& M) { return M.val.get(); }
-    static const double* dinv(Level& L) { return L.dinv.get(); }
-};
-template <>
-struct Vec<float> {
-    static float* b(Level& L) { return L.fb.get(); }
-    static float* xa(Level& L) { return L.fxa.get(); }
-    static float* xb(Level& L) { return L.fxb.get(); }
-    static float* d(Level& L) { return L.fd.get(); }
-    static float* r(Level& L) { return L.fr.get(); }
-    static const float* A(const DCsr& M) { return M.val32.get(); }
-    static const float* dinv(Level& L) { return L.dinv32.get(); }
-};
-
 template <typename T>
 void Hierarchy::vcycle_t(const double* r64, double* z64, DotTarget rz, hipStream_t s) {
     using V = Vec<T>;
@@ -409,23 +454,10 @@ void Hierarchy::vcycle_t(const double* r64, double* z64, DotTarget rz, hipStream
         }
         T* x = V::xa(Lv);
         T* y = V::xb(Lv);
-        const bool timed = timer.enabled && l == 0;
         smooth_first<T>(n, b64, b, V::dinv(Lv), (T)Lv.c2[0], V::d(Lv), x, s);
         for (size_t k = 1; k < Lv.c1.size(); ++k) {
-            if (timed) {
-                hipEvent_t e0, e1;
-                MATAMG_HIP(hipEventCreate(&e0));
-                MATAMG_HIP(hipEventCreate(&e1));
-                MATAMG_HIP(hipEventRecord(e0, s));
-                spmv_smooth<T>(Lv.A, V::A(Lv.A), x, b, V::dinv(Lv), V::d(Lv), (T)Lv.c1[k], (T)Lv.c2[k], y, nullptr,
-                               nullptr, DotTarget{}, s);
-                MATAMG_HIP(hipEventRecord(e1, s));
-                timer.ev.push_back(e0);
-                timer.ev.push_back(e1);
-            } else {
-                spmv_smooth<T>(Lv.A, V::A(Lv.A), x, b, V::dinv(Lv), V::d(Lv), (T)Lv.c1[k], (T)Lv.c2[k], y, nullptr,
-                               nullptr, DotTarget{}, s);
-            }
+            spmv_smooth<T>(Lv.A, V::A(Lv.A), x, b, V::dinv(Lv), V::d(Lv), (T)Lv.c1[k], (T)Lv.c2[k], y, nullptr,
+                           nullptr, DotTarget{}, s);
             std::swap(x, y);
         }
         cur[l] = x;
@@ -455,20 +487,8 @@ void Hierarchy::vcycle_t(const double* r64, double* z64, DotTarget rz, hipStream
                 else out64 = z64;
             }
             const double* dv = last ? r64 : nullptr;
-            const bool timed = timer.enabled && l == 0;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (timed) {
-                MATAMG_HIP(hipEventCreate(&e0));
-                MATAMG_HIP(hipEventCreate(&e1));
-                MATAMG_HIP(hipEventRecord(e0, s));
-            }
             spmv_smooth<T>(Lv.A, V::A(Lv.A), x, b, V::dinv(Lv), V::d(Lv), (T)(k == 0 ? 0.0 : Lv.c1[k]), (T)Lv.c2[k],
                            out, out64, dv, last ? rz : DotTarget{}, s);
-            if (timed) {
-                MATAMG_HIP(hipEventRecord(e1, s));
-                timer.ev.push_back(e0);
-                timer.ev.push_back(e1);
-            }
             if (!last) std::swap(x, y);
         }
         cur[l] = x;

@@ -147,21 +147,25 @@ template void dot<double>(const double*, const double*, int64_t, double*, unsign
 template void dot<float>(const float*, const float*, int64_t, double*, unsigned*, double*, hipStream_t);
 
 // =============================================================== streaming
-std::vector<int> stream_blocks(const int* rp, int n) {
+int stream_group(int max_len) { return max_len <= kLongRow ? 1 : 8; }
+
+std::vector<int> stream_blocks(const int* rp, int n, int group) {
+    const int max_rows = kBlock / group;
+    const int long_len = long_row_limit(group);
     std::vector<int> blk;
     blk.reserve((size_t)n / 32 + 2);
     blk.push_back(0);
     int cur = 0, rows = 0;
     for (int r = 0; r < n; ++r) {
         int len = rp[r + 1] - rp[r];
-        if (len > kLongRow) {
+        if (len > long_len) {
             if (rows > 0) blk.push_back(r);
             blk.push_back(r + 1);
             cur = 0;
             rows = 0;
             continue;
         }
-        if (rows > 0 && (cur + len > kStreamCap || rows == kMaxRowsPerBlock)) {
+        if (rows > 0 && (cur + len > kStreamCap || rows == max_rows)) {
             blk.push_back(r);
             cur = 0;
             rows = 0;
@@ -228,7 +232,7 @@ __device__ __forceinline__ double epilogue(const SArgs<T>& a, int r, T s) {
 
 constexpr int kPerThread = kStreamCap / kBlock;
 
-template <typename T, int MODE, bool HAS_DOT>
+template <typename T, int MODE, bool HAS_DOT, int G>
 __global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a, int nblk) {
     __shared__ T prod[kStreamCap];
     __shared__ double sh[kBlock / 64];
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a, int nblk) {
     const int k0 = a.rowptr[r0], k1 = a.rowptr[r1];
     const int cnt = k1 - k0;
     double dp = 0.0;
-    if (!(r1 - r0 == 1 && cnt > kLongRow)) {
+    if (!(r1 - r0 == 1 && cnt > long_row_limit(G))) {
         // issue every load of this thread's share before using any of them
         int c[kPerThread];
         T v[kPerThread];
@@ -257,13 +261,18 @@ __global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a, int nblk) {
             if (t < cnt) prod[t] = v[u] * a.x[c[u]];
         }
         __syncthreads();
-        const int r = r0 + (int)threadIdx.x;
+        // G threads per row: strided partial sums, then a fixed shuffle tree
+        const int gl = (int)threadIdx.x % G;
+        const int r = r0 + (int)threadIdx.x / G;
+        T s = 0;
         if (r < r1) {
             const int s0 = a.rowptr[r] - k0, s1 = a.rowptr[r + 1] - k0;
-            T s = 0;
-            for (int k = s0; k < s1; ++k) s += prod[k];
-            dp = epilogue<T, MODE, HAS_DOT>(a, r, s);
+            for (int k = s0 + gl; k < s1; k += G) s += prod[k];
         }
+        if constexpr (G > 1) {
+            for (int off = G / 2; off > 0; off >>= 1) s += __shfl_down(s, off, G);
+        }
+        if (gl == 0 && r < r1) dp = epilogue<T, MODE, HAS_DOT>(a, r, s);
     } else {
         // one long row (a block of its own): strided partial sums, fixed tree
         T s = 0;
@@ -290,7 +299,10 @@ __global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a, int nblk) {
 template <typename T, int MODE, bool HAS_DOT>
 void launch_stream(const DCsr& A, const SArgs<T>& a, hipStream_t s) {
     if (A.nblk <= 0) return;
-    hipLaunchKernelGGL((k_stream<T, MODE, HAS_DOT>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a, A.nblk);
+    if (A.group == 1)
+        hipLaunchKernelGGL((k_stream<T, MODE, HAS_DOT, 1>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a, A.nblk);
+    else
+        hipLaunchKernelGGL((k_stream<T, MODE, HAS_DOT, 8>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a, A.nblk);
     MATAMG_LAUNCH_CHECK();
     if constexpr (HAS_DOT) finish_sum(a.dt, A.nblk, s);
 }

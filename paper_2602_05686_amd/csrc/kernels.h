@@ -19,7 +19,9 @@ void dot(const T* a, const T* b, int64_t n, double* partial, unsigned* counter, 
 
 // --------------------------------------------------------------- streaming ---
 // row blocks for the streaming CSR kernels, computed from a host row pointer
-std::vector<int> stream_blocks(const int* rowptr_host, int n);
+std::vector<int> stream_blocks(const int* rowptr_host, int n, int group);
+// threads per row for a matrix whose longest row has `max_len` entries
+int stream_group(int max_len);
 
 // dot-fusion target: per-block partial sums, reduced by finish_sum into *result
 struct DotTarget {
