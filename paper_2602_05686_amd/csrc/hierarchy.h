@@ -39,6 +39,10 @@ struct Hierarchy {
     DBuf<unsigned> counter;  // reduction counters
     DBuf<double> cr, cz, cp, cq, cx, cb;  // CG vectors (x, b used for host inputs)
     double* hscal = nullptr; // pinned host mirror of scal
+    hipStream_t ws = nullptr;        // the solve's own stream (graphs cannot capture the null stream)
+    hipEvent_t ev_in = nullptr;      // orders the solve after the caller's stream
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // captured CG steps, by parity
+    bool use_graphs = true;
     double t_setup = 0.0;
     bool fp32 = false;
 
@@ -49,6 +53,7 @@ struct Hierarchy {
     void vcycle_t(const double* r, double* z, DotTarget rz, hipStream_t s);
     double vcycle_alg_bytes() const;
     double time_smoother(int level, int reps, hipStream_t s, double* bytes_per_launch);
+    hipGraphExec_t step_graph(int cur);
 };
 
 // device scalar slots

@@ -4,6 +4,7 @@
 // the V-cycle (Algorithm "Vcycle") and the outer preconditioned CG.
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 
 #include "hierarchy.h"
 #include "setup_kernels.h"
@@ -145,6 +146,10 @@ struct Vec<float> {
 
 Hierarchy::~Hierarchy() {
     if (hscal) (void)hipHostFree(hscal);
+    for (auto& g : graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ws) (void)hipStreamDestroy(ws);
 }
 
 // Steady-state duration of one smoother step on `level` (the fused
@@ -211,6 +216,14 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
     MATAMG_HIP(hipMemsetAsync(h.counter.get(), 0, sizeof(unsigned), s));
     MATAMG_HIP(hipMemsetAsync(h.scal.get(), 0, sizeof(double) * S_NSCAL, s));
     MATAMG_HIP(hipHostMalloc((void**)&h.hscal, sizeof(double) * S_NSCAL, hipHostMallocDefault));
+    MATAMG_HIP(hipStreamCreateWithFlags(&h.ws, hipStreamNonBlocking));
+    {
+        // MATAMG_NO_GRAPH=1 runs every CG step eagerly (used to check the
+        // captured graphs against direct launches)
+        const char* ng = std::getenv("MATAMG_NO_GRAPH");
+        h.use_graphs = !(ng && ng[0] == '1');
+    }
+    MATAMG_HIP(hipEventCreateWithFlags(&h.ev_in, hipEventDisableTiming));
     DBuf<int> flag(1, mc);
     MATAMG_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int), s));
 
@@ -421,6 +434,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
         }
     }
     const size_t n0 = (size_t)h.lev[0].A.n;
+    h.cx.alloc(n0, mc);
     h.cr.alloc(n0, mc);
     h.cz.alloc(n0, mc);
     h.cp.alloc(n0, mc);
@@ -529,76 +543,116 @@ double Hierarchy::vcycle_alg_bytes() const {
 }
 
 // ---------------------------------------------------------------------- PCG
+// One captured graph per parity of the iteration counter: the V-cycle and
+// search-direction update of step k followed by q = A p and the x / r update
+// of step k + 1.  All operands are hierarchy-owned buffers, so the two
+// graphs are captured once per hierarchy and replayed every step; the
+// convergence test reads the device scalars after each replay.
+hipGraphExec_t Hierarchy::step_graph(int cur) {
+    const int g = (cur == S_RZ0) ? 0 : 1;
+    if (graph[g]) return graph[g];
+    const int nxt = (cur == S_RZ0) ? S_RZ1 : S_RZ0;
+    const DCsr& A = lev[0].A;
+    const int n = A.n;
+    MATAMG_HIP(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
+    vcycle(cr.get(), cz.get(), dt(nxt), ws);
+    cg_direction(n, cp.get(), cz.get(), scal.get() + nxt, scal.get() + cur, ws);
+    spmv_dot(A, cp.get(), cq.get(), dt(S_PQ), ws);
+    cg_update(n, cx.get(), cr.get(), cp.get(), cq.get(), scal.get() + nxt, scal.get() + S_PQ, dt(S_RR), ws);
+    hipGraph_t gr = nullptr;
+    MATAMG_HIP(hipStreamEndCapture(ws, &gr));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    MATAMG_HIP(e);
+    graph[g] = ex;
+    return ex;
+}
+
 amg_status pcg_solve(Hierarchy& h, const double* b_in, double* x_io, double tol, int max_iter, bool host_ptrs,
                      hipStream_t s, amg_solve_info* info) {
     const double t0 = now_s();
     const DCsr& A = h.lev[0].A;
     const int n = A.n;
+    hipStream_t ws = h.ws;
+    // order after the caller's earlier work on its stream
+    MATAMG_HIP(hipEventRecord(h.ev_in, s));
+    MATAMG_HIP(hipStreamWaitEvent(ws, h.ev_in, 0));
     const double* b = b_in;
-    double* x = x_io;
+    double* x = h.cx.get();
     if (host_ptrs) {
-        if (!h.cx) h.cx.alloc(n, &h.mem);
         if (!h.cb) h.cb.alloc(n, &h.mem);
-        h2d(h.cb.get(), b_in, n, s);
-        h2d(h.cx.get(), x_io, n, s);
+        h2d(h.cb.get(), b_in, n, ws);
         b = h.cb.get();
-        x = h.cx.get();
+        h2d(x, x_io, n, ws);
+    } else {
+        MATAMG_HIP(hipMemcpyAsync(x, x_io, sizeof(double) * n, hipMemcpyDeviceToDevice, ws));
     }
     double* r = h.cr.get();
     double* z = h.cz.get();
     double* p = h.cp.get();
     double* q = h.cq.get();
     auto read_scal = [&]() {
-        MATAMG_HIP(hipMemcpyAsync(h.hscal, h.scal.get(), sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, s));
-        MATAMG_HIP(hipStreamSynchronize(s));
+        MATAMG_HIP(hipMemcpyAsync(h.hscal, h.scal.get(), sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, ws));
+        MATAMG_HIP(hipStreamSynchronize(ws));
     };
     amg_status st = AMG_ERR_NOT_CONVERGED;
     int iters = 0;
     double rel_true = 0.0;
-    dot<double>(b, b, n, h.partial.get(), h.counter.get(), h.scal.get() + S_BB, s);
-    spmv_resid_norm(A, x, b, r, h.dt(S_RR), s);
+    dot<double>(b, b, n, h.partial.get(), h.counter.get(), h.scal.get() + S_BB, ws);
+    spmv_resid_norm(A, x, b, r, h.dt(S_RR), ws);
     read_scal();
     const double bn = std::sqrt(h.hscal[S_BB]);
     if (bn == 0.0) {
-        MATAMG_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+        MATAMG_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, ws));
         st = AMG_OK;
     } else if (std::sqrt(h.hscal[S_RR]) / bn <= tol) {
         rel_true = std::sqrt(h.hscal[S_RR]) / bn;
         st = AMG_OK;
-    } else {
-        int cur = S_RZ0, nxt = S_RZ1;
-        h.vcycle(r, z, h.dt(cur), s);
-        cg_direction(n, p, z, h.scal.get() + cur, nullptr, s);
-        for (int it = 1; it <= max_iter; ++it) {
-            spmv_dot(A, p, q, h.dt(S_PQ), s);
-            cg_update(n, x, r, p, q, h.scal.get() + cur, h.scal.get() + S_PQ, h.dt(S_RR), s);
+    } else if (max_iter > 0) {
+        // first step eagerly: z = M r, p = z, q = A p, x and r updated
+        int cur = S_RZ0;
+        h.vcycle(r, z, h.dt(cur), ws);
+        cg_direction(n, p, z, h.scal.get() + cur, nullptr, ws);
+        spmv_dot(A, p, q, h.dt(S_PQ), ws);
+        cg_update(n, x, r, p, q, h.scal.get() + cur, h.scal.get() + S_PQ, h.dt(S_RR), ws);
+        for (int it = 1;; ++it) {
             read_scal();
+            iters = it;
             const double pq = h.hscal[S_PQ], rzv = h.hscal[cur];
             if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(rzv)) {
                 st = AMG_ERR_BREAKDOWN;
-                iters = it;
                 break;
             }
-            iters = it;
-            double rel = std::sqrt(h.hscal[S_RR]) / bn;
+            const double rel = std::sqrt(h.hscal[S_RR]) / bn;
             rel_true = rel;
             if (rel <= tol) {
-                spmv_resid_norm(A, x, b, q, h.dt(S_TMP), s);
+                spmv_resid_norm(A, x, b, q, h.dt(S_TMP), ws);
                 read_scal();
                 rel_true = std::sqrt(h.hscal[S_TMP]) / bn;
                 if (rel_true <= tol) {
                     st = AMG_OK;
                     break;
                 }
-                MATAMG_HIP(hipMemcpyAsync(r, q, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+                // residual replacement
+                MATAMG_HIP(hipMemcpyAsync(r, q, sizeof(double) * n, hipMemcpyDeviceToDevice, ws));
             }
-            h.vcycle(r, z, h.dt(nxt), s);
-            cg_direction(n, p, z, h.scal.get() + nxt, h.scal.get() + cur, s);
-            std::swap(cur, nxt);
+            if (it >= max_iter) break;
+            const int nxt = (cur == S_RZ0) ? S_RZ1 : S_RZ0;
+            if (h.use_graphs) {
+                MATAMG_HIP(hipGraphLaunch(h.step_graph(cur), ws));
+            } else {
+                h.vcycle(r, z, h.dt(nxt), ws);
+                cg_direction(n, p, z, h.scal.get() + nxt, h.scal.get() + cur, ws);
+                spmv_dot(A, p, q, h.dt(S_PQ), ws);
+                cg_update(n, x, r, p, q, h.scal.get() + nxt, h.scal.get() + S_PQ, h.dt(S_RR), ws);
+            }
+            cur = nxt;
         }
     }
-    if (host_ptrs) d2h(x_io, h.cx.get(), n, s);
-    MATAMG_HIP(hipStreamSynchronize(s));
+    if (host_ptrs) d2h(x_io, x, n, ws);
+    else MATAMG_HIP(hipMemcpyAsync(x_io, x, sizeof(double) * n, hipMemcpyDeviceToDevice, ws));
+    MATAMG_HIP(hipStreamSynchronize(ws));
     if (info) {
         info->iterations = iters;
         info->rel_res_true = rel_true;

@@ -176,6 +176,25 @@ def test_determinism(amg):
     assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
 
 
+def test_graph_replays_match_direct_launches(amg, monkeypatch):
+    """The captured CG-step graphs, replayed every iteration, give bitwise the
+    same iterates as launching the same kernels directly, across repeated
+    solves with eager work in between."""
+    prob = layered_stack_3d(n=16, repeats=4)
+    banner("graph vs eager: layered16")
+    h_graph = amg.Hierarchy.from_problem(prob, max_coarse=100)
+    monkeypatch.setenv("MATAMG_NO_GRAPH", "1")
+    h_eager = amg.Hierarchy.from_problem(prob, max_coarse=100)
+    monkeypatch.delenv("MATAMG_NO_GRAPH")
+    xe, ie = h_eager.solve(prob.b)
+    for rep in range(3):
+        xg, ig = h_graph.solve(prob.b)
+        assert ig["iterations"] == ie["iterations"]
+        assert np.array_equal(xg, xe), f"replay {rep} differs"
+        xe2, _ = h_eager.solve(prob.b * 0.5)   # eager work between replays
+        assert np.array_equal(xe2, 0.5 * xe) or np.linalg.norm(xe2 - 0.5 * xe) <= 1e-12 * np.linalg.norm(xe)
+
+
 def test_single_level_direct(amg):
     prob = poisson_box((10, 10), dirichlet="x0")
     banner("single level")
