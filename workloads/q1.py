@@ -23,8 +23,12 @@ All random draws come from numpy's SeedSequence([config_id, seed, ...]).
 
 from __future__ import annotations
 
+import ctypes
 import dataclasses
 import math
+import os
+import subprocess
+import threading
 
 import numpy as np
 
@@ -135,11 +139,97 @@ def _reference_gradients(h):
     return G
 
 
-def assemble_q1(name, shape, lengths, elem_sigma, f_elem, dirichlet_fn, meta=None):
+# ----------------------------------------------------------------------------
+# row-streamed C assembler for 3D (same operations in the same order as the
+# numpy loops below, so the results are identical)
+# ----------------------------------------------------------------------------
+class _Q1Input(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("iso", ctypes.c_int), ("kiso", ctypes.c_void_p), ("sig", ctypes.c_void_p),
+                ("G", ctypes.c_void_p), ("Gsum", ctypes.c_void_p), ("fg", ctypes.c_void_p),
+                ("dmask", ctypes.c_void_p), ("g", ctypes.c_void_p)]
+
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "q1asm.c")
+_SO = os.path.join(_HERE, "_q1asm.so")
+_lib_cache = []
+_lib_lock = threading.Lock()
+
+
+def build_fast(force=False):
+    """Compile q1asm.c into workloads/_q1asm.so (gcc, no contraction)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + f".{os.getpid()}.tmp"
+        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", _SRC, "-o", tmp], check=True)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _fast_lib():
+    with _lib_lock:
+        if not _lib_cache:
+            lib = None
+            try:
+                lib = ctypes.CDLL(build_fast())
+                lib.q1_rowptr_3d.restype = ctypes.c_int64
+                lib.q1_rowptr_3d.argtypes = [ctypes.POINTER(_Q1Input), ctypes.c_void_p]
+                lib.q1_fill_3d.restype = None
+                lib.q1_fill_3d.argtypes = [ctypes.POINTER(_Q1Input), ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+            except (OSError, subprocess.CalledProcessError, FileNotFoundError):
+                lib = None
+            _lib_cache.append(lib)
+        return _lib_cache[0]
+
+
+def _assemble_3d_fast(shape, G, vol, elem_sigma, f_elem, dmask, g, threads=None):
+    lib = _fast_lib()
+    nx, ny, nz = shape
+    n = (nx + 1) * (ny + 1) * (nz + 1)
+    sig = np.ascontiguousarray(elem_sigma, dtype=np.float64).reshape(-1, 9)
+    offdiag_zero = not np.any(sig[:, [1, 2, 3, 5, 6, 7]])
+    iso = offdiag_zero and np.array_equal(sig[:, 0], sig[:, 4]) and np.array_equal(sig[:, 0], sig[:, 8])
+    kiso = np.ascontiguousarray(sig[:, 0])
+    Gc = np.ascontiguousarray(G.reshape(9, 64))
+    Gsum = np.ascontiguousarray(sum(G[k, k] for k in range(3)).reshape(64))
+    fg = np.ascontiguousarray(np.asarray(f_elem, dtype=np.float64) * (vol / 8))
+    dm = np.ascontiguousarray(dmask.astype(np.uint8))
+    gg = np.ascontiguousarray(g, dtype=np.float64)
+    inp = _Q1Input(nx, ny, nz, int(iso), kiso.ctypes.data, sig.ctypes.data, Gc.ctypes.data, Gsum.ctypes.data,
+                   fg.ctypes.data, dm.ctypes.data, gg.ctypes.data)
+    rp = np.empty(n + 1, dtype=np.int64)
+    nnz = lib.q1_rowptr_3d(ctypes.byref(inp), rp.ctypes.data)
+    if nnz >= 2**31:
+        raise ValueError("nnz exceeds int32 indexing")
+    col = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    b = np.empty(n, dtype=np.float64)
+    threads = threads or min(8, os.cpu_count() or 1)
+    cuts = np.linspace(0, n, threads + 1).astype(np.int64)
+
+    def work(t):
+        lib.q1_fill_3d(ctypes.byref(inp), rp.ctypes.data, int(cuts[t]), int(cuts[t + 1]), col.ctypes.data,
+                       val.ctypes.data, b.ctypes.data)
+
+    if threads == 1 or n < 100000:
+        lib.q1_fill_3d(ctypes.byref(inp), rp.ctypes.data, 0, n, col.ctypes.data, val.ctypes.data, b.ctypes.data)
+    else:
+        ths = [threading.Thread(target=work, args=(t,)) for t in range(threads)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+    return rp.astype(np.int32), col, val, b
+
+
+def assemble_q1(name, shape, lengths, elem_sigma, f_elem, dirichlet_fn, meta=None, fast=True):
     """Assemble A and b on a box mesh and eliminate the Dirichlet nodes.
 
     elem_sigma: [nelem, dim, dim] SPD tensors; f_elem: [nelem] element-constant
-    source; dirichlet_fn(coords) -> (mask[n] bool, g[n] float).
+    source; dirichlet_fn(coords) -> (mask[n] bool, g[n] float).  In 3D the
+    row-streamed C assembler (q1asm.c, identical results) is used when it
+    builds, unless fast=False.
     """
     dim = len(shape)
     shape = tuple(int(s) for s in shape)
@@ -152,12 +242,28 @@ def assemble_q1(name, shape, lengths, elem_sigma, f_elem, dirichlet_fn, meta=Non
     vol = float(np.prod(h))
     nloc = 1 << dim
     nslot = 3 ** dim
+    if dim == 3 and fast and _fast_lib() is not None:
+        dmask, g = dirichlet_fn(coords)
+        dmask = np.asarray(dmask, dtype=bool)
+        g = np.where(dmask, np.asarray(g, dtype=np.float64), 0.0)
+        rowptr, col, val, b = _assemble_3d_fast(shape, G, vol, elem_sigma, f_elem, dmask, g)
+        return Problem(
+            name=name, dim=dim, shape=shape, lengths=lengths, rowptr=rowptr, col=col, val=val, b=b,
+            coords=coords, elem_nodes=elem_nodes,
+            elem_sigma=np.ascontiguousarray(elem_sigma, dtype=np.float64),
+            dirichlet=dmask, g=g, meta=dict(meta or {}),
+        )
 
-    # element arrays viewed on the element grid (z, y, x order for reshaping)
+    # element arrays viewed on the element grid (z, y, x order for reshaping);
+    # V is stored slot-major so every sliced update writes contiguous planes
     egshape = tuple(shape[::-1])
     ngshape = tuple(nn[::-1])
     sig = elem_sigma.reshape(egshape + (dim, dim))
-    V = np.zeros(ngshape + (nslot,))
+    V = np.zeros((nslot,) + ngshape)
+    offdiag_zero = all(not np.any(sig[..., p, q]) for p in range(dim) for q in range(dim) if p != q)
+    iso = offdiag_zero and all(np.array_equal(sig[..., 0, 0], sig[..., k, k]) for k in range(1, dim))
+    kiso = np.ascontiguousarray(sig[..., 0, 0]) if iso else None
+    Gsum = sum(G[k, k] for k in range(dim))
 
     def slot_of(off):
         s = 0
@@ -171,13 +277,16 @@ def assemble_q1(name, shape, lengths, elem_sigma, f_elem, dirichlet_fn, meta=Non
         for bb in range(nloc):
             bbits = [(bb >> k) & 1 for k in range(dim)]
             off = [bbits[k] - abits[k] for k in range(dim)]
-            ke = np.zeros(egshape)
-            for p in range(dim):
-                for q in range(dim):
-                    gpq = G[p, q, a, bb]
-                    if gpq != 0.0:
-                        ke += sig[..., p, q] * gpq
-            V[sl + (slot_of(off),)] += ke
+            if iso:
+                ke = kiso * Gsum[a, bb]
+            else:
+                ke = np.zeros(egshape)
+                for p in range(dim):
+                    for q in range(dim):
+                        gpq = G[p, q, a, bb]
+                        if gpq != 0.0:
+                            ke += sig[..., p, q] * gpq
+            V[(slot_of(off),) + sl] += ke
 
     # load vector: integral of phi_a over a box is vol / 2^dim
     bgrid = np.zeros(ngshape)
@@ -186,7 +295,7 @@ def assemble_q1(name, shape, lengths, elem_sigma, f_elem, dirichlet_fn, meta=Non
         abits = [(a >> k) & 1 for k in range(dim)]
         sl = tuple(slice(abits[k], abits[k] + shape[k]) for k in reversed(range(dim)))
         bgrid[sl] += fg
-    V = V.reshape(n, nslot)
+    V = np.ascontiguousarray(V.reshape(nslot, n).T)
     b = bgrid.reshape(n)
 
     # structural validity of each slot and the linear column offset
