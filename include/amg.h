@@ -100,6 +100,7 @@ typedef struct {
     double vcycle_alg_bytes;           /* algorithmic HBM bytes of one V-cycle */
     double t_setup_s;
     int64_t device_bytes;              /* device memory held by the hierarchy */
+    int64_t device_peak_bytes;         /* most device memory held at once during setup and solves */
 } amg_hierarchy_stats;
 
 /* Fill *o with the defaults listed above (dim = 3). */
@@ -178,6 +179,83 @@ amg_status amg_time_smoother(amg_hierarchy* h, int32_t level, int32_t reps, void
                              double* bytes_per_launch);
 
 void amg_free(amg_hierarchy* h);
+
+/* ------------------------------------------------------------------------
+ * Serving: a solve server that keeps many hierarchies on the device and
+ * advances all their solves together (continuous batching).
+ *
+ * Requests carry the same problem arrays as amg_setup (host memory, copied
+ * inside amg_server_submit, so the caller may free them on return), a
+ * right-hand side b, an optional initial guess x0 (NULL = zero), the
+ * tolerance and an iteration cap.  Each request is solved exactly as
+ * amg_setup + amg_pcg_solve would solve it with the server's options: same
+ * hierarchy, same kernels per row block, same CG control (section 4's
+ * preconditioned CG with one V-cycle per step), so its result does not
+ * depend on which other requests share the device with it.
+ *
+ * Admission: requests wait in arrival order; the head is admitted once its
+ * estimated device-memory peak fits in what the budget has left and fewer
+ * than max_active requests are admitted.  A request whose estimate exceeds
+ * the whole budget is refused at submission (AMG_ERR_BUDGET).  After setup
+ * the reservation shrinks to the bytes the hierarchy keeps resident.
+ *
+ * Work: setup_workers threads (own HIP streams) build hierarchies of
+ * admitted requests while an engine thread runs one preconditioned CG step
+ * of every solving request per round as shared launches, one per V-cycle
+ * step and level and per CG update, on its own stream; new requests join at
+ * the next round and finished ones leave.  All device memory comes from the
+ * current device's stream-ordered pool.
+ *
+ * Thread safety: submit, poll, result and stats may be called from any
+ * thread.  amg_server_destroy drops unfinished requests.
+ * ------------------------------------------------------------------------ */
+typedef struct amg_server amg_server;
+
+typedef struct {
+    int64_t submitted, completed, failed, rejected;
+    int64_t budget_bytes;         /* the admission budget */
+    int64_t reserved_bytes;       /* reserved now by admitted requests */
+    int64_t peak_reserved_bytes;  /* most reserved at once */
+    int32_t active;               /* admitted, unfinished requests */
+    int64_t waiting;              /* submitted, not yet admitted */
+    int64_t steps;                /* batched CG rounds run */
+    int64_t launches;             /* kernel launches issued by those rounds */
+    double mean_batch;            /* mean number of requests per round */
+    int64_t max_batch;            /* most requests in one round */
+    int64_t estimate_exceeded;    /* requests whose setup peak exceeded the estimate */
+} amg_server_stats;
+
+typedef struct {
+    double t_arrival, t_admit, t_setup_done, t_done; /* seconds since amg_server_create */
+    int64_t est_bytes;            /* reservation at admission (estimated setup peak) */
+    int64_t setup_peak_bytes;     /* measured setup peak */
+    int64_t resident_bytes;       /* kept while solving */
+    int32_t levels;
+    int32_t max_batch;            /* most requests that shared a round with it */
+    int64_t n, nnz;
+} amg_request_stats;
+
+/* opt: NULL = defaults; budget_bytes > 0; max_active in [1, 1024];
+ * setup_workers in [1, 8].  Uses the current HIP device. */
+amg_status amg_server_create(const amg_options* opt, int64_t budget_bytes, int32_t max_active, int32_t setup_workers,
+                             amg_server** out);
+/* Arrays as in amg_setup (host memory); b, x0 FP64 [n].  On success
+ * *request_id identifies the request.  Errors: INVALID_ARG, BUDGET. */
+amg_status amg_server_submit(amg_server* s, int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                             int64_t nelem, int32_t nodes_per_elem, const int32_t* elem_nodes,
+                             const double* elem_sigma, const double* coords, const double* b, const double* x0,
+                             double tol, int32_t max_iter, uint64_t* request_id);
+/* Up to cap ids of finished requests, each reported once; waits up to
+ * timeout_s seconds (0: return at once) while none is ready. */
+amg_status amg_server_poll(amg_server* s, double timeout_s, uint64_t* ids, int32_t cap, int32_t* ndone);
+/* Hands over a finished request and forgets it: x (host, n doubles, may be
+ * NULL) receives the solution, info its solve record (info->status: the
+ * request's outcome, e.g. NOT_CONVERGED or a setup error, whose message
+ * amg_last_error then returns), rs (may be NULL) its timeline and memory.
+ * Returns INVALID_ARG for an unknown, unfinished or already taken id. */
+amg_status amg_server_result(amg_server* s, uint64_t id, double* x, amg_solve_info* info, amg_request_stats* rs);
+amg_status amg_server_info(amg_server* s, amg_server_stats* out);
+void amg_server_destroy(amg_server* s);
 const char* amg_status_string(amg_status s);
 const char* amg_last_error(void);
 

@@ -10,6 +10,7 @@ from ._lib import (  # noqa: F401
     LIB_PATH,
     AmgError,
     Hierarchy,
+    Server,
     load,
     options,
 )

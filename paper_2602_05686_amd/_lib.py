@@ -29,6 +29,8 @@ EXPORTED = [
     "amg_options_default", "amg_setup", "amg_pcg_solve", "amg_vcycle", "amg_level_spmv", "amg_hierarchy_info",
     "amg_get_aggregates", "amg_get_soc_mask", "amg_get_level_csr", "amg_get_level_aux", "amg_time_smoother",
     "amg_free", "amg_status_string", "amg_last_error",
+    "amg_server_create", "amg_server_submit", "amg_server_poll", "amg_server_result", "amg_server_info",
+    "amg_server_destroy",
 ]
 
 
@@ -79,6 +81,26 @@ class HierStats(ctypes.Structure):
         ("vcycle_alg_bytes", ctypes.c_double),
         ("t_setup_s", ctypes.c_double),
         ("device_bytes", ctypes.c_int64),
+        ("device_peak_bytes", ctypes.c_int64),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+        ("rejected", ctypes.c_int64), ("budget_bytes", ctypes.c_int64), ("reserved_bytes", ctypes.c_int64),
+        ("peak_reserved_bytes", ctypes.c_int64), ("active", ctypes.c_int32), ("waiting", ctypes.c_int64),
+        ("steps", ctypes.c_int64), ("launches", ctypes.c_int64), ("mean_batch", ctypes.c_double),
+        ("max_batch", ctypes.c_int64), ("estimate_exceeded", ctypes.c_int64),
+    ]
+
+
+class RequestStats(ctypes.Structure):
+    _fields_ = [
+        ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_setup_done", ctypes.c_double),
+        ("t_done", ctypes.c_double), ("est_bytes", ctypes.c_int64), ("setup_peak_bytes", ctypes.c_int64),
+        ("resident_bytes", ctypes.c_int64), ("levels", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+        ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
     ]
 
 
@@ -108,12 +130,20 @@ def load():
     L.amg_time_smoother.argtypes = [P, i32, i32, P, ctypes.POINTER(f64), ctypes.POINTER(f64)]
     L.amg_free.argtypes = [P]
     L.amg_free.restype = None
+    L.amg_server_create.argtypes = [ctypes.POINTER(Options), i64, i32, i32, ctypes.POINTER(P)]
+    L.amg_server_submit.argtypes = [P, i64, P, P, P, i64, i32, P, P, P, P, P, f64, i32,
+                                    ctypes.POINTER(ctypes.c_uint64)]
+    L.amg_server_poll.argtypes = [P, f64, P, i32, ctypes.POINTER(i32)]
+    L.amg_server_result.argtypes = [P, ctypes.c_uint64, P, ctypes.POINTER(SolveInfo), ctypes.POINTER(RequestStats)]
+    L.amg_server_info.argtypes = [P, ctypes.POINTER(ServerStats)]
+    L.amg_server_destroy.argtypes = [P]
+    L.amg_server_destroy.restype = None
     L.amg_status_string.argtypes = [i32]
     L.amg_status_string.restype = ctypes.c_char_p
     L.amg_last_error.argtypes = []
     L.amg_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("amg_free", "amg_status_string", "amg_last_error"):
+        if name not in ("amg_free", "amg_status_string", "amg_last_error", "amg_server_destroy"):
             getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -237,7 +267,8 @@ class Hierarchy:
         return dict(levels=L, n=list(s.n[:L]), nnz=list(s.nnz[:L]), nnz_p=list(s.nnz_p[:L]),
                     mis_rounds=list(s.mis_rounds[:L]), omega=list(s.omega[:L]), lam_pf=list(s.lam_pf[:L]),
                     lam_cheb=list(s.lam_cheb[:L]), op_complexity=s.op_complexity,
-                    vcycle_alg_bytes=s.vcycle_alg_bytes, t_setup_s=s.t_setup_s, device_bytes=s.device_bytes)
+                    vcycle_alg_bytes=s.vcycle_alg_bytes, t_setup_s=s.t_setup_s, device_bytes=s.device_bytes,
+                    device_peak_bytes=s.device_peak_bytes)
 
     def aggregates(self, level):
         n = self.stats()["n"][level]
@@ -280,3 +311,85 @@ class Hierarchy:
         if which == "dirichlet":
             return out.astype(bool)
         return out
+
+
+class Server:
+    """Solve server (amg_server_*): continuous batching of many solves on one GPU.
+
+    submit() copies a problem into the server and returns its id; poll()
+    returns ids of finished requests; result() hands one over as
+    (x, info, timeline).
+    """
+
+    def __init__(self, budget_bytes=8 << 30, max_active=32, setup_workers=2, dim=3, **kw):
+        L = load()
+        self.opts = options(dim=dim, **kw)
+        s = ctypes.c_void_p()
+        check(L.amg_server_create(ctypes.byref(self.opts), int(budget_bytes), int(max_active), int(setup_workers),
+                                  ctypes.byref(s)), "amg_server_create")
+        self._s = s
+        self._n = {}
+
+    def submit(self, prob, b=None, x0=None, tol=1e-8, max_iter=1000):
+        """Submit a workloads.Problem (right-hand side prob.b unless b is given)."""
+        L = load()
+        rp = np.ascontiguousarray(prob.rowptr, dtype=np.int32)
+        ci = np.ascontiguousarray(prob.col, dtype=np.int32)
+        va = np.ascontiguousarray(prob.val, dtype=np.float64)
+        en = np.ascontiguousarray(prob.elem_nodes, dtype=np.int32)
+        es = np.ascontiguousarray(prob.elem_sigma, dtype=np.float64)
+        xc = np.ascontiguousarray(prob.coords, dtype=np.float64)
+        bb = np.ascontiguousarray(prob.b if b is None else b, dtype=np.float64)
+        x0p = None
+        if x0 is not None:
+            x0a = np.ascontiguousarray(x0, dtype=np.float64)
+            x0p = _hp(x0a)
+        n = rp.shape[0] - 1
+        rid = ctypes.c_uint64()
+        code = L.amg_server_submit(self._s, n, _hp(rp), _hp(ci), _hp(va), en.shape[0], en.shape[1], _hp(en), _hp(es),
+                                   _hp(xc), _hp(bb), x0p, float(tol), int(max_iter), ctypes.byref(rid))
+        check(code, "amg_server_submit")
+        self._n[rid.value] = n
+        return rid.value
+
+    def poll(self, timeout_s=0.0, cap=256):
+        ids = (ctypes.c_uint64 * cap)()
+        nd = ctypes.c_int32()
+        check(load().amg_server_poll(self._s, float(timeout_s), ids, cap, ctypes.byref(nd)), "amg_server_poll")
+        return [int(ids[i]) for i in range(nd.value)]
+
+    def result(self, rid):
+        n = self._n.pop(rid)
+        x = np.empty(n)
+        info = SolveInfo()
+        rs = RequestStats()
+        L = load()
+        check(L.amg_server_result(self._s, ctypes.c_uint64(rid), _hp(x), ctypes.byref(info), ctypes.byref(rs)),
+              "amg_server_result")
+        detail = L.amg_last_error().decode(errors="replace") if info.status != AMG_OK else ""
+        out = dict(status=STATUS[info.status], iterations=info.iterations, rel_res=info.rel_res_true,
+                   t_solve_s=info.t_solve_s, error=detail)
+        tl = {f: getattr(rs, f) for f, _ in RequestStats._fields_}
+        return x, out, tl
+
+    def stats(self):
+        s = ServerStats()
+        check(load().amg_server_info(self._s, ctypes.byref(s)), "amg_server_info")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_s", None) is not None and self._s.value:
+            load().amg_server_destroy(self._s)
+        self._s = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

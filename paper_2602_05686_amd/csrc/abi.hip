@@ -3,14 +3,21 @@
 #include <string>
 
 #include "hierarchy.h"
+#include "server.h"
 
 struct amg_hierarchy {
     std::unique_ptr<matamg::Hierarchy> h;
 };
 
+struct amg_server {
+    std::unique_ptr<matamg::Server> s;
+};
+
 namespace matamg {
 
 thread_local std::string g_last_error;
+thread_local hipStream_t g_alloc_stream = nullptr;
+hipStream_t& alloc_stream() { return g_alloc_stream; }
 
 [[noreturn]] void fail(amg_status code, const std::string& msg) { throw Error{code, msg}; }
 
@@ -177,6 +184,7 @@ amg_status amg_hierarchy_info(const amg_hierarchy* hh, amg_hierarchy_stats* st) 
         st->vcycle_alg_bytes = h.vcycle_alg_bytes();
         st->t_setup_s = h.t_setup;
         st->device_bytes = h.mem.bytes;
+        st->device_peak_bytes = h.mem.peak;
         return AMG_OK;
     });
 }
@@ -253,6 +261,108 @@ amg_status amg_time_smoother(amg_hierarchy* hh, int32_t level, int32_t reps, voi
 }
 
 void amg_free(amg_hierarchy* h) { delete h; }
+
+// ------------------------------------------------------------------ serving
+amg_status amg_server_create(const amg_options* opt, int64_t budget_bytes, int32_t max_active, int32_t setup_workers,
+                             amg_server** out) {
+    return guarded([&]() -> amg_status {
+        if (!out) fail(AMG_ERR_INVALID_ARG, "out is null");
+        *out = nullptr;
+        amg_options o;
+        if (opt) o = *opt;
+        else amg_options_default(&o);
+        check_options(o);
+        if (budget_bytes <= 0) fail(AMG_ERR_INVALID_ARG, "budget must be positive");
+        if (max_active < 1 || max_active > 1024) fail(AMG_ERR_INVALID_ARG, "max_active must lie in [1, 1024]");
+        if (setup_workers < 1 || setup_workers > 8) fail(AMG_ERR_INVALID_ARG, "setup_workers must lie in [1, 8]");
+        auto srv = std::make_unique<Server>(o, budget_bytes, max_active, setup_workers);
+        *out = new amg_server{std::move(srv)};
+        return AMG_OK;
+    });
+}
+
+amg_status amg_server_submit(amg_server* s, int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                             int64_t nelem, int32_t nodes_per_elem, const int32_t* elem_nodes,
+                             const double* elem_sigma, const double* coords, const double* b, const double* x0,
+                             double tol, int32_t max_iter, uint64_t* request_id) {
+    return guarded([&]() -> amg_status {
+        if (!s || !s->s) fail(AMG_ERR_INVALID_ARG, "null server");
+        return s->s->submit(n, rowptr, col, val, nelem, nodes_per_elem, elem_nodes, elem_sigma, coords, b, x0, tol,
+                            max_iter, request_id);
+    });
+}
+
+amg_status amg_server_poll(amg_server* s, double timeout_s, uint64_t* ids, int32_t cap, int32_t* ndone) {
+    return guarded([&]() -> amg_status {
+        if (!s || !s->s || !ndone || cap < 0 || (cap > 0 && !ids)) fail(AMG_ERR_INVALID_ARG, "bad poll arguments");
+        *ndone = s->s->poll(ids, cap, timeout_s);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_server_result(amg_server* s, uint64_t id, double* x, amg_solve_info* info, amg_request_stats* rs) {
+    return guarded([&]() -> amg_status {
+        if (!s || !s->s) fail(AMG_ERR_INVALID_ARG, "null server");
+        std::unique_ptr<Request> r = s->s->take(id);
+        if (!r) fail(AMG_ERR_INVALID_ARG, "request " + std::to_string(id) + " is unknown, unfinished or already taken");
+        if (x && !r->x.empty()) std::memcpy(x, r->x.data(), sizeof(double) * r->x.size());
+        if (info) {
+            info->iterations = r->iters;
+            info->rel_res_true = r->rel_true;
+            info->t_solve_s = r->t_done - r->t_setup_done;
+            info->status = r->status;
+        }
+        if (rs) {
+            std::memset(rs, 0, sizeof(*rs));
+            rs->t_arrival = r->t_arrival;
+            rs->t_admit = r->t_admit;
+            rs->t_setup_done = r->t_setup_done;
+            rs->t_done = r->t_done;
+            rs->est_bytes = r->est;
+            rs->setup_peak_bytes = r->setup_peak;
+            rs->resident_bytes = r->resident;
+            rs->levels = r->levels;
+            rs->max_batch = r->max_batch;
+            rs->n = r->n;
+            rs->nnz = r->nnz;
+        }
+        if (r->status != AMG_OK && !r->error.empty()) g_last_error = r->error;
+        return AMG_OK;
+    });
+}
+
+amg_status amg_server_info(amg_server* s, amg_server_stats* out) {
+    return guarded([&]() -> amg_status {
+        if (!s || !s->s || !out) fail(AMG_ERR_INVALID_ARG, "bad stats arguments");
+        ServerStats st;
+        int active = 0;
+        int64_t budget = 0, used = 0, peak = 0, waiting = 0;
+        s->s->stats(&st, &budget, &used, &peak, &active, &waiting);
+        std::memset(out, 0, sizeof(*out));
+        out->submitted = st.submitted;
+        out->completed = st.completed;
+        out->failed = st.failed;
+        out->rejected = st.rejected;
+        out->budget_bytes = budget;
+        out->reserved_bytes = used;
+        out->peak_reserved_bytes = peak;
+        out->active = active;
+        out->waiting = waiting;
+        out->steps = st.steps;
+        out->launches = st.launches;
+        out->mean_batch = st.steps > 0 ? (double)st.batch_sum / (double)st.steps : 0.0;
+        out->max_batch = st.max_batch;
+        out->estimate_exceeded = st.estimate_exceeded;
+        return AMG_OK;
+    });
+}
+
+void amg_server_destroy(amg_server* s) {
+    try {
+        delete s;
+    } catch (...) {
+    }
+}
 
 const char* amg_status_string(amg_status s) {
     switch (s) {

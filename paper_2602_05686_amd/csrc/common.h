@@ -45,6 +45,20 @@ struct MemCounter {
     }
 };
 
+// Stream-ordered allocation.  Threads that run many hierarchies side by side
+// (the solve server) set a per-thread stream; device buffers created and
+// released on that thread then come from the device's memory pool
+// (hipMallocAsync / hipFreeAsync on that stream) instead of hipMalloc /
+// hipFree, whose release waits for every stream of the device.
+hipStream_t& alloc_stream();
+struct AllocStreamScope {
+    hipStream_t prev;
+    explicit AllocStreamScope(hipStream_t s) : prev(alloc_stream()) { alloc_stream() = s; }
+    ~AllocStreamScope() { alloc_stream() = prev; }
+    AllocStreamScope(const AllocStreamScope&) = delete;
+    AllocStreamScope& operator=(const AllocStreamScope&) = delete;
+};
+
 template <typename T>
 class DBuf {
   public:
@@ -66,7 +80,9 @@ class DBuf {
         n_ = n;
         mc_ = mc;
         if (n == 0) return;
-        hipError_t e = hipMalloc(&p_, n * sizeof(T));
+        hipStream_t s = alloc_stream();
+        pooled_ = s != nullptr;
+        hipError_t e = pooled_ ? hipMallocAsync((void**)&p_, n * sizeof(T), s) : hipMalloc(&p_, n * sizeof(T));
         if (e != hipSuccess) {
             p_ = nullptr;
             n_ = 0;
@@ -76,7 +92,9 @@ class DBuf {
     }
     void release() {
         if (p_) {
-            (void)hipFree(p_);
+            hipStream_t s = alloc_stream();
+            if (pooled_ && s) (void)hipFreeAsync(p_, s);
+            else (void)hipFree(p_);
             if (mc_) mc_->add(-(int64_t)(n_ * sizeof(T)));
         }
         p_ = nullptr;
@@ -91,10 +109,12 @@ class DBuf {
         std::swap(p_, o.p_);
         std::swap(n_, o.n_);
         std::swap(mc_, o.mc_);
+        std::swap(pooled_, o.pooled_);
     }
     T* p_ = nullptr;
     size_t n_ = 0;
     MemCounter* mc_ = nullptr;
+    bool pooled_ = false;
 };
 
 // CSR matrix resident on the device

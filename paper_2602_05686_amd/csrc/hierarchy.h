@@ -54,6 +54,8 @@ struct Hierarchy {
     double vcycle_alg_bytes() const;
     double time_smoother(int level, int reps, hipStream_t s, double* bytes_per_launch);
     hipGraphExec_t step_graph(int cur);
+    void ensure_solve_resources();
+    void release_setup_data();
 };
 
 // device scalar slots

@@ -195,6 +195,28 @@ double Hierarchy::time_smoother(int level, int reps, hipStream_t s, double* byte
     return ms_total / reps;
 }
 
+// the solve's own stream, ordering event and pinned scalar mirror, created
+// on the first solve (hierarchies driven by the solve server never need them)
+void Hierarchy::ensure_solve_resources() {
+    if (!hscal) MATAMG_HIP(hipHostMalloc((void**)&hscal, sizeof(double) * S_NSCAL, hipHostMallocDefault));
+    if (!ws) MATAMG_HIP(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
+    if (!ev_in) MATAMG_HIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+}
+
+// drop what only the parity getters read (strength values, drop masks,
+// aggregates, coordinates and tensors); the V-cycle and CG do not use them
+void Hierarchy::release_setup_data() {
+    for (int l = 0; l < nlev; ++l) {
+        Level& L = lev[l];
+        L.S.release();
+        L.mask.release();
+        L.agg.release();
+        L.x.release();
+        L.sig.release();
+        L.dir.release();
+    }
+}
+
 DotTarget Hierarchy::dt(int slot) const { return DotTarget{partial.get(), counter.get(), scal.get() + slot}; }
 
 std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const int* col, const double* val,
@@ -215,15 +237,12 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
     h.counter.alloc(1, mc);
     MATAMG_HIP(hipMemsetAsync(h.counter.get(), 0, sizeof(unsigned), s));
     MATAMG_HIP(hipMemsetAsync(h.scal.get(), 0, sizeof(double) * S_NSCAL, s));
-    MATAMG_HIP(hipHostMalloc((void**)&h.hscal, sizeof(double) * S_NSCAL, hipHostMallocDefault));
-    MATAMG_HIP(hipStreamCreateWithFlags(&h.ws, hipStreamNonBlocking));
     {
         // MATAMG_NO_GRAPH=1 runs every CG step eagerly (used to check the
         // captured graphs against direct launches)
         const char* ng = std::getenv("MATAMG_NO_GRAPH");
         h.use_graphs = !(ng && ng[0] == '1');
     }
-    MATAMG_HIP(hipEventCreateWithFlags(&h.ev_in, hipEventDisableTiming));
     DBuf<int> flag(1, mc);
     MATAMG_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int), s));
 
@@ -574,6 +593,7 @@ amg_status pcg_solve(Hierarchy& h, const double* b_in, double* x_io, double tol,
     const double t0 = now_s();
     const DCsr& A = h.lev[0].A;
     const int n = A.n;
+    h.ensure_solve_resources();
     hipStream_t ws = h.ws;
     // order after the caller's earlier work on its stream
     MATAMG_HIP(hipEventRecord(h.ev_in, s));

@@ -10,8 +10,7 @@
 // and applies the epilogue.  A long row is reduced by the whole block: strided
 // partial sums and a fixed tree.  Every sum therefore has a fixed
 // order for a given matrix: results are bitwise reproducible run to run.
-#include "device_util.h"
-#include "kernels.h"
+#include "solve_device.h"
 
 namespace matamg {
 
@@ -106,11 +105,6 @@ void exclusive_scan(const int* in, int* out, int64_t n, int* tmp, hipStream_t s)
 
 // ====================================================================== dot
 namespace {
-inline int vec_grid(int64_t n) {
-    int g = ceil_div(n > 0 ? n : 1, kBlock);
-    return g < 2048 ? g : 2048;
-}
-
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dot(const T* a, const T* b, int64_t n, DotTarget dt) {
     __shared__ double sh[kBlock / 64];
@@ -121,17 +115,14 @@ __global__ __launch_bounds__(kBlock) void k_dot(const T* a, const T* b, int64_t 
     store_partial(t, dt);
 }
 
-__global__ __launch_bounds__(kBlock) void k_finish_sum(int nb, const double* partial, double* result) {
+__global__ __launch_bounds__(kBlock) void k_finish_sum(FinishArgs a) {
     __shared__ double sh[kBlock / 64];
-    double v = 0.0;
-    for (int i = threadIdx.x; i < nb; i += kBlock) v += partial[i];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) *result = v;
+    finish_body(a, sh);
 }
 }  // namespace
 
 void finish_sum(const DotTarget& dt, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(kBlock), 0, s, nblocks, (const double*)dt.partial, dt.result);
+    hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(kBlock), 0, s, FinishArgs{nblocks, dt.partial, dt.result});
     MATAMG_LAUNCH_CHECK();
 }
 
@@ -178,122 +169,12 @@ std::vector<int> stream_blocks(const int* rp, int n, int group) {
 }
 
 namespace {
-enum Mode { M_PLAIN = 0, M_RESID = 1, M_ADD = 2, M_SMOOTH = 3, M_DOTPQ = 4, M_RESNORM = 5, M_SCALENORM = 6 };
-
-template <typename T>
-struct SArgs {
-    const int* rowptr;
-    const int* col;
-    const T* val;
-    const int* blk;
-    const T* x;        // gathered operand
-    const T* b;        // right-hand side (RESID, SMOOTH, RESNORM)
-    const T* yin;      // ADD: base vector; SMOOTH: iterate at the row
-    const T* dinv;     // SMOOTH: inverse diagonal; SCALENORM: row scale
-    T* d;              // SMOOTH: direction (in/out)
-    T* y;              // output
-    double* y64;       // SMOOTH: FP64 output instead of y
-    const double* dotvec;  // SMOOTH: fused dot partner
-    T c1, c2;
-    DotTarget dt;
-};
-
-template <typename T, int MODE, bool HAS_DOT>
-__device__ __forceinline__ double epilogue(const SArgs<T>& a, int r, T s) {
-    double dp = 0.0;
-    if constexpr (MODE == M_PLAIN) {
-        a.y[r] = s;
-    } else if constexpr (MODE == M_RESID) {
-        a.y[r] = a.b[r] - s;
-    } else if constexpr (MODE == M_ADD) {
-        a.y[r] = a.yin[r] + s;
-    } else if constexpr (MODE == M_SMOOTH) {
-        T res = a.b[r] - s;
-        T dn = a.c1 * a.d[r] + a.c2 * (a.dinv[r] * res);
-        a.d[r] = dn;
-        T xn = a.yin[r] + dn;
-        if (a.y64) a.y64[r] = (double)xn;
-        else a.y[r] = xn;
-        if constexpr (HAS_DOT) dp = (double)xn * a.dotvec[r];
-    } else if constexpr (MODE == M_DOTPQ) {
-        a.y[r] = s;
-        dp = (double)a.x[r] * (double)s;
-    } else if constexpr (MODE == M_RESNORM) {
-        T v = a.b[r] - s;
-        a.y[r] = v;
-        dp = (double)v * (double)v;
-    } else if constexpr (MODE == M_SCALENORM) {
-        T v = a.dinv[r] * s;
-        a.y[r] = v;
-        dp = (double)v * (double)v;
-    }
-    return dp;
-}
-
-constexpr int kPerThread = kStreamCap / kBlock;
-
 template <typename T, int MODE, bool HAS_DOT, int G>
 __global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a, int nblk) {
-    __shared__ T prod[kStreamCap];
-    __shared__ double sh[kBlock / 64];
-    __shared__ T shr[kBlock / 64];
+    __shared__ StreamShared<T> S;
     const int bid = xcd_block(nblk);
     if (bid >= nblk) return;
-    const int r0 = a.blk[bid], r1 = a.blk[bid + 1];
-    const int k0 = a.rowptr[r0], k1 = a.rowptr[r1];
-    const int cnt = k1 - k0;
-    double dp = 0.0;
-    if (!(r1 - r0 == 1 && cnt > long_row_limit(G))) {
-        // issue every load of this thread's share before using any of them
-        int c[kPerThread];
-        T v[kPerThread];
-#pragma unroll
-        for (int u = 0; u < kPerThread; ++u) {
-            const int t = (int)threadIdx.x + u * kBlock;
-            if (t < cnt) {
-                c[u] = __builtin_nontemporal_load(a.col + k0 + t);
-                v[u] = __builtin_nontemporal_load(a.val + k0 + t);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kPerThread; ++u) {
-            const int t = (int)threadIdx.x + u * kBlock;
-            if (t < cnt) prod[t] = v[u] * a.x[c[u]];
-        }
-        __syncthreads();
-        // G threads per row: strided partial sums, then a fixed shuffle tree
-        const int gl = (int)threadIdx.x % G;
-        const int r = r0 + (int)threadIdx.x / G;
-        T s = 0;
-        if (r < r1) {
-            const int s0 = a.rowptr[r] - k0, s1 = a.rowptr[r + 1] - k0;
-            for (int k = s0 + gl; k < s1; k += G) s += prod[k];
-        }
-        if constexpr (G > 1) {
-            for (int off = G / 2; off > 0; off >>= 1) s += __shfl_down(s, off, G);
-        }
-        if (gl == 0 && r < r1) dp = epilogue<T, MODE, HAS_DOT>(a, r, s);
-    } else {
-        // one long row (a block of its own): strided partial sums, fixed tree
-        T s = 0;
-        for (int t = threadIdx.x; t < cnt; t += kBlock) {
-            const int k = k0 + t;
-            s += a.val[k] * a.x[a.col[k]];
-        }
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (lane == 0) shr[w] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            T t = shr[0];
-            for (int i = 1; i < kBlock / 64; ++i) t += shr[i];
-            dp = epilogue<T, MODE, HAS_DOT>(a, r0, t);
-        }
-    }
-    if constexpr (HAS_DOT) {
-        double t = block_sum(dp, sh);
-        if (threadIdx.x == 0) a.dt.partial[bid] = t;
-    }
+    stream_block<T, MODE, HAS_DOT, G>(a, bid, S);
 }
 
 template <typename T, int MODE, bool HAS_DOT>
@@ -397,20 +278,8 @@ INST(float)
 // ================================================================= vectors
 namespace {
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_smooth_first(int64_t n, const double* b64, T* b, const T* dinv, T c2,
-                                                         T* d, T* x) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        T bi;
-        if (b64) {
-            bi = (T)b64[i];
-            b[i] = bi;
-        } else {
-            bi = b[i];
-        }
-        T di = c2 * (dinv[i] * bi);
-        d[i] = di;
-        x[i] = di;
-    }
+__global__ __launch_bounds__(kBlock) void k_smooth_first(SmoothFirstArgs<T> a) {
+    smooth_first_body(a, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_scale_inv_norm(int64_t n, const double* nrm2, const double* in,
@@ -420,30 +289,13 @@ __global__ __launch_bounds__(kBlock) void k_scale_inv_norm(int64_t n, const doub
         out[i] = in[i] * inv;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, double* x, double* r, const double* p,
-                                                      const double* q, const double* rz, const double* pq,
-                                                      DotTarget dt) {
+__global__ __launch_bounds__(kBlock) void k_cg_update(CgUpdArgs a) {
     __shared__ double sh[kBlock / 64];
-    // a non-positive or non-finite curvature is a breakdown: leave x and r
-    // unchanged so the caller keeps the last iterate
-    const double pqv = *pq, rzv = *rz;
-    const double alpha = (pqv > 0.0 && isfinite(pqv) && isfinite(rzv)) ? rzv / pqv : 0.0;
-    double v = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        x[i] = x[i] + alpha * p[i];
-        double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        v += ri * ri;
-    }
-    double t = block_sum(v, sh);
-    store_partial(t, dt);
+    cg_update_body(a, blockIdx.x, gridDim.x, sh);
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_direction(int64_t n, double* p, const double* z,
-                                                         const double* rz_new, const double* rz_old) {
-    const double beta = rz_old ? (*rz_new / *rz_old) : 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        p[i] = rz_old ? z[i] + beta * p[i] : z[i];
+__global__ __launch_bounds__(kBlock) void k_cg_direction(CgDirArgs a) {
+    cg_direction_body(a, blockIdx.x, gridDim.x);
 }
 
 template <typename A, typename B>
@@ -471,7 +323,8 @@ __global__ __launch_bounds__(kBlock) void k_seeded_uniform(int64_t n, uint64_t k
 template <typename T>
 void smooth_first(int64_t n, const double* b64, T* b, const T* dinv, T c2, T* d, T* x, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_smooth_first<T>, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, b64, b, dinv, c2, d, x);
+    hipLaunchKernelGGL(k_smooth_first<T>, dim3(vec_grid(n)), dim3(kBlock), 0, s,
+                       SmoothFirstArgs<T>{n, b64, b, dinv, c2, d, x});
     MATAMG_LAUNCH_CHECK();
 }
 template void smooth_first<double>(int64_t, const double*, double*, const double*, double, double*, double*,
@@ -488,7 +341,7 @@ void scale_by_inv_norm(int64_t n, const double* nrm2, const double* in, double* 
 void cg_update(int64_t n, double* x, double* r, const double* p, const double* q, const double* rz,
                const double* pq, DotTarget rr, hipStream_t s) {
     const int g = vec_grid(n);
-    hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, n, x, r, p, q, rz, pq, rr);
+    hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kBlock), 0, s, CgUpdArgs{n, x, r, p, q, rz, pq, rr.partial});
     MATAMG_LAUNCH_CHECK();
     finish_sum(rr, g, s);
 }
@@ -496,7 +349,7 @@ void cg_update(int64_t n, double* x, double* r, const double* p, const double* q
 void cg_direction(int64_t n, double* p, const double* z, const double* rz_new, const double* rz_old,
                   hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_cg_direction, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, p, z, rz_new, rz_old);
+    hipLaunchKernelGGL(k_cg_direction, dim3(vec_grid(n)), dim3(kBlock), 0, s, CgDirArgs{n, p, z, rz_new, rz_old});
     MATAMG_LAUNCH_CHECK();
 }
 
@@ -517,24 +370,16 @@ void fill_seeded_uniform(int64_t n, uint64_t key, double* v, hipStream_t s) {
 
 // =================================================================== dense
 namespace {
-// one wavefront per row of the dense inverse; FP64 accumulation
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const double* M, const T* in, T* out) {
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (row >= n) return;
-    const double* m = M + (size_t)row * n;
-    double s = 0.0;
-    for (int j = lane; j < n; j += 64) s += m[j] * (double)in[j];
-    s = wave_sum(s);
-    if (lane == 0) out[row] = (T)s;
+__global__ __launch_bounds__(kBlock) void k_dense_gemv(GemvArgs<T> a) {
+    gemv_body(a, blockIdx.x);
 }
 }  // namespace
 
 template <typename T>
 void dense_gemv(int n, const double* M, const T* in, T* out, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_dense_gemv<T>, dim3(ceil_div(n, kBlock / 64)), dim3(kBlock), 0, s, n, M, in, out);
+    hipLaunchKernelGGL(k_dense_gemv<T>, dim3(gemv_grid(n)), dim3(kBlock), 0, s, GemvArgs<T>{n, M, in, out});
     MATAMG_LAUNCH_CHECK();
 }
 template void dense_gemv<double>(int, const double*, const double*, double*, hipStream_t);

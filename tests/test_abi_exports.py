@@ -64,3 +64,48 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(L, "LIB_PATH", os.path.join(ROOT, "no_such_library.so"))
     with pytest.raises(RuntimeError, match="not built"):
         L.load()
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """Field offsets and sizes of the binding's structs equal the C layout."""
+    import shutil
+    import subprocess
+
+    from paper_2602_05686_amd import _lib
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {
+        "amg_options": _lib.Options, "amg_solve_info": _lib.SolveInfo, "amg_hierarchy_stats": _lib.HierStats,
+        "amg_server_stats": _lib.ServerStats, "amg_request_stats": _lib.RequestStats,
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "amg.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_server_argument_checks_precede_device_work(lib):
+    import paper_2602_05686_amd as amg
+
+    o = amg.options(dim=3)
+    s = ctypes.c_void_p()
+    assert lib.amg_server_create(ctypes.byref(o), 0, 4, 1, ctypes.byref(s)) == 1 and s.value is None
+    assert b"budget" in lib.amg_last_error()
+    assert lib.amg_server_create(ctypes.byref(o), 1 << 30, 0, 1, ctypes.byref(s)) == 1
+    assert lib.amg_server_create(ctypes.byref(o), 1 << 30, 4, 0, ctypes.byref(s)) == 1
+    nd = ctypes.c_int32()
+    assert lib.amg_server_poll(None, 0.0, None, 0, ctypes.byref(nd)) == 1
+    lib.amg_server_destroy(None)
