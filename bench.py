@@ -13,7 +13,10 @@ residual of 1e-8.  value = DOF * steps / time.  The JSON line also carries
 solve-only throughput, the FP32-hierarchy form against the FP64 form, the
 V-cycle's algorithmic HBM bandwidth, the roofline of the dominant kernel
 (the finest level's fused Chebyshev SpMV: back-to-back launches between
-HIP events on its stream) and the CPU oracle timed on a bounded sample of the same recipe.
+HIP events on its stream), the serving stream (256 requests at 20/s,
+n log-uniform in [32, 128], layered or anisotropic, FP32-hierarchy form,
+8 GiB budget: p50 / p99 latency and solves/s) and the CPU oracle timed on a
+bounded sample of the same recipe.
 """
 
 import argparse
@@ -64,6 +67,112 @@ def cpu_baseline(prob, iterations, sample_iters):
                 host_cpu=cpu_model(), host_threads=os.cpu_count())
 
 
+def run_serving(args, amg, log):
+    """Serving stream: Poisson arrivals at `rate`/s of `num` requests, mesh n^3
+    with n log-uniform in [32, 128], layered (20 repeats, 10:1) or rotated
+    anisotropic, per-request seeds, FP32-hierarchy form, tol 1e-8, admitted
+    under an HBM budget.  The requests are generated before the replay; each
+    is submitted at its arrival time and latency is t_done - t_arrival as the
+    server clocks them."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
+    from workloads import problem_from_request, serving_stream
+
+    reqs = serving_stream(num=args.serve_num, rate=args.serve_rate)
+    log(f"serving: generating {len(reqs)} requests")
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        probs = list(ex.map(problem_from_request, reqs))
+    t_gen = time.perf_counter() - t0
+    dofs = [p.n for p in probs]
+    log(f"serving: generated in {t_gen:.1f}s, {sum(dofs)} DOF in total")
+    # requests re-solved alone afterwards: the smallest of each kind
+    check_ids = []
+    for kind in ("layered", "aniso"):
+        ks = [i for i, r in enumerate(reqs) if r["kind"] == kind]
+        if ks:
+            check_ids.append(min(ks, key=lambda i: reqs[i]["n"]))
+    keep = {i: probs[i] for i in check_ids}
+    srv = amg.Server(budget_bytes=int(args.serve_budget_gib * (1 << 30)), max_active=args.serve_active,
+                     setup_workers=2, precision="fp32")
+    # warm-up request (loads the code objects), outside the replay
+    w = srv.submit(probs[check_ids[0]], max_iter=args.serve_max_iter)
+    while not srv.poll(timeout_s=5.0):
+        pass
+    srv.result(w)
+    results = {}
+    done = threading.Event()
+    id_of = {}
+
+    def collect():
+        while len(results) < len(probs):
+            for rid in srv.poll(timeout_s=1.0):
+                x, info, tl = srv.result(rid)
+                i = id_of[rid]
+                results[i] = (x if i in keep else None, info, tl)
+                if len(results) % 32 == 0:
+                    log(f"serving: {len(results)} of {len(probs)} done")
+        done.set()
+
+    th = threading.Thread(target=collect, daemon=True)
+    log("serving: replaying the arrival stream")
+    lateness = []
+    t_start = time.perf_counter()
+    th.start()
+    for i, r in enumerate(reqs):
+        wait = t_start + r["t_arrival"] - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        lateness.append(time.perf_counter() - t_start - r["t_arrival"])
+        rid = srv.submit(probs[i], max_iter=args.serve_max_iter)
+        id_of[rid] = i
+        probs[i] = None  # the server holds its own copy
+    done.wait()
+    t_wall = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    lat = np.array([results[i][2]["t_done"] - results[i][2]["t_arrival"] for i in range(len(reqs))])
+    t_first = min(results[i][2]["t_arrival"] for i in range(len(reqs)))
+    t_last = max(results[i][2]["t_done"] for i in range(len(reqs)))
+    iters = np.array([results[i][1]["iterations"] for i in range(len(reqs))])
+    status = {}
+    for i in range(len(reqs)):
+        s = results[i][1]["status"]
+        status[s] = status.get(s, 0) + 1
+    conv = [i for i in range(len(reqs)) if results[i][1]["status"] == "OK"]
+    # the same requests alone: the one-hierarchy solver, same options
+    alone = []
+    for i in check_ids:
+        p = keep[i]
+        h = amg.Hierarchy.from_problem(p, precision="fp32")
+        xa, ia = h.solve(p.b, max_iter=args.serve_max_iter, raise_on_error=False)
+        h.close()
+        xm = results[i][0]
+        alone.append(dict(request=i, n=p.n, kind=reqs[i]["kind"], bitwise_equal=bool(np.array_equal(xa, xm)),
+                          iterations_mix=results[i][1]["iterations"], iterations_alone=ia["iterations"],
+                          shared_rounds_with=results[i][2]["max_batch"] - 1))
+    makespan = t_last - t_first
+    out = {
+        "requests": len(reqs), "rate_per_s": args.serve_rate, "budget_GiB": args.serve_budget_gib,
+        "max_active": args.serve_active, "precision": "fp32-hierarchy", "tol": 1e-8, "max_iter": args.serve_max_iter,
+        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_latency_s": float(lat.mean()), "max_latency_s": float(lat.max()),
+        "solves_per_s": len(reqs) / makespan, "makespan_s": makespan, "served_dof_per_s": sum(dofs) / makespan,
+        "status_counts": status, "converged": len(conv),
+        "iterations": {"median": float(np.median(iters)), "p90": float(np.percentile(iters, 90)),
+                       "max": int(iters.max())},
+        "mean_batch": st["mean_batch"], "max_batch": st["max_batch"], "rounds": st["steps"],
+        "launches": st["launches"], "peak_reserved_GiB": st["peak_reserved_bytes"] / 2**30,
+        "estimate_exceeded": st["estimate_exceeded"], "failed": st["failed"],
+        "submit_lateness_max_s": float(max(lateness)), "generation_s": t_gen, "replay_wall_s": t_wall,
+        "alone_vs_mix": alone,
+    }
+    log(f"serving: p50 {out['p50_latency_s']:.2f}s p99 {out['p99_latency_s']:.2f}s, "
+        f"{out['solves_per_s']:.2f} solves/s, statuses {status}, mean batch {st['mean_batch']:.1f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +186,13 @@ def main():
     ap.add_argument("--profile-kernels", action="store_true",
                     help="one setup, a few V-cycles and a 1 GiB device copy (for counter collection), no JSON")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving stream (its JSON object)")
+    ap.add_argument("--serve-num", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0)
+    ap.add_argument("--serve-active", type=int, default=32)
+    ap.add_argument("--serve-max-iter", type=int, default=1000)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -95,6 +211,10 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.serving_only:
+        print(json.dumps(run_serving(args, amg, log)), flush=True)
+        return
 
     log(f"generating layered stack {args.n}^3, {args.repeats} repeats, {args.stretch:g}:1")
     prob = layered_stack_3d(n=args.n, repeats=args.repeats, stretch=args.stretch)
@@ -196,6 +316,12 @@ def main():
                     rel_err_vs_closed_form=float(np.linalg.norm(x32 - exact) / np.linalg.norm(exact)))
         log(f"fp32 form: solve {info32['t_solve_s'] * 1e3:.1f} ms, iters {info32['iterations']}")
 
+    serving = None
+    if not args.no_serving:
+        del d
+        torch.cuda.empty_cache()
+        serving = run_serving(args, amg, log)
+
     cpu = None
     if args.cpu_sample > 0:
         log(f"oracle sample: setup + {args.cpu_sample} PCG iterations")
@@ -232,6 +358,7 @@ def main():
                      "traffic": None, "avg_launch_us": avg_ms * 1e3, "launches": args.vcycles,
                      "alg_bytes_per_launch": kt["bytes_per_launch"]},
         "fp32_form": fp32,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
