@@ -1,4 +1,5 @@
 // extern "C" boundary: argument checks, error translation, data accessors.
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -16,8 +17,20 @@ struct amg_server {
 namespace matamg {
 
 thread_local std::string g_last_error;
-thread_local hipStream_t g_alloc_stream = nullptr;
-hipStream_t& alloc_stream() { return g_alloc_stream; }
+thread_local AllocMode g_alloc_mode;
+AllocMode& alloc_mode() { return g_alloc_mode; }
+
+bool pool_enabled() {
+    const char* e = std::getenv("MATAMG_NO_POOL");
+    return !(e && e[0] == '1');
+}
+
+void keep_pool_memory(int device) {
+    hipMemPool_t pool = nullptr;
+    MATAMG_HIP(hipDeviceGetDefaultMemPool(&pool, device));
+    uint64_t keep = UINT64_MAX;
+    MATAMG_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+}
 
 [[noreturn]] void fail(amg_status code, const std::string& msg) { throw Error{code, msg}; }
 
@@ -260,7 +273,16 @@ amg_status amg_time_smoother(amg_hierarchy* hh, int32_t level, int32_t reps, voi
     });
 }
 
-void amg_free(amg_hierarchy* h) { delete h; }
+void amg_free(amg_hierarchy* h) {
+    if (!h) return;
+    // pooled buffers are released on the null stream: let every stream of
+    // the device finish with them first
+    (void)hipDeviceSynchronize();
+    try {
+        delete h;
+    } catch (...) {
+    }
+}
 
 // ------------------------------------------------------------------ serving
 amg_status amg_server_create(const amg_options* opt, int64_t budget_bytes, int32_t max_active, int32_t setup_workers,

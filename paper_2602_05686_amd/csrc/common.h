@@ -45,19 +45,30 @@ struct MemCounter {
     }
 };
 
-// Stream-ordered allocation.  Threads that run many hierarchies side by side
-// (the solve server) set a per-thread stream; device buffers created and
-// released on that thread then come from the device's memory pool
-// (hipMallocAsync / hipFreeAsync on that stream) instead of hipMalloc /
-// hipFree, whose release waits for every stream of the device.
-hipStream_t& alloc_stream();
+// Stream-ordered allocation.  Code that builds hierarchies (setup, the solve
+// server's threads) sets a per-thread stream; device buffers created and
+// released under it come from the device's memory pool (hipMallocAsync /
+// hipFreeAsync on that stream) instead of hipMalloc / hipFree, whose release
+// waits for every stream of the device and whose mapping of fresh memory is
+// slow.
+struct AllocMode {
+    bool pooled = false;
+    hipStream_t stream = nullptr;
+};
+AllocMode& alloc_mode();
 struct AllocStreamScope {
-    hipStream_t prev;
-    explicit AllocStreamScope(hipStream_t s) : prev(alloc_stream()) { alloc_stream() = s; }
-    ~AllocStreamScope() { alloc_stream() = prev; }
+    AllocMode prev;
+    explicit AllocStreamScope(hipStream_t s, bool pooled = true) : prev(alloc_mode()) {
+        alloc_mode() = AllocMode{pooled, s};
+    }
+    ~AllocStreamScope() { alloc_mode() = prev; }
     AllocStreamScope(const AllocStreamScope&) = delete;
     AllocStreamScope& operator=(const AllocStreamScope&) = delete;
 };
+// keep memory freed to the device's default pool for reuse (idempotent)
+void keep_pool_memory(int device);
+// false when MATAMG_NO_POOL=1 asks for plain hipMalloc / hipFree everywhere
+bool pool_enabled();
 
 template <typename T>
 class DBuf {
@@ -80,9 +91,9 @@ class DBuf {
         n_ = n;
         mc_ = mc;
         if (n == 0) return;
-        hipStream_t s = alloc_stream();
-        pooled_ = s != nullptr;
-        hipError_t e = pooled_ ? hipMallocAsync((void**)&p_, n * sizeof(T), s) : hipMalloc(&p_, n * sizeof(T));
+        const AllocMode m = alloc_mode();
+        pooled_ = m.pooled;
+        hipError_t e = pooled_ ? hipMallocAsync((void**)&p_, n * sizeof(T), m.stream) : hipMalloc(&p_, n * sizeof(T));
         if (e != hipSuccess) {
             p_ = nullptr;
             n_ = 0;
@@ -92,8 +103,10 @@ class DBuf {
     }
     void release() {
         if (p_) {
-            hipStream_t s = alloc_stream();
-            if (pooled_ && s) (void)hipFreeAsync(p_, s);
+            // a pooled buffer goes back to the pool in the order of the current
+            // thread's stream (the null stream outside a scope: callers free
+            // hierarchies only once the device is idle)
+            if (pooled_) (void)hipFreeAsync(p_, alloc_mode().stream);
             else (void)hipFree(p_);
             if (mc_) mc_->add(-(int64_t)(n_ * sizeof(T)));
         }

@@ -224,6 +224,16 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
                                            const double* elem_sigma, const double* coords,
                                            const amg_options& opt, bool host_ptrs, hipStream_t s) {
     const double t0 = now_s();
+    // setup allocates and frees many temporaries: take them from the pool in
+    // the order of the setup stream (unless the caller's thread already set a
+    // scope, as the solve server's workers do)
+    const bool scoped = alloc_mode().pooled;
+    if (!scoped && pool_enabled()) {
+        int dev = 0;
+        MATAMG_HIP(hipGetDevice(&dev));
+        keep_pool_memory(dev);
+    }
+    AllocStreamScope scope(scoped ? alloc_mode().stream : s, scoped || pool_enabled());
     auto hp = std::make_unique<Hierarchy>();
     Hierarchy& h = *hp;
     h.opt = opt;
@@ -350,7 +360,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
             L.nc = nagg;
             L.agg.alloc(nl, mc);
             agg_assign(nl, L.A.rowptr.get(), L.A.col.get(), L.mask.get(), L.dir.get(), state.get(), rank.get(),
-                       phase2.get(), L.agg.get(), s);
+                       phase2.get(), L.agg.get(), flags.get(), und.get(), s);
         }
 
         // filtered matrix, 1-norm diagonal, damping, smoothed prolongator

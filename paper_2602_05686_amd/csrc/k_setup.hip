@@ -437,31 +437,63 @@ __global__ void k_agg_phase2(int n, const int* rowptr, const int* col, const uin
 
 // remaining nodes join the phase-2 aggregate with the most kept neighbours,
 // ties to the smallest aggregate id
-__global__ void k_agg_phase3(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint8_t* dir,
-                             const int* phase2, int* agg) {
+// Phase 3: a node left unassigned by phase 2 joins the phase-2 aggregate
+// that holds most of its kept neighbours (ties: smallest aggregate id).
+// The first kernel settles every other node and lists the unassigned ones;
+// the second gives each listed node a wavefront: lanes take the row's
+// candidates, count each candidate's occurrences over the whole row, and a
+// lane reduction picks (largest count, smallest id).  The outcome of a node
+// depends only on phase 2, so the list order does not matter.
+__global__ void k_agg_phase3_split(int n, const uint8_t* dir, const int* phase2, int* agg, int* list, int* nlist) {
     ROW_LOOP(i, n) {
-        int a = phase2[i];
-        if (a < 0 && !(dir && dir[i])) {
-            int best = -1, bestcnt = 0;
-            const int lo = rowptr[i], hi = rowptr[i + 1];
-            for (int k = lo; k < hi; ++k) {
-                const int j = col[k];
-                if (j == i || !mask[k] || phase2[j] < 0) continue;
-                const int c = phase2[j];
-                int cnt = 0;
-                for (int k2 = lo; k2 < hi; ++k2) {
-                    const int j2 = col[k2];
-                    if (j2 == i || !mask[k2]) continue;
-                    if (phase2[j2] == c) cnt++;
-                }
-                if (cnt > bestcnt || (cnt == bestcnt && c < best)) {
-                    best = c;
-                    bestcnt = cnt;
+        const int a = phase2[i];
+        if (a < 0 && !(dir && dir[i])) list[atomicAdd(nlist, 1)] = (int)i;
+        else agg[i] = a;
+    }
+}
+
+__device__ __forceinline__ int phase3_candidate(const int* col, const uint8_t* mask, const int* phase2, int i, int k,
+                                                int hi) {
+    if (k >= hi) return -1;
+    const int j = col[k];
+    if (j == i || !mask[k]) return -1;
+    return phase2[j];  // -1 if j is unassigned too
+}
+
+__global__ __launch_bounds__(kBlock) void k_agg_phase3_rows(const int* rowptr, const int* col, const uint8_t* mask,
+                                                            const int* phase2, const int* list, const int* nlist,
+                                                            int* agg) {
+    const int lane = threadIdx.x & 63;
+    const int waves = (int)(gridDim.x * blockDim.x) >> 6;
+    const int nl = *nlist;
+    for (int w = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); w < nl; w += waves) {
+        const int i = list[w];
+        const int lo = rowptr[i], hi = rowptr[i + 1];
+        int bestc = -1, bestn = 0;
+        for (int k0 = lo; k0 < hi; k0 += 64) {
+            const int c = phase3_candidate(col, mask, phase2, i, k0 + lane, hi);
+            int cnt = 0;
+            for (int k1 = lo; k1 < hi; k1 += 64) {
+                const int c2 = phase3_candidate(col, mask, phase2, i, k1 + lane, hi);
+                for (int q = 0; q < 64; ++q) {
+                    const int cq = __shfl(c2, q, 64);  // every lane takes part in the shuffle
+                    cnt += (c >= 0 && cq == c) ? 1 : 0;
                 }
             }
-            a = best;
+            if (c >= 0 && (cnt > bestn || (cnt == bestn && c < bestc))) {
+                bestn = cnt;
+                bestc = c;
+            }
         }
-        agg[i] = a;
+        for (int off = 32; off > 0; off >>= 1) {
+            const int on = __shfl_xor(bestn, off, 64);
+            const int oc = __shfl_xor(bestc, off, 64);
+            if (on > bestn || (on == bestn && on > 0 && oc < bestc)) {
+                bestn = on;
+                bestc = oc;
+            }
+        }
+        if (lane == 0) agg[i] = bestc;
     }
 }
 
@@ -723,9 +755,16 @@ void agg_root_flags(int n, const uint8_t* state, int* flags, hipStream_t s) {
 }
 
 void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint8_t* dir,
-                const uint8_t* state, const int* root_rank, int* phase2, int* agg, hipStream_t s) {
+                const uint8_t* state, const int* root_rank, int* phase2, int* agg, int* list, int* nlist,
+                hipStream_t s) {
     LAUNCH(k_agg_phase2, n, n, rowptr, col, mask, dir, state, root_rank, phase2);
-    LAUNCH(k_agg_phase3, n, n, rowptr, col, mask, dir, phase2, agg);
+    MATAMG_HIP(hipMemsetAsync(nlist, 0, sizeof(int), s));
+    LAUNCH(k_agg_phase3_split, n, n, dir, phase2, agg, list, nlist);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_agg_phase3_rows, dim3(1024), dim3(kBlock), 0, s, rowptr, col, mask, phase2,
+                           (const int*)list, (const int*)nlist, agg);
+        MATAMG_LAUNCH_CHECK();
+    }
 }
 
 void filter_count(const DCsr& A, const uint8_t* mask, int* cnt, hipStream_t s) {

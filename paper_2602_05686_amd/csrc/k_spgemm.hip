@@ -224,10 +224,13 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
                                 if (valid) (void)hash_insert(keys, mask, c);
                             });
     phase_fence<GLOBAL>();
-    // compact the occupied slots into the output column range (arbitrary order)
+    // compact the occupied slots (arbitrary order): into LDS on the LDS path
+    // (the accumulator's space, unused until the ranks are known), into the
+    // output column range otherwise
     const int base = crp[i];
     const int d = crp[i + 1] - base;
     int* cl = ccol + base;
+    int* lst = GLOBAL ? cl : reinterpret_cast<int*>(acc);
     int filled = 0;
     for (unsigned h0 = 0; h0 <= mask; h0 += 64) {
         const unsigned h = h0 + lane;
@@ -235,15 +238,15 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
         const bool occ = key >= 0;
         const uint64_t bal = __ballot(occ);
         const int before = __popcll(bal & ((1ull << lane) - 1ull));
-        if (occ && filled + before < d) cl[filled + before] = key;
+        if (occ && filled + before < d) lst[filled + before] = key;
         filled += __popcll(bal);
     }
     phase_fence<GLOBAL>();
     // rank of each column among the row's columns = its output position
     for (int e = lane; e < d; e += 64) {
-        const int c = cl[e];
+        const int c = lst[e];
         int r = 0;
-        for (int q = 0; q < d; ++q) r += (cl[q] < c);
+        for (int q = 0; q < d; ++q) r += (lst[q] < c);
         vals[hash_find_fresh<GLOBAL>(keys, mask, c)] = r;
     }
     phase_fence<GLOBAL>();
@@ -254,17 +257,28 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
     }
     for (int e = lane; e < d; e += 64) acc[e] = 0.0;
     phase_fence<GLOBAL>();
-    // accumulate in canonical product order; one lane performs every addition
+    // Accumulate in canonical product order.  Within each step of 64
+    // products, the first lane holding an output column (its leader) adds
+    // that column's products of the step to the running value in lane order;
+    // steps follow each other in product order.  Every entry therefore
+    // receives exactly the sequence of additions of a serial row product.
     for_each_product<true>(arp, acol, aval, brp, bcol, bval, i,
                            [&](bool valid, int c, double pv, int t0, int total) {
                                int r = valid ? vals[hash_find_fresh<GLOBAL>(keys, mask, c)] : 0;
                                r = (r >= 0 && r < d) ? r : 0;
                                const int m = min(64, total - t0);
+                               double run = valid ? acc[r] : 0.0;
+                               bool leader = valid;
                                for (int q = 0; q < m; ++q) {
                                    const int rq = __shfl(r, q, 64);
                                    const double vq = __shfl(pv, q, 64);
-                                   if (lane == 0) acc[rq] += vq;
+                                   if (valid && rq == r) {
+                                       if (q < lane) leader = false;
+                                       run += vq;
+                                   }
                                }
+                               if (leader) acc[r] = run;
+                               phase_fence<GLOBAL>();
                            });
     phase_fence<GLOBAL>();
     for (int e = lane; e < d; e += 64) cval[base + e] = acc[e];

@@ -265,10 +265,7 @@ Server::Server(const amg_options& opt, int64_t budget, int max_active, int setup
     MATAMG_HIP(hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, device_));
     if (!pools) fail(AMG_ERR_HIP, "the device has no stream-ordered memory pool");
     // keep freed pool memory for reuse instead of returning it at every sync
-    hipMemPool_t pool = nullptr;
-    MATAMG_HIP(hipDeviceGetDefaultMemPool(&pool, device_));
-    uint64_t keep = UINT64_MAX;
-    MATAMG_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+    keep_pool_memory(device_);
     MATAMG_HIP(hipStreamCreateWithFlags(&es_, hipStreamNonBlocking));
     sscal_.alloc((size_t)max_active * S_NSCAL);
     MATAMG_HIP(hipMemsetAsync(sscal_.get(), 0, sizeof(double) * (size_t)max_active * S_NSCAL, es_));

@@ -37,8 +37,11 @@ void mis_init(int n, const uint8_t* dir, uint8_t* state, hipStream_t s);
 void mis_round(const DCsr& A, const uint8_t* mask, uint64_t key, uint8_t* state, uint64_t* t1, uint64_t* t2,
                int* undecided, hipStream_t s);
 void agg_root_flags(int n, const uint8_t* state, int* flags, hipStream_t s);
+// phase 2 (neighbours of roots) and phase 3 (leftovers); list: n ints and
+// nlist: one int of device scratch
 void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint8_t* dir,
-                const uint8_t* state, const int* root_rank, int* phase2, int* agg, hipStream_t s);
+                const uint8_t* state, const int* root_rank, int* phase2, int* agg, int* list, int* nlist,
+                hipStream_t s);
 
 // filtered matrix A_F (diagonal + kept entries, lumped diagonal) and its 1-norm diagonal
 void filter_count(const DCsr& A, const uint8_t* mask, int* cnt, hipStream_t s);
