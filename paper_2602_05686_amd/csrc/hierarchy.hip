@@ -30,17 +30,24 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Row blocks of A for the streaming kernels, computed on the device.
+// MATAMG_CHECK_PARTITION=1 also runs the host walk and fails on any
+// difference (used by the tests).
 void make_blocks(DCsr& A, MemCounter* mc, hipStream_t s) {
-    std::vector<int> rp((size_t)A.n + 1);
-    d2h(rp.data(), A.rowptr.get(), rp.size(), s);
-    int max_len = 0;
-    for (int i = 0; i < A.n; ++i) max_len = std::max(max_len, rp[i + 1] - rp[i]);
-    A.group = stream_group(max_len);
-    std::vector<int> blk = stream_blocks(rp.data(), A.n, A.group);
-    A.nblk = (int)blk.size() - 1;
-    A.blk.alloc(blk.size(), mc);
-    h2d(A.blk.get(), blk.data(), blk.size(), s);
-    MATAMG_HIP(hipStreamSynchronize(s));
+    stream_partition(A, mc, s);
+    const char* chk = std::getenv("MATAMG_CHECK_PARTITION");
+    if (chk && chk[0] == '1') {
+        std::vector<int> rp((size_t)A.n + 1);
+        d2h(rp.data(), A.rowptr.get(), rp.size(), s);
+        int max_len = 0;
+        for (int i = 0; i < A.n; ++i) max_len = std::max(max_len, rp[i + 1] - rp[i]);
+        const int group = stream_group(max_len);
+        std::vector<int> blk = stream_blocks(rp.data(), A.n, group);
+        std::vector<int> dev((size_t)A.nblk + 1);
+        d2h(dev.data(), A.blk.get(), dev.size(), s);
+        if (group != A.group || blk != dev)
+            fail(AMG_ERR_HIP, "device row-block partition differs from the host walk (n=" + std::to_string(A.n) + ")");
+    }
 }
 
 // reduction partials: one slot per block of the widest fused-reduction launch

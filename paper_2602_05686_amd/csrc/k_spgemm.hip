@@ -24,6 +24,8 @@ namespace {
 constexpr int kWaves = kBlock / 64;
 constexpr int kHS = 1024;     // LDS hash slots per wave
 constexpr int kDMax = 512;    // max distinct columns on the LDS path
+constexpr int kRankTile = 1024;  // LDS tile of the column list when ranking long rows
+constexpr int kRankKeys = 8;     // keys per lane per ranking pass
 
 __device__ __forceinline__ unsigned hash_slot(int key, unsigned mask) {
     return ((unsigned)key * 2654435761u) & mask;
@@ -45,6 +47,7 @@ __device__ __forceinline__ int hash_insert(int* keys, unsigned mask, int key) {
 // f(valid, colB, value, t0, total) is called by every lane for each step of
 // 64 products starting at t0; lanes past the end get valid = false.  All
 // cross-lane traffic uses shuffles, so every lane executes the same steps.
+// f returns whether to go on; its answer must be the same on every lane.
 template <bool NEED_VAL, typename F>
 __device__ void for_each_product(const int* arp, const int* acol, const double* aval, const int* brp,
                                  const int* bcol, const double* bval, int i, F&& f) {
@@ -89,7 +92,7 @@ __device__ void for_each_product(const int* arp, const int* acol, const double* 
                 colB = bcol[kb];
                 if (NEED_VAL) pv = sa * bval[kb];
             }
-            f(valid, colB, pv, t0, total);
+            if (!f(valid, colB, pv, t0, total)) return;
         }
     }
 }
@@ -165,20 +168,19 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int
     }
     for (unsigned h = lane; h <= mask; h += 64) keys[h] = -1;
     phase_fence<GLOBAL>();
+    // distinct columns so far (the same on every lane); the LDS path stops as
+    // soon as the row cannot fit, so its table never fills up
     int added = 0;
-    int full = 0;
+    bool full = false;
     for_each_product<false>(arp, acol, nullptr, brp, bcol, nullptr, i,
                             [&](bool valid, int c, double, int, int) {
-                                if (valid) {
-                                    const int r = hash_insert(keys, mask, c);
-                                    if (r > 0) added++;
-                                    if (r < 0) full = 1;
-                                }
+                                int r = 0;
+                                if (valid) r = hash_insert(keys, mask, c);
+                                added += __popcll(__ballot(r > 0));
+                                const bool overflow = __ballot(r < 0) != 0;
+                                full = full || overflow;
+                                return GLOBAL || !(full || added > kDMax);
                             });
-    for (int off = 32; off > 0; off >>= 1) {
-        added += __shfl_down(added, off, 64);
-        full |= __shfl_down(full, off, 64);
-    }
     if (lane == 0) {
         if (!GLOBAL && (full || added > kDMax)) cnt[i] = -1;
         else cnt[i] = added;
@@ -194,6 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
     __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kHS];
     __shared__ int svals[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kHS];
     __shared__ double sacc[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kDMax];
+    __shared__ int stile[GLOBAL ? kWaves : 1][GLOBAL ? kRankTile : 1];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ridx = blockIdx.x * kWaves + w;
     if (ridx >= nrows) return;
@@ -222,6 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
     for_each_product<false>(arp, acol, nullptr, brp, bcol, nullptr, i,
                             [&](bool valid, int c, double, int, int) {
                                 if (valid) (void)hash_insert(keys, mask, c);
+                                return true;
                             });
     phase_fence<GLOBAL>();
     // compact the occupied slots (arbitrary order): into LDS on the LDS path
@@ -243,11 +247,40 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
     }
     phase_fence<GLOBAL>();
     // rank of each column among the row's columns = its output position
-    for (int e = lane; e < d; e += 64) {
-        const int c = lst[e];
-        int r = 0;
-        for (int q = 0; q < d; ++q) r += (lst[q] < c);
-        vals[hash_find_fresh<GLOBAL>(keys, mask, c)] = r;
+    if constexpr (!GLOBAL) {
+        for (int e = lane; e < d; e += 64) {
+            const int c = lst[e];
+            int r = 0;
+            for (int q = 0; q < d; ++q) r += (lst[q] < c);
+            vals[hash_find_fresh<GLOBAL>(keys, mask, c)] = r;
+        }
+    } else {
+        // long rows: kRankKeys keys per lane at a time, compared against the
+        // list staged through LDS in tiles
+        int* tile = stile[w];
+        for (int e0 = 0; e0 < d; e0 += 64 * kRankKeys) {
+            int c[kRankKeys], r[kRankKeys];
+#pragma unroll
+            for (int u = 0; u < kRankKeys; ++u) {
+                const int e = e0 + u * 64 + lane;
+                c[u] = e < d ? lst[e] : -1;
+                r[u] = 0;
+            }
+            for (int t0 = 0; t0 < d; t0 += kRankTile) {
+                const int tn = min(kRankTile, d - t0);
+                for (int q = lane; q < tn; q += 64) tile[q] = lst[t0 + q];
+                phase_fence<false>();
+                for (int q = 0; q < tn; ++q) {
+                    const int v = tile[q];
+#pragma unroll
+                    for (int u = 0; u < kRankKeys; ++u) r[u] += (v < c[u]) ? 1 : 0;
+                }
+                phase_fence<false>();
+            }
+#pragma unroll
+            for (int u = 0; u < kRankKeys; ++u)
+                if (c[u] >= 0) vals[hash_find_fresh<GLOBAL>(keys, mask, c[u])] = r[u];
+        }
     }
     phase_fence<GLOBAL>();
     for (unsigned h = lane; h <= mask; h += 64) {
@@ -279,6 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
                                }
                                if (leader) acc[r] = run;
                                phase_fence<GLOBAL>();
+                               return true;
                            });
     phase_fence<GLOBAL>();
     for (int e = lane; e < d; e += 64) cval[base + e] = acc[e];

@@ -22,6 +22,9 @@ void dot(const T* a, const T* b, int64_t n, double* partial, unsigned* counter, 
 std::vector<int> stream_blocks(const int* rowptr_host, int n, int group);
 // threads per row for a matrix whose longest row has `max_len` entries
 int stream_group(int max_len);
+// A.group, A.nblk and A.blk from A's device row pointer (the same greedy
+// partition as stream_blocks, computed on the device); synchronises s
+void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s);
 
 // dot-fusion target: per-block partial sums, reduced by finish_sum into *result
 struct DotTarget {

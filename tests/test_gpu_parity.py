@@ -235,3 +235,18 @@ def test_error_paths(amg):
     # zero right-hand side
     x, info = h.solve(np.zeros(prob.n))
     assert info["status"] == "OK" and np.all(x == 0)
+
+
+def test_device_partition_equals_host_walk(amg, monkeypatch):
+    """Every matrix's row-block partition computed on the device (pointer
+    doubling over the greedy walk's successor map) equals the host walk."""
+    banner("device row-block partition vs host walk")
+    monkeypatch.setenv("MATAMG_CHECK_PARTITION", "1")
+    for name in ("checker64", "layered16", "aniso16", "twodomain64"):
+        prob_fn, kw = CASES[name]
+        prob = prob_fn()
+        h = amg.Hierarchy.from_problem(prob, **kw)  # raises on any difference
+        h.close()
+    prob = rotated_anisotropic_3d(n=24, block=8)
+    h = amg.Hierarchy.from_problem(prob, max_coarse=50, precision="fp32")
+    h.close()
