@@ -386,7 +386,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
             DBuf<double> dt(nl, mc), dtinv(nl, mc);
             filter_fill(L.A, L.mask.get(), F.rowptr.get(), F.col.get(), F.val.get(), dt.get(), dtinv.get(), s);
             make_blocks(F, mc, s);
-            ensure_partial(h, std::max(F.nblk, L.A.nblk));
+            ensure_partial(h, std::max(stream_partials(F), stream_partials(L.A)));
             L.lam_pf = power_method(F, dtinv.get(), opt.power_iters, stream_key(opt.seed, kPurposePf, l), h, s);
             L.omega = L.lam_pf > 0.0 ? opt.omega_sym / L.lam_pf : 0.0;
             DCsr Ph;
@@ -427,7 +427,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
         h.nlev = l + 2;
     }
     h.nlev = l + 1;
-    ensure_partial(h, h.lev[0].A.nblk);
+    ensure_partial(h, stream_partials(h.lev[0].A));
 
     // smoother spectral bounds and coefficients
     for (int k = 0; k + 1 < h.nlev; ++k) {

@@ -51,8 +51,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_batch(const CgUpdArgs* arg
     cg_update_body(a, blockIdx.x - starts[j], starts[j + 1] - starts[j], sh);
 }
 
-__global__ __launch_bounds__(kBlock) void k_finish_batch(const FinishArgs* args) {
-    __shared__ double sh[kBlock / 64];
+__global__ __launch_bounds__(kFinishThreads) void k_finish_batch(const FinishArgs* args) {
+    __shared__ double sh[kFinishThreads / 64];
     const FinishArgs a = args[blockIdx.x];
     finish_body(a, sh);
 }
@@ -119,7 +119,7 @@ void cg_update_batch(const CgUpdArgs* args, const int* starts, int nseg, int tot
 
 void finish_batch(const FinishArgs* args, int nseg, hipStream_t s) {
     if (nseg <= 0) return;
-    hipLaunchKernelGGL(k_finish_batch, dim3(nseg), dim3(kBlock), 0, s, args);
+    hipLaunchKernelGGL(k_finish_batch, dim3(nseg), dim3(kFinishThreads), 0, s, args);
     MATAMG_LAUNCH_CHECK();
 }
 

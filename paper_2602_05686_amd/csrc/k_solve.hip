@@ -115,14 +115,14 @@ __global__ __launch_bounds__(kBlock) void k_dot(const T* a, const T* b, int64_t 
     store_partial(t, dt);
 }
 
-__global__ __launch_bounds__(kBlock) void k_finish_sum(FinishArgs a) {
-    __shared__ double sh[kBlock / 64];
+__global__ __launch_bounds__(kFinishThreads) void k_finish_sum(FinishArgs a) {
+    __shared__ double sh[kFinishThreads / 64];
     finish_body(a, sh);
 }
 }  // namespace
 
 void finish_sum(const DotTarget& dt, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(kBlock), 0, s, FinishArgs{nblocks, dt.partial, dt.result});
+    hipLaunchKernelGGL(k_finish_sum, dim3(1), dim3(kFinishThreads), 0, s, FinishArgs{nblocks, dt.partial, dt.result});
     MATAMG_LAUNCH_CHECK();
 }
 
@@ -185,7 +185,7 @@ void launch_stream(const DCsr& A, const SArgs<T>& a, hipStream_t s) {
     else
         hipLaunchKernelGGL((k_stream<T, MODE, HAS_DOT, 8>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a, A.nblk);
     MATAMG_LAUNCH_CHECK();
-    if constexpr (HAS_DOT) finish_sum(a.dt, A.nblk, s);
+    if constexpr (HAS_DOT) finish_sum(a.dt, stream_partials(A), s);
 }
 
 template <typename T>

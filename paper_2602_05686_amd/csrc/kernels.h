@@ -26,6 +26,10 @@ int stream_group(int max_len);
 // partition as stream_blocks, computed on the device); synchronises s
 void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s);
 
+// dot partials of a streaming launch: one per wavefront of each row block
+constexpr int kStreamPartials = kBlock / 64;
+inline int stream_partials(const DCsr& A) { return A.nblk * kStreamPartials; }
+
 // dot-fusion target: per-block partial sums, reduced by finish_sum into *result
 struct DotTarget {
     double* partial = nullptr;

@@ -234,7 +234,7 @@ void emit_vcycle(std::map<int64_t, Stage<T>>& st, Request* R, DotTarget rz) {
         }
         cur[l] = x;
     }
-    stage<T>(st, key_up(0, kUpFinish), K_FINISH).fin.push_back(FinishArgs{h.lev[0].A.nblk, rz.partial, rz.result});
+    stage<T>(st, key_up(0, kUpFinish), K_FINISH).fin.push_back(FinishArgs{stream_partials(h.lev[0].A), rz.partial, rz.result});
 }
 
 struct TableBuilder {
@@ -494,7 +494,7 @@ void Server::run_step(std::vector<Request*>& batch) {
             a.dt = DotTarget{h.partial.get(), h.counter.get(), sc + S_PQ};
             add_stream64(stage<T>(st, key_cg(1), K_STREAM64, M_DOTPQ, true), A, a);
         }
-        stage<T>(st, key_cg(2), K_FINISH).fin.push_back(FinishArgs{A.nblk, h.partial.get(), sc + S_PQ});
+        stage<T>(st, key_cg(2), K_FINISH).fin.push_back(FinishArgs{stream_partials(A), h.partial.get(), sc + S_PQ});
         {
             Stage<T>& s = stage<T>(st, key_cg(3), K_CGUPD);
             s.cu.push_back(CgUpdArgs{n, h.cx.get(), h.cr.get(), h.cp.get(), h.cq.get(), sc + target, sc + S_PQ,

@@ -81,8 +81,9 @@ struct StreamShared {
 
 // Row block `bid` of the matrix in `a`: stream its val/col range into LDS
 // products, reduce each row with G threads (or the whole block for a long
-// row), apply the epilogue, and store the block's dot partial at
-// a.dt.partial[bid].
+// row), apply the epilogue, and store each wavefront's dot partial at
+// a.dt.partial[bid * kStreamPartials + wave] (no block-wide step at the end,
+// so the waves of a block retire independently).
 template <typename T, int MODE, bool HAS_DOT, int G>
 __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamShared<T>& S) {
     const int r0 = a.blk[bid], r1 = a.blk[bid + 1];
@@ -137,8 +138,8 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
         }
     }
     if constexpr (HAS_DOT) {
-        double t = block_sum(dp, S.sh);
-        if (threadIdx.x == 0) a.dt.partial[bid] = t;
+        const double t = wave_sum(dp);
+        if ((threadIdx.x & 63) == 0) a.dt.partial[bid * kStreamPartials + (threadIdx.x >> 6)] = t;
     }
 }
 
@@ -213,18 +214,39 @@ __device__ __forceinline__ void cg_update_body(const CgUpdArgs& a, int lb, int g
     if (threadIdx.x == 0) a.partial[lb] = t;
 }
 
-// *result = sum of partial[0..nb) in index order (one block)
+// *result = sum of partial[0..nb) (one block of kFinishThreads threads).
+// Thread t adds partial[t], partial[t + T], ... in ascending order, four
+// independent loads in flight at a time; the per-thread sums are combined
+// by a fixed tree.  The order depends on nb only.
+constexpr int kFinishThreads = 1024;
+
 struct FinishArgs {
     int nb;
     const double* partial;
     double* result;
 };
 
-__device__ __forceinline__ void finish_body(const FinishArgs& a, double* sh) {
+__device__ __forceinline__ void finish_body(const FinishArgs& a, double* sh /* kFinishThreads / 64 */) {
+    constexpr int T = kFinishThreads;
     double v = 0.0;
-    for (int i = threadIdx.x; i < a.nb; i += kBlock) v += a.partial[i];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) *a.result = v;
+    int i = threadIdx.x;
+    for (; i + 3 * T < a.nb; i += 4 * T) {
+        const double p0 = a.partial[i], p1 = a.partial[i + T], p2 = a.partial[i + 2 * T], p3 = a.partial[i + 3 * T];
+        v += p0;
+        v += p1;
+        v += p2;
+        v += p3;
+    }
+    for (; i < a.nb; i += T) v += a.partial[i];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int k = 1; k < T / 64; ++k) t += sh[k];
+        *a.result = t;
+    }
 }
 
 // ------------------------------------------------------------- dense GEMV
