@@ -37,32 +37,55 @@ struct SArgs {
     DotTarget dt;
 };
 
+// Per-row operands of the epilogue, loaded before the row's sum is known so
+// that their latency overlaps the streaming of the block's entries.
+template <typename T>
+struct RowOperands {
+    T b, dinv, d, xin;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ RowOperands<T> row_operands(const SArgs<T>& a, int r) {
+    RowOperands<T> o{};
+    if constexpr (MODE == M_RESID || MODE == M_RESNORM) o.b = a.b[r];
+    if constexpr (MODE == M_ADD) o.xin = a.yin[r];
+    if constexpr (MODE == M_SMOOTH) {
+        o.b = a.b[r];
+        o.dinv = a.dinv[r];
+        o.d = a.d[r];
+        o.xin = a.yin[r];
+    }
+    if constexpr (MODE == M_DOTPQ) o.xin = a.x[r];
+    if constexpr (MODE == M_SCALENORM) o.dinv = a.dinv[r];
+    return o;
+}
+
 template <typename T, int MODE, bool HAS_DOT>
-__device__ __forceinline__ double epilogue(const SArgs<T>& a, int r, T s) {
+__device__ __forceinline__ double epilogue(const SArgs<T>& a, int r, T s, const RowOperands<T>& o) {
     double dp = 0.0;
     if constexpr (MODE == M_PLAIN) {
         a.y[r] = s;
     } else if constexpr (MODE == M_RESID) {
-        a.y[r] = a.b[r] - s;
+        a.y[r] = o.b - s;
     } else if constexpr (MODE == M_ADD) {
-        a.y[r] = a.yin[r] + s;
+        a.y[r] = o.xin + s;
     } else if constexpr (MODE == M_SMOOTH) {
-        T res = a.b[r] - s;
-        T dn = a.c1 * a.d[r] + a.c2 * (a.dinv[r] * res);
+        T res = o.b - s;
+        T dn = a.c1 * o.d + a.c2 * (o.dinv * res);
         a.d[r] = dn;
-        T xn = a.yin[r] + dn;
+        T xn = o.xin + dn;
         if (a.y64) a.y64[r] = (double)xn;
         else a.y[r] = xn;
         if constexpr (HAS_DOT) dp = (double)xn * a.dotvec[r];
     } else if constexpr (MODE == M_DOTPQ) {
         a.y[r] = s;
-        dp = (double)a.x[r] * (double)s;
+        dp = (double)o.xin * (double)s;
     } else if constexpr (MODE == M_RESNORM) {
-        T v = a.b[r] - s;
+        T v = o.b - s;
         a.y[r] = v;
         dp = (double)v * (double)v;
     } else if constexpr (MODE == M_SCALENORM) {
-        T v = a.dinv[r] * s;
+        T v = o.dinv * s;
         a.y[r] = v;
         dp = (double)v * (double)v;
     }
@@ -79,11 +102,40 @@ struct StreamShared {
     T shr[kBlock / 64];
 };
 
+// prod[t] = val[k0 + t] * x[col[k0 + t]] for t < cnt, with NU = ceil(cnt /
+// kBlock) strides per thread: all loads first (indices past the end clamped
+// to the last entry, results discarded), then the gathers, then the stores.
+template <typename T, int NU>
+__device__ __forceinline__ void stage_products(const SArgs<T>& a, int k0, int cnt, T* prod) {
+    int c[NU];
+    T v[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int t = (int)threadIdx.x + u * kBlock;
+        const int tc = t < cnt ? t : cnt - 1;
+        c[u] = __builtin_nontemporal_load(a.col + k0 + tc);
+        v[u] = __builtin_nontemporal_load(a.val + k0 + tc);
+    }
+    T xv[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) xv[u] = a.x[c[u]];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int t = (int)threadIdx.x + u * kBlock;
+        if (t < cnt) prod[t] = v[u] * xv[u];
+    }
+}
+
 // Row block `bid` of the matrix in `a`: stream its val/col range into LDS
 // products, reduce each row with G threads (or the whole block for a long
 // row), apply the epilogue, and store each wavefront's dot partial at
 // a.dt.partial[bid * kStreamPartials + wave] (no block-wide step at the end,
 // so the waves of a block retire independently).
+//
+// Every load of the streaming phase is unconditional: indices past the
+// block's end are clamped to its last entry (or row) and the results are
+// discarded, so the compiler issues all of them back to back with no
+// branch, and no wait, between them.
 template <typename T, int MODE, bool HAS_DOT, int G>
 __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamShared<T>& S) {
     const int r0 = a.blk[bid], r1 = a.blk[bid + 1];
@@ -91,35 +143,39 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
     const int cnt = k1 - k0;
     double dp = 0.0;
     if (!(r1 - r0 == 1 && cnt > long_row_limit(G))) {
-        // issue every load of this thread's share before using any of them
-        int c[kPerThread];
-        T v[kPerThread];
-#pragma unroll
-        for (int u = 0; u < kPerThread; ++u) {
-            const int t = (int)threadIdx.x + u * kBlock;
-            if (t < cnt) {
-                c[u] = __builtin_nontemporal_load(a.col + k0 + t);
-                v[u] = __builtin_nontemporal_load(a.val + k0 + t);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kPerThread; ++u) {
-            const int t = (int)threadIdx.x + u * kBlock;
-            if (t < cnt) S.prod[t] = v[u] * a.x[c[u]];
+        const int gl = (int)threadIdx.x % G;
+        const int r = r0 + (int)threadIdx.x / G;
+        const bool owner = r < r1;
+        const int rc = owner ? r : r1 - 1;
+        const int e0 = a.rowptr[rc], e1 = a.rowptr[rc + 1];
+        // one thread per row: every thread prefetches its row's operands;
+        // with G > 1 only the row's first thread needs them, after the sum
+        RowOperands<T> ops{};
+        if constexpr (G == 1) ops = row_operands<T, MODE>(a, rc);
+        // ceil(cnt / kBlock) strides of the block's entries (block-uniform)
+        switch ((cnt + kBlock - 1) / kBlock) {
+            case 1: stage_products<T, 1>(a, k0, cnt, S.prod); break;
+            case 2: stage_products<T, 2>(a, k0, cnt, S.prod); break;
+            case 3: stage_products<T, 3>(a, k0, cnt, S.prod); break;
+            case 4: stage_products<T, 4>(a, k0, cnt, S.prod); break;
+            case 5: stage_products<T, 5>(a, k0, cnt, S.prod); break;
+            case 6: stage_products<T, 6>(a, k0, cnt, S.prod); break;
+            case 7: stage_products<T, 7>(a, k0, cnt, S.prod); break;
+            case 8: stage_products<T, 8>(a, k0, cnt, S.prod); break;
+            default: break;
         }
         __syncthreads();
         // G threads per row: strided partial sums, then a fixed shuffle tree
-        const int gl = (int)threadIdx.x % G;
-        const int r = r0 + (int)threadIdx.x / G;
         T s = 0;
-        if (r < r1) {
-            const int s0 = a.rowptr[r] - k0, s1 = a.rowptr[r + 1] - k0;
-            for (int k = s0 + gl; k < s1; k += G) s += S.prod[k];
-        }
+        if (owner)
+            for (int k = e0 - k0 + gl; k < e1 - k0; k += G) s += S.prod[k];
         if constexpr (G > 1) {
             for (int off = G / 2; off > 0; off >>= 1) s += __shfl_down(s, off, G);
         }
-        if (gl == 0 && r < r1) dp = epilogue<T, MODE, HAS_DOT>(a, r, s);
+        if (gl == 0 && owner) {
+            if constexpr (G > 1) ops = row_operands<T, MODE>(a, r);
+            dp = epilogue<T, MODE, HAS_DOT>(a, r, s, ops);
+        }
     } else {
         // one long row (a block of its own): strided partial sums, fixed tree
         T s = 0;
@@ -134,7 +190,7 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
         if (threadIdx.x == 0) {
             T t = S.shr[0];
             for (int i = 1; i < kBlock / 64; ++i) t += S.shr[i];
-            dp = epilogue<T, MODE, HAS_DOT>(a, r0, t);
+            dp = epilogue<T, MODE, HAS_DOT>(a, r0, t, row_operands<T, MODE>(a, r0));
         }
     }
     if constexpr (HAS_DOT) {
