@@ -150,6 +150,10 @@ constexpr int kMaxRowsPerBlock = kBlock;
 constexpr int kLongRow = 96;         // single-thread rows: longer rows get a whole block
 // rows longer than this are reduced by a whole block, for `group` threads per row
 constexpr int long_row_limit(int group) { return group == 1 ? kLongRow : (32 * group < kStreamCap ? 32 * group : kStreamCap); }
+// rows each group of `group` threads reduces in a block (one after the other)
+constexpr int rows_per_group(int group) { return group == 1 ? 1 : 4; }
+// most rows in one row block
+constexpr int max_block_rows(int group) { return kBlock / group * rows_per_group(group); }
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 

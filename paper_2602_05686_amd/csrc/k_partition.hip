@@ -110,7 +110,7 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s) {
     d2h(&max_len, one.get(), 1, s);
     A.group = stream_group(max_len);
     const int limit = long_row_limit(A.group);
-    const int max_rows = kBlock / A.group;
+    const int max_rows = max_block_rows(A.group);
 
     const size_t n1 = (size_t)n + 1;
     DBuf<int> flags(n1, mc), pos(n1, mc), tmp(scan_tmp_size(n1), mc), longs(n1, mc);

@@ -141,7 +141,7 @@ template void dot<float>(const float*, const float*, int64_t, double*, unsigned*
 int stream_group(int max_len) { return max_len <= kLongRow ? 1 : 8; }
 
 std::vector<int> stream_blocks(const int* rp, int n, int group) {
-    const int max_rows = kBlock / group;
+    const int max_rows = max_block_rows(group);
     const int long_len = long_row_limit(group);
     std::vector<int> blk;
     blk.reserve((size_t)n / 32 + 2);

@@ -165,16 +165,26 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
             default: break;
         }
         __syncthreads();
-        // G threads per row: strided partial sums, then a fixed shuffle tree
-        T s = 0;
-        if (owner)
-            for (int k = e0 - k0 + gl; k < e1 - k0; k += G) s += S.prod[k];
-        if constexpr (G > 1) {
-            for (int off = G / 2; off > 0; off >>= 1) s += __shfl_down(s, off, G);
-        }
-        if (gl == 0 && owner) {
-            if constexpr (G > 1) ops = row_operands<T, MODE>(a, r);
-            dp = epilogue<T, MODE, HAS_DOT>(a, r, s, ops);
+        if constexpr (G == 1) {
+            T s = 0;
+            if (owner)
+                for (int k = e0 - k0; k < e1 - k0; ++k) s += S.prod[k];
+            if (owner) dp = epilogue<T, MODE, HAS_DOT>(a, r, s, ops);
+        } else {
+            // G threads per row, rows_per_group(G) rows per group: strided
+            // partial sums, then a fixed shuffle tree, row after row
+#pragma unroll
+            for (int q = 0; q < rows_per_group(G); ++q) {
+                const int rq = r + q * (kBlock / G);
+                const bool own = rq < r1;
+                const int rqc = own ? rq : r1 - 1;
+                const int f0 = a.rowptr[rqc] - k0, f1 = a.rowptr[rqc + 1] - k0;
+                T s = 0;
+                if (own)
+                    for (int k = f0 + gl; k < f1; k += G) s += S.prod[k];
+                for (int off = G / 2; off > 0; off >>= 1) s += __shfl_down(s, off, G);
+                if (gl == 0 && own) dp += epilogue<T, MODE, HAS_DOT>(a, rq, s, row_operands<T, MODE>(a, rq));
+            }
         }
     } else {
         // one long row (a block of its own): strided partial sums, fixed tree
