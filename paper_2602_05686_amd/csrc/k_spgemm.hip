@@ -24,6 +24,7 @@ namespace {
 constexpr int kWaves = kBlock / 64;
 constexpr int kHS = 1024;     // LDS hash slots per wave
 constexpr int kDMax = 512;    // max distinct columns on the LDS path
+constexpr int kHSSmall = 256; // LDS hash slots per wave for rows of at most 128 products
 constexpr int kRankTile = 1024;  // LDS tile of the column list when ranking long rows
 constexpr int kRankKeys = 8;     // keys per lane per ranking pass
 
@@ -150,7 +151,8 @@ __device__ __forceinline__ unsigned hash_find_fresh(const int* keys, unsigned ma
 template <bool GLOBAL>
 __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int* rows, const int* arp,
                                                             const int* acol, const int* brp, const int* bcol,
-                                                            int* cnt, int* gkeys, const int64_t* goff) {
+                                                            int* cnt, int* gkeys, const int64_t* goff,
+                                                            int* pcount) {
     __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kHS];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ridx = blockIdx.x * kWaves + w;
@@ -164,7 +166,9 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int
         mask = (unsigned)(goff[ridx + 1] - o) - 1;
     } else {
         keys = skeys[w];
-        mask = lds_table_mask(row_products(arp, acol, brp, i));
+        const int m = row_products(arp, acol, brp, i);
+        if (lane == 0) pcount[i] = m;
+        mask = lds_table_mask(m);
     }
     for (unsigned h = lane; h <= mask; h += 64) keys[h] = -1;
     phase_fence<GLOBAL>();
@@ -187,21 +191,30 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int
     }
 }
 
-template <bool GLOBAL>
+// LDS path (GLOBAL = false): the rows whose product count m lies in
+// (mlo, mhi] and that did not overflow (skip), with HS hash slots per wave
+// (HS >= 2 * mhi unless HS = kHS); GLOBAL: the listed overflow rows.
+template <bool GLOBAL, int HS>
 __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int* rows, const int* arp,
                                                            const int* acol, const double* aval, const int* brp,
                                                            const int* bcol, const double* bval, const int* crp,
                                                            int* ccol, double* cval, const int* skip, int* gkeys,
-                                                           int* gvals, double* gacc, const int64_t* goff) {
-    __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kHS];
-    __shared__ int svals[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kHS];
-    __shared__ double sacc[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kDMax];
+                                                           int* gvals, double* gacc, const int64_t* goff,
+                                                           const int* pcount, int mlo, int mhi) {
+    __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS];
+    __shared__ int svals[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS];
+    __shared__ double sacc[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS / 2];
     __shared__ int stile[GLOBAL ? kWaves : 1][GLOBAL ? kRankTile : 1];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ridx = blockIdx.x * kWaves + w;
     if (ridx >= nrows) return;
     const int i = rows ? rows[ridx] : ridx;
-    if (!GLOBAL && skip && skip[i]) return;
+    int m = 0;
+    if constexpr (!GLOBAL) {
+        if (skip && skip[i]) return;
+        m = pcount[i];
+        if (m <= mlo || m > mhi) return;
+    }
     int *keys, *vals;
     double* acc;
     unsigned mask;
@@ -215,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
         keys = skeys[w];
         vals = svals[w];
         acc = sacc[w];
-        mask = lds_table_mask(row_products(arp, acol, brp, i));
+        mask = lds_table_mask(m);
     }
     for (unsigned h = lane; h <= mask; h += 64) {
         keys[h] = -1;
@@ -402,13 +415,13 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
     C.n = n;
     C.m = B.m;
     const int nn = n > 0 ? n : 1;
-    DBuf<int> cnt((size_t)nn, mc), flags((size_t)nn, mc), pos((size_t)n + 1, mc);
+    DBuf<int> cnt((size_t)nn, mc), flags((size_t)nn, mc), pos((size_t)n + 1, mc), pcount((size_t)nn, mc);
     DBuf<int> tmp(scan_tmp_size(n), mc);
     const int nb = ceil_div(nn, kWaves);
     if (n > 0) {
         hipLaunchKernelGGL((k_spgemm_symbolic<false>), dim3(nb), dim3(kBlock), 0, s, n, (const int*)nullptr,
                            A.rowptr.get(), A.col.get(), B.rowptr.get(), B.col.get(), cnt.get(), (int*)nullptr,
-                           (const int64_t*)nullptr);
+                           (const int64_t*)nullptr, pcount.get());
         hipLaunchKernelGGL(k_overflow_flags, dim3(g1(n)), dim3(kBlock), 0, s, n, cnt.get(), flags.get());
         MATAMG_LAUNCH_CHECK();
     }
@@ -435,7 +448,7 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
         gacc.alloc((size_t)tot, mc);
         hipLaunchKernelGGL((k_spgemm_symbolic<true>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
                            list.get(), A.rowptr.get(), A.col.get(), B.rowptr.get(), B.col.get(), cnt.get(),
-                           gkeys.get(), toff.get());
+                           gkeys.get(), toff.get(), (int*)nullptr);
         MATAMG_LAUNCH_CHECK();
     }
     C.rowptr.alloc((size_t)n + 1, mc);
@@ -446,17 +459,24 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
     C.col.alloc((size_t)(nnz > 0 ? nnz : 1), mc);
     C.val.alloc((size_t)(nnz > 0 ? nnz : 1), mc);
     if (n > 0) {
-        hipLaunchKernelGGL((k_spgemm_numeric<false>), dim3(nb), dim3(kBlock), 0, s, n, (const int*)nullptr,
+        // rows with few products: small tables, so more wavefronts fit a CU
+        hipLaunchKernelGGL((k_spgemm_numeric<false, kHSSmall>), dim3(nb), dim3(kBlock), 0, s, n, (const int*)nullptr,
                            A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(), B.val.get(),
                            C.rowptr.get(), C.col.get(), C.val.get(), (const int*)flags.get(), (int*)nullptr,
-                           (int*)nullptr, (double*)nullptr, (const int64_t*)nullptr);
+                           (int*)nullptr, (double*)nullptr, (const int64_t*)nullptr, (const int*)pcount.get(), -1,
+                           kHSSmall / 2);
+        hipLaunchKernelGGL((k_spgemm_numeric<false, kHS>), dim3(nb), dim3(kBlock), 0, s, n, (const int*)nullptr,
+                           A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(), B.val.get(),
+                           C.rowptr.get(), C.col.get(), C.val.get(), (const int*)flags.get(), (int*)nullptr,
+                           (int*)nullptr, (double*)nullptr, (const int64_t*)nullptr, (const int*)pcount.get(),
+                           kHSSmall / 2, 0x7fffffff);
         MATAMG_LAUNCH_CHECK();
     }
     if (novf > 0) {
-        hipLaunchKernelGGL((k_spgemm_numeric<true>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
+        hipLaunchKernelGGL((k_spgemm_numeric<true, 1>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
                            list.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(),
                            B.val.get(), C.rowptr.get(), C.col.get(), C.val.get(), (const int*)nullptr, gkeys.get(),
-                           gvals.get(), gacc.get(), toff.get());
+                           gvals.get(), gacc.get(), toff.get(), (const int*)nullptr, 0, 0);
         MATAMG_LAUNCH_CHECK();
     }
     MATAMG_HIP(hipStreamSynchronize(s));
