@@ -342,15 +342,24 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
         {
             DBuf<uint8_t> state(nl, mc);
             DBuf<uint64_t> t1(nl, mc), t2(nl, mc);
-            DBuf<int> und(1, mc);
+            // rounds run in batches with one read-back per batch: a round
+            // after the last undecided node is gone changes nothing, and the
+            // per-round undecided counts give the exact round count
+            constexpr int kMisBatch = 4;
+            DBuf<int> und(kMisBatch, mc);
             const uint64_t key = stream_key(opt.seed, kPurposeMis, l);
             mis_init(nl, L.dir.get(), state.get(), s);
             int rounds = 0;
-            for (;;) {
-                mis_round(L.A, L.mask.get(), key, state.get(), t1.get(), t2.get(), und.get(), s);
-                ++rounds;
-                if (read_flag(und.get(), s) == 0) break;
-                if (rounds > nl + 1) fail(AMG_ERR_HIP, "distance-2 MIS did not terminate");
+            for (bool done = false; !done;) {
+                for (int j = 0; j < kMisBatch; ++j)
+                    mis_round(L.A, L.mask.get(), key, state.get(), t1.get(), t2.get(), und.get() + j, s);
+                int left[kMisBatch];
+                d2h(left, und.get(), kMisBatch, s);
+                for (int j = 0; j < kMisBatch && !done; ++j) {
+                    ++rounds;
+                    done = left[j] == 0;
+                }
+                if (!done && rounds > nl + 1) fail(AMG_ERR_HIP, "distance-2 MIS did not terminate");
             }
             L.mis_rounds = rounds;
             t1.release();

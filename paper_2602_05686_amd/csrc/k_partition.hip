@@ -10,6 +10,8 @@
 // and the block starts -- the orbit of row 0 under next -- are marked by
 // pointer doubling: after round k every start within 2^(k+1) blocks of row 0
 // is marked.  The result equals the host walk exactly.
+#include <algorithm>
+
 #include "device_util.h"
 #include "kernels.h"
 
@@ -23,14 +25,31 @@ inline int grid1(int64_t n) {
 
 #define FOR_ROWS(i, n) for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (n); i += (int64_t)gridDim.x * kBlock)
 
-__global__ void k_max_row_len(int n, const int* rp, int* out) {
+// longest row; launched with a small grid so that few blocks meet at the atomic
+__global__ __launch_bounds__(kBlock) void k_max_row_len(int n, const int* rp, int* out) {
+    __shared__ int sm[kBlock / 64];
     int m = 0;
     FOR_ROWS(i, n) m = max(m, rp[i + 1] - rp[i]);
     for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(out, m);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) m = max(m, sm[w]);
+        if (m > 0) atomicMax(out, m);
+    }
 }
 
-__global__ void k_long_flags(int n, const int* rp, int limit, int* flags) {
+// par[0] = longest row -> par[1] = threads per row, par[2] = long-row
+// limit, par[3] = most rows per block (the host's stream_group rule)
+__global__ void k_group_params(int* par) {
+    const int group = par[0] <= kLongRow ? 1 : 8;
+    par[1] = group;
+    par[2] = long_row_limit(group);
+    par[3] = max_block_rows(group);
+}
+
+__global__ void k_long_flags(int n, const int* rp, const int* par, int* flags) {
+    const int limit = par[2];
     FOR_ROWS(i, n) flags[i] = (rp[i + 1] - rp[i] > limit) ? 1 : 0;
 }
 
@@ -39,9 +58,9 @@ __global__ void k_long_list(int n, const int* flags, const int* pos, int* list) 
 }
 
 // end (exclusive) of the block that starts at row r; next[n] = n
-__global__ void k_block_next(int n, const int* rp, int limit, int max_rows, const int* longs, const int* nlong,
-                             int* next) {
+__global__ void k_block_next(int n, const int* rp, const int* par, const int* longs, const int* nlong, int* next) {
     const int nl = *nlong;
+    const int limit = par[2], max_rows = par[3];
     FOR_ROWS(r64, (int64_t)n + 1) {
         const int r = (int)r64;
         if (r == n) {
@@ -84,6 +103,12 @@ __global__ void k_jump_square(int n, const int* jump, int* out) {
     FOR_ROWS(p, (int64_t)n + 1) out[p] = jump[jump[p]];
 }
 
+// out[0] = number of blocks, out[1] = threads per row
+__global__ void k_partition_result(int n, const int* pos, const int* par, int* out) {
+    out[0] = pos[n];
+    out[1] = par[1];
+}
+
 __global__ void k_fill_starts(int n, const int* mark, const int* pos, int* blk) {
     FOR_ROWS(i, n) if (mark[i]) blk[pos[i]] = (int)i;
     if (blockIdx.x == 0 && threadIdx.x == 0) blk[pos[n]] = n;
@@ -102,23 +127,21 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s) {
         return;
     }
     const int* rp = A.rowptr.get();
-    DBuf<int> one(2, mc);
-    MATAMG_HIP(hipMemsetAsync(one.get(), 0, 2 * sizeof(int), s));
-    hipLaunchKernelGGL(k_max_row_len, dim3(grid1(n)), dim3(kBlock), 0, s, n, rp, one.get());
+    // threads per row from the longest row, decided on the device: the
+    // only read-back is the block count at the end
+    DBuf<int> par(8, mc);
+    MATAMG_HIP(hipMemsetAsync(par.get(), 0, 8 * sizeof(int), s));
+    hipLaunchKernelGGL(k_max_row_len, dim3(std::min(grid1(n), 256)), dim3(kBlock), 0, s, n, rp, par.get());
+    hipLaunchKernelGGL(k_group_params, dim3(1), dim3(1), 0, s, par.get());
     MATAMG_LAUNCH_CHECK();
-    int max_len = 0;
-    d2h(&max_len, one.get(), 1, s);
-    A.group = stream_group(max_len);
-    const int limit = long_row_limit(A.group);
-    const int max_rows = max_block_rows(A.group);
 
     const size_t n1 = (size_t)n + 1;
     DBuf<int> flags(n1, mc), pos(n1, mc), tmp(scan_tmp_size(n1), mc), longs(n1, mc);
-    hipLaunchKernelGGL(k_long_flags, dim3(grid1(n)), dim3(kBlock), 0, s, n, rp, limit, flags.get());
+    hipLaunchKernelGGL(k_long_flags, dim3(grid1(n)), dim3(kBlock), 0, s, n, rp, (const int*)par.get(), flags.get());
     exclusive_scan(flags.get(), pos.get(), n, tmp.get(), s);
     hipLaunchKernelGGL(k_long_list, dim3(grid1(n)), dim3(kBlock), 0, s, n, flags.get(), pos.get(), longs.get());
     DBuf<int> ja(n1, mc), jb(n1, mc);
-    hipLaunchKernelGGL(k_block_next, dim3(grid1(n1)), dim3(kBlock), 0, s, n, rp, limit, max_rows, longs.get(),
+    hipLaunchKernelGGL(k_block_next, dim3(grid1(n1)), dim3(kBlock), 0, s, n, rp, (const int*)par.get(), longs.get(),
                        pos.get() + n, ja.get());
     MATAMG_LAUNCH_CHECK();
     // pointer doubling from row 0 (flags reused as the start marks)
@@ -135,14 +158,17 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s) {
     }
     MATAMG_LAUNCH_CHECK();
     exclusive_scan(flags.get(), pos.get(), n, tmp.get(), s);
-    int nblk = 0;
-    d2h(&nblk, pos.get() + n, 1, s);
+    hipLaunchKernelGGL(k_partition_result, dim3(1), dim3(1), 0, s, n, (const int*)pos.get(), (const int*)par.get(),
+                       par.get() + 4);
+    int res[2] = {0, 0};
+    d2h(res, par.get() + 4, 2, s);
+    const int nblk = res[0];
+    A.group = res[1];
     A.nblk = nblk;
     A.blk.alloc((size_t)nblk + 1, mc);
     hipLaunchKernelGGL(k_fill_starts, dim3(grid1(n)), dim3(kBlock), 0, s, n, (const int*)flags.get(),
                        (const int*)pos.get(), A.blk.get());
     MATAMG_LAUNCH_CHECK();
-    MATAMG_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace matamg

@@ -479,7 +479,7 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
                            gvals.get(), gacc.get(), toff.get(), (const int*)nullptr, 0, 0);
         MATAMG_LAUNCH_CHECK();
     }
-    MATAMG_HIP(hipStreamSynchronize(s));
+    // no synchronisation: temporaries go back to the pool in stream order
 }
 
 void transpose(const DCsr& A, DCsr& T, MemCounter* mc, hipStream_t s) {

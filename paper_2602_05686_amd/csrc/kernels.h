@@ -23,7 +23,8 @@ std::vector<int> stream_blocks(const int* rowptr_host, int n, int group);
 // threads per row for a matrix whose longest row has `max_len` entries
 int stream_group(int max_len);
 // A.group, A.nblk and A.blk from A's device row pointer (the same greedy
-// partition as stream_blocks, computed on the device); synchronises s
+// partition as stream_blocks, computed on the device); reads back the block
+// count, so s is synchronised once
 void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s);
 
 // dot partials of a streaming launch: one per wavefront of each row block
