@@ -21,6 +21,7 @@ _lib = None
 
 OK, INVALID_ARG, OUT_OF_MEMORY, NOT_SPD, STAGNATED, NOT_CONVERGED, BREAKDOWN = 0, 1, 2, 4, 5, 6, 7
 SOC = {"material": 0, "distance": 1, "sa": 2}
+DROP = {"pointwise": 0, "cut": 1}
 SMOOTHER = {"chebyshev": 0, "jacobi": 1}
 
 
@@ -71,7 +72,7 @@ def lib():
         i32, i64, f64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
         L.orc_clement.argtypes = [i32, i32, i32, i32, P, P, P]
         L.orc_detect_dirichlet.argtypes = [i32, P, P, P, P]
-        L.orc_strength.argtypes = [i32, P, P, P, i32, P, P, P, i32, f64, P, P, P, P]
+        L.orc_strength.argtypes = [i32, P, P, P, i32, P, P, P, i32, i32, f64, P, P, P, P]
         L.orc_aggregate.argtypes = [i32, P, P, P, P, u64, i32, P, P, P, P]
         L.orc_setup.argtypes = [i32, P, P, P, i32, i32, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(P)]
         L.orc_free.argtypes = [P]
@@ -112,6 +113,8 @@ def default_options(**kw) -> Options:
             v = SOC[v]
         if k == "smoother" and isinstance(v, str):
             v = SMOOTHER[v]
+        if k == "drop" and isinstance(v, str):
+            v = DROP[v]
         setattr(o, k, v)
     return o
 
@@ -135,7 +138,7 @@ def detect_dirichlet(rowptr, col, val):
     return d.astype(bool)
 
 
-def strength(rowptr, col, val, dim, x, sig, dirichlet=None, soc="material", theta=0.08):
+def strength(rowptr, col, val, dim, x, sig, dirichlet=None, soc="material", theta=0.08, drop="pointwise"):
     """Returns (lval, ldiag, S, mask) over A's stored pattern."""
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
     col = np.ascontiguousarray(col, dtype=np.int32)
@@ -153,7 +156,8 @@ def strength(rowptr, col, val, dim, x, sig, dirichlet=None, soc="material", thet
         dd = np.ascontiguousarray(dirichlet, dtype=np.uint8)
         dp = _p(dd)
     socv = SOC[soc] if isinstance(soc, str) else int(soc)
-    _check(lib().orc_strength(n, _p(rowptr), _p(col), _p(val), dim, _p(x), _p(sig), dp, socv, float(theta),
+    dropv = DROP[drop] if isinstance(drop, str) else int(drop)
+    _check(lib().orc_strength(n, _p(rowptr), _p(col), _p(val), dim, _p(x), _p(sig), dp, socv, dropv, float(theta),
                               _p(lv), _p(ld), _p(S), _p(mask)), "strength")
     return lv, ld, S, mask.astype(bool)
 

@@ -33,6 +33,7 @@ enum {
 };
 
 enum { SOC_MATERIAL = 0, SOC_DISTANCE = 1, SOC_SA = 2 };
+enum { DROP_POINTWISE = 0, DROP_CUT = 1 };
 enum { SMOOTH_CHEBYSHEV = 0, SMOOTH_JACOBI = 1 };
 
 typedef struct {
@@ -351,12 +352,18 @@ int orc_detect_dirichlet(int n, const int32_t *rowptr, const int32_t *col, const
  * Pointwise criterion |S_ij| >= theta is evaluated in the square-free form
  *   l_ij * l_ij >= (theta*theta) * (L_ii * L_jj),   l_ij = |L_ij|,
  * which is the same inequality for positive quantities and involves no square
- * root.  S itself is reported with the square root.
+ * root.  S itself is reported with the square root.  drop = DROP_CUT applies
+ * the cut-drop criterion instead (cut_drop below).
  */
+static int cut_drop(int n, const int32_t *rowptr, const int32_t *col, const unsigned char *dir,
+                    const double *lval, const double *ldiag, const unsigned char *coinc, double theta,
+                    unsigned char *mask);
+
 int orc_strength(int n, const int32_t *rowptr, const int32_t *col, const double *val, int dim,
-                 const double *x, const double *sig, const unsigned char *dir, int soc, double theta,
+                 const double *x, const double *sig, const unsigned char *dir, int soc, int drop, double theta,
                  double *lval, double *ldiag, double *S, unsigned char *mask)
 {
+    if (drop != DROP_POINTWISE && drop != DROP_CUT) return ORC_INVALID_ARG;
     if (dim < 1 || dim > 3) return ORC_INVALID_ARG;
     int nc = ncomp_of(dim);
     int nnz = rowptr[n];
@@ -442,9 +449,106 @@ int orc_strength(int n, const int32_t *rowptr, const int32_t *col, const double 
             mask[k] = (l * l >= th2 * prod) ? 1 : 0;
         }
     }
+    int rc = ORC_OK;
+    if (drop == DROP_CUT) rc = cut_drop(n, rowptr, col, dir, lval, ldiag, coinc, theta, mask);
     free(adiag);
     free(minv);
     free(coinc);
+    return rc;
+}
+
+static int cmp_desc(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x < y) - (x > y);
+}
+
+/*
+ * Cut-drop criterion (section "Strength-of-connection measures and dropping
+ * criteria"): order the strengths of row i decreasingly, s_1 >= s_2 >= ...,
+ * let k be the first position with theta * s_k >= s_{k+1}, and keep the
+ * entries whose strength is at least s_k; drop nothing when no such k exists.
+ *
+ * Readings (the paper leaves them open):
+ *  - the ordered row includes the diagonal, S_ii = 1;
+ *  - the row's strengths are compared through the square-free key
+ *      t_ij = (l_ij * l_ij) / L_jj   (= S_ij^2 L_ii, L_ii common to the row),
+ *    with t_ii = L_ii for the diagonal and for coincident points (S = 1), and
+ *    theta * s_k >= s_{k+1} as (theta*theta) * t_k >= t_{k+1};  an entry with
+ *    L_jj <= 0 has S = 1 like the pointwise form, so t = L_ii;
+ *  - a row with L_ii <= 0 (no positive coupling) keeps every entry;
+ *  - edges touching a Dirichlet node stay dropped and are not ordered;
+ *  - the result is made symmetric by keeping (i, j) only if both rows keep it.
+ */
+static int cut_drop(int n, const int32_t *rowptr, const int32_t *col, const unsigned char *dir,
+                    const double *lval, const double *ldiag, const unsigned char *coinc, double theta,
+                    unsigned char *mask)
+{
+    const int nnz = rowptr[n];
+    unsigned char *keep = (unsigned char *)calloc((size_t)(nnz > 0 ? nnz : 1), 1);
+    double *tk = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    double *ord = NULL;
+    int maxlen = 0;
+    for (int i = 0; i < n; ++i) {
+        int len = rowptr[i + 1] - rowptr[i];
+        if (len > maxlen) maxlen = len;
+    }
+    ord = (double *)malloc(sizeof(double) * (size_t)(maxlen > 0 ? maxlen : 1));
+    if (!keep || !tk || !ord) {
+        free(keep);
+        free(tk);
+        free(ord);
+        return ORC_OUT_OF_MEMORY;
+    }
+    const double th2 = theta * theta;
+    for (int i = 0; i < n; ++i) {
+        const int k0 = rowptr[i], k1 = rowptr[i + 1];
+        if (dir && dir[i]) {
+            for (int k = k0; k < k1; ++k) keep[k] = (col[k] == i);
+            continue;
+        }
+        const double lii = ldiag[i];
+        int m = 0;
+        for (int k = k0; k < k1; ++k) {
+            const int j = col[k];
+            tk[k] = -1.0;  /* not ordered */
+            if (j == i || coinc[k]) tk[k] = lii;
+            else if (dir && dir[j]) continue;
+            else tk[k] = (ldiag[j] > 0.0) ? (lval[k] * lval[k]) / ldiag[j] : lii;
+            ord[m++] = tk[k];
+        }
+        double cut = -1.0;  /* keep everything */
+        if (lii > 0.0) {
+            qsort(ord, (size_t)m, sizeof(double), cmp_desc);
+            for (int p = 0; p + 1 < m; ++p)
+                if (th2 * ord[p] >= ord[p + 1]) {
+                    cut = ord[p];
+                    break;
+                }
+        }
+        for (int k = k0; k < k1; ++k) keep[k] = (col[k] == i) || (tk[k] >= 0.0 && tk[k] >= cut);
+    }
+    for (int i = 0; i < n; ++i) {
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int j = col[k];
+            if (j == i) {
+                mask[k] = 1;
+                continue;
+            }
+            /* the entry (j, i): binary search in row j's sorted columns */
+            int lo = rowptr[j], hi = rowptr[j + 1] - 1, kt = -1;
+            while (lo <= hi) {
+                int mid = (lo + hi) / 2;
+                if (col[mid] == i) { kt = mid; break; }
+                if (col[mid] < i) lo = mid + 1;
+                else hi = mid - 1;
+            }
+            mask[k] = (keep[k] && kt >= 0 && keep[kt]) ? 1 : 0;
+        }
+    }
+    free(keep);
+    free(tk);
+    free(ord);
     return ORC_OK;
 }
 
@@ -859,8 +963,8 @@ int orc_setup(int n, const int32_t *rowptr, const int32_t *col, const double *va
         L->agg = (int *)malloc(sizeof(int) * (size_t)nl);
         if (!L->dir || !L->lval || !L->ldiag || !L->S || !L->mask || !L->agg) { rc = ORC_OUT_OF_MEMORY; goto fail; }
         if (l == 0) orc_detect_dirichlet(nl, L->A.rowptr, L->A.col, L->A.val, L->dir);
-        rc = orc_strength(nl, L->A.rowptr, L->A.col, L->A.val, d, L->x, L->sig, L->dir, opt->soc, opt->theta,
-                          L->lval, L->ldiag, L->S, L->mask);
+        rc = orc_strength(nl, L->A.rowptr, L->A.col, L->A.val, d, L->x, L->sig, L->dir, opt->soc, opt->drop,
+                          opt->theta, L->lval, L->ldiag, L->S, L->mask);
         if (rc) goto fail;
         rc = orc_aggregate(nl, L->A.rowptr, L->A.col, L->mask, L->dir, opt->seed, l, L->agg, &L->nc,
                            &L->mis_rounds, NULL);

@@ -173,3 +173,100 @@ def test_clement_2d_corner_edge_counts():
     assert sig[4, 0] == (1 + 2 + 3 + 4) / 4
     assert sig[0, 0] == 1.0 and sig[8, 0] == 4.0
     assert sig[1, 0] == (1 + 2) / 2
+
+
+# ----------------------------------------------------------------- cut-drop
+def literal_cut_drop(prob, S, dirichlet, theta):
+    """The cut-drop criterion as the paper states it, on the strength values
+    S (with the square root): per row, order |S_ij| decreasingly (diagonal
+    S_ii = 1 included), k = first position with theta*s_k >= s_{k+1}, keep
+    |S_ij| >= s_k (everything if no such k); then keep (i, j) only if both
+    rows keep it.  Edges touching a Dirichlet node are dropped."""
+    n = prob.n
+    keep = np.zeros(len(prob.col), dtype=bool)
+    for i in range(n):
+        lo, hi = prob.rowptr[i], prob.rowptr[i + 1]
+        if dirichlet[i]:
+            keep[lo:hi] = prob.col[lo:hi] == i
+            continue
+        ks = [k for k in range(lo, hi) if prob.col[k] == i or not dirichlet[prob.col[k]]]
+        vals = sorted((abs(S[k]) for k in ks), reverse=True)
+        cut = -1.0
+        for p in range(len(vals) - 1):
+            if theta * vals[p] >= vals[p + 1]:
+                cut = vals[p]
+                break
+        for k in ks:
+            keep[k] = prob.col[k] == i or abs(S[k]) >= cut
+    mask = np.zeros_like(keep)
+    for i in range(n):
+        for k in range(prob.rowptr[i], prob.rowptr[i + 1]):
+            j = prob.col[k]
+            lo, hi = prob.rowptr[j], prob.rowptr[j + 1]
+            kt = lo + np.searchsorted(prob.col[lo:hi], i)
+            mask[k] = keep[k] and keep[kt]
+    return mask
+
+
+def test_cut_drop_uniform_material_keeps_every_edge():
+    prob, x, sig = fig4_grid(1.0)
+    _, _, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 2, x, sig, soc="material", theta=0.08,
+                                    drop="cut")
+    assert mask.all()
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e8])
+def test_cut_drop_fig4_drops_the_interface_only(kappa):
+    prob, x, sig = fig4_grid(kappa)
+    _, _, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 2, x, sig, soc="material", theta=0.08,
+                                    drop="cut")
+    m = mask.astype(float)
+    # node 12 (low side): its low-low edges stay; the low-high edge has the
+    # closed form 1/sqrt(6 (4 kappa + 2)), i.e. 1/sqrt(24) * kappa^{-1/2} against
+    # 1/sqrt(24) for the low-low edge: a gap below theta = 0.08 opens only
+    # once kappa^{-1/2} < 0.08 (kappa = 1e2 gives 0.1: nothing is cut)
+    assert entry(prob, m, 12, 11) and entry(prob, m, 12, 7) and entry(prob, m, 12, 17)
+    cut = kappa ** -0.5 < 0.08
+    assert bool(entry(prob, m, 12, 13)) != cut
+    assert bool(entry(prob, m, 12, 8)) != cut and bool(entry(prob, m, 12, 18)) != cut
+    # inside the high region every edge is kept (no gap there)
+    assert entry(prob, m, 14, 15) and entry(prob, m, 14, 9) and entry(prob, m, 14, 19)
+    assert np.array_equal(mask, literal_cut_drop(prob, S, np.zeros(prob.n, bool), 0.08))
+
+
+@pytest.mark.parametrize("soc", ["material", "distance", "sa"])
+@pytest.mark.parametrize("theta", [0.08, 0.3, 0.6])
+def test_cut_drop_equals_the_literal_definition(soc, theta):
+    """Random full SPD tensors, jittered coordinates and Dirichlet faces: the
+    square-free evaluation equals the literal sorted definition."""
+    rng = np.random.default_rng(11)
+    prob = rotated_anisotropic_3d(n=6, block=2, seed=3)
+    n = prob.n
+    sig = oracle.clement(n, 3, prob.elem_nodes, prob.elem_sigma)
+    sig = sig * rng.uniform(0.5, 2.0, size=(n, 1)) ** 2
+    x = prob.coords + rng.normal(scale=0.01, size=prob.coords.shape)
+    d = oracle.detect_dirichlet(prob.rowptr, prob.col, prob.val)
+    _, _, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 3, x, sig, dirichlet=d, soc=soc,
+                                    theta=theta, drop="cut")
+    ref = literal_cut_drop(prob, S, d, theta)
+    assert np.array_equal(mask, ref)
+    # symmetric, diagonal kept, nothing strong at a Dirichlet node
+    rows = np.repeat(np.arange(n), np.diff(prob.rowptr))
+    M = np.zeros((n, n), dtype=bool)
+    M[rows, prob.col] = mask
+    assert np.array_equal(M, M.T)
+    assert M[np.arange(n), np.arange(n)].all()
+    off = M & ~np.eye(n, dtype=bool)
+    assert not off[d].any()
+
+
+def test_cut_drop_with_theta_one_keeps_the_largest_only():
+    """theta = 1: the first gap is at the largest value, so each row keeps
+    only its strongest entries (here the diagonal, S = 1 > every |S_ij|)."""
+    prob = config1_checkerboard_2d(n=8, cells=2)
+    sig = oracle.clement(prob.n, 2, prob.elem_nodes, prob.elem_sigma)
+    d = oracle.detect_dirichlet(prob.rowptr, prob.col, prob.val)
+    _, _, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 2, prob.coords, sig, dirichlet=d,
+                                    theta=1.0, drop="cut")
+    rows = np.repeat(np.arange(prob.n), np.diff(prob.rowptr))
+    assert np.array_equal(mask, rows == prob.col)
