@@ -56,7 +56,10 @@ typedef enum {
     AMG_SOC_SA = 2        /* classical |A_ij| / sqrt(|A_ii A_jj|) */
 } amg_soc;
 
-typedef enum { AMG_DROP_POINTWISE = 0 } amg_drop;
+/* dropping criterion C (section 2.1): pointwise |S_ij| >= theta, or cut-drop
+ * (each row's strengths in decreasing order are cut after the first pair
+ * with theta * s_k >= s_{k+1}; kept where both rows keep the entry) */
+typedef enum { AMG_DROP_POINTWISE = 0, AMG_DROP_CUT = 1 } amg_drop;
 typedef enum { AMG_PREC_FP64 = 0, AMG_PREC_FP32_HIER = 1 } amg_precision;
 typedef enum { AMG_SMOOTH_CHEBYSHEV = 0, AMG_SMOOTH_JACOBI = 1 } amg_smoother;
 

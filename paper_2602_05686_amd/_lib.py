@@ -24,6 +24,7 @@ PTR_HOST, PTR_DEVICE = 0, 1
 SOC = {"material": 0, "distance": 1, "sa": 2}
 SMOOTHER = {"chebyshev": 0, "jacobi": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
+DROP = {"pointwise": 0, "cut": 1}
 
 EXPORTED = [
     "amg_options_default", "amg_setup", "amg_pcg_solve", "amg_vcycle", "amg_level_spmv", "amg_hierarchy_info",
@@ -166,6 +167,8 @@ def options(dim=3, **kw) -> Options:
             v = SMOOTHER[v]
         elif k == "precision" and isinstance(v, str):
             v = PRECISION[v]
+        elif k == "drop" and isinstance(v, str):
+            v = DROP[v]
         setattr(o, k, v)
     return o
 

@@ -64,7 +64,7 @@ amg_status check_options(const amg_options& o) {
     if (o.dim < 1 || o.dim > 3) fail(AMG_ERR_INVALID_ARG, "dim must be 1, 2 or 3");
     if (!(o.theta >= 0.0 && o.theta <= 1.0)) fail(AMG_ERR_INVALID_ARG, "theta must lie in [0, 1]");
     if (o.soc < AMG_SOC_MATERIAL || o.soc > AMG_SOC_SA) fail(AMG_ERR_INVALID_ARG, "unknown strength measure");
-    if (o.drop != AMG_DROP_POINTWISE) fail(AMG_ERR_INVALID_ARG, "unknown dropping criterion");
+    if (o.drop != AMG_DROP_POINTWISE && o.drop != AMG_DROP_CUT) fail(AMG_ERR_INVALID_ARG, "unknown dropping criterion");
     if (o.smoother != AMG_SMOOTH_CHEBYSHEV && o.smoother != AMG_SMOOTH_JACOBI)
         fail(AMG_ERR_INVALID_ARG, "unknown smoother");
     if (o.max_coarse < 1) fail(AMG_ERR_INVALID_ARG, "max_coarse must be positive");

@@ -334,6 +334,10 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
         L.S.alloc((size_t)(nzl > 0 ? nzl : 1), mc);
         L.mask.alloc((size_t)(nzl > 0 ? nzl : 1), mc);
         soc_mask(L.A, L.dir.get(), lval.get(), ldiag.get(), opt.theta, L.S.get(), L.mask.get(), s);
+        if (opt.drop == AMG_DROP_CUT) {
+            DBuf<uint8_t> keep((size_t)(nzl > 0 ? nzl : 1), mc);
+            cut_drop(L.A, L.dir.get(), lval.get(), ldiag.get(), opt.theta, keep.get(), L.mask.get(), s);
+        }
         lval.release();
         ldiag.release();
         minv.release();

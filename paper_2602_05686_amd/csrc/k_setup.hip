@@ -13,6 +13,8 @@
 
 #include "device_util.h"
 #include "kernels.h"
+#include <algorithm>
+
 #include "setup_kernels.h"
 
 namespace matamg {
@@ -328,6 +330,95 @@ __global__ __launch_bounds__(kBlock) void k_soc_mask(MaskArgs a) {
         for (int t = threadIdx.x; t < rb.cnt; t += kBlock) mask_entry(a, rowof[t], rb.k0 + t);
     } else {
         for (int t = threadIdx.x; t < rb.cnt; t += kBlock) mask_entry(a, rb.r0, rb.k0 + t);
+    }
+}
+
+// ---------------------------------------------------------------- cut-drop
+// Cut-drop criterion (strength-of-connection section): row i keeps the
+// entries whose strength is at least s_k, s_k the first value of the
+// decreasingly ordered row with theta * s_k >= s_{k+1} (all if none).  The
+// row's strengths are compared through t_ij = (l_ij * l_ij) / L_jj (S_ij^2 L_ii
+// with the common L_ii dropped), t = L_ii for the diagonal and coincident
+// points, and the test is (theta*theta) * t_k >= t_{k+1}.  Instead of sorting,
+// every ordered entry a finds the next smaller key nxt(a) in its row: a gap
+// sits after a iff th2 * t_a >= nxt(a), and the first gap in decreasing order
+// is the one with the largest t_a.  One wavefront per row.
+__device__ __forceinline__ double cut_key(const int* col, const uint8_t* dir, const double* lval,
+                                          const double* ldiag, int i, double lii, int k, int hi) {
+    if (k >= hi) return -1.0;
+    const int j = col[k];
+    if (j == i) return lii;
+    if (dir && dir[j]) return -1.0;  // not ordered, never kept
+    const double l = lval[k];
+    if (l < 0.0) return lii;         // coincident points: S = 1
+    const double ljj = ldiag[j];
+    return ljj > 0.0 ? (l * l) / ljj : lii;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cut_keep(int n, const int* rowptr, const int* col, const uint8_t* dir,
+                                                     const double* lval, const double* ldiag, double th2,
+                                                     uint8_t* keep) {
+    const int lane = threadIdx.x & 63;
+    const int waves = (int)(gridDim.x * blockDim.x) >> 6;
+    for (int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); i < n; i += waves) {
+        const int lo = rowptr[i], hi = rowptr[i + 1];
+        if (dir && dir[i]) {
+            for (int k = lo + lane; k < hi; k += 64) keep[k] = col[k] == i;
+            continue;
+        }
+        const double lii = ldiag[i];
+        double cut = -1.0;  // keep every ordered entry
+        if (lii > 0.0) {
+            double best = -1.0;
+            for (int a0 = lo; a0 < hi; a0 += 64) {
+                const double ta = cut_key(col, dir, lval, ldiag, i, lii, a0 + lane, hi);
+                double nxt = -1.0;
+                for (int b0 = lo; b0 < hi; b0 += 64) {
+                    const double tb = cut_key(col, dir, lval, ldiag, i, lii, b0 + lane, hi);
+                    const int m = min(64, hi - b0);
+                    for (int q = 0; q < m; ++q) {
+                        const double v = __shfl(tb, q, 64);  // every lane takes part
+                        if (v >= 0.0 && v < ta && v > nxt) nxt = v;
+                    }
+                }
+                if (ta >= 0.0 && nxt >= 0.0 && th2 * ta >= nxt && ta > best) best = ta;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double o = __shfl_xor(best, off, 64);
+                best = o > best ? o : best;
+            }
+            cut = best;
+        }
+        for (int k0 = lo; k0 < hi; k0 += 64) {
+            const int k = k0 + lane;
+            const double t = cut_key(col, dir, lval, ldiag, i, lii, k, hi);
+            if (k < hi) keep[k] = (col[k] == i) || (t >= 0.0 && t >= cut);
+        }
+    }
+}
+
+// mask_ij = keep_ij and keep_ji (the entry (j, i) found by binary search)
+__global__ void k_cut_symmetric(int n, const int* rowptr, const int* col, const uint8_t* keep, uint8_t* mask) {
+    ROW_LOOP(i, n) {
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int j = col[k];
+            if (j == (int)i) {
+                mask[k] = 1;
+                continue;
+            }
+            int lo = rowptr[j], hi = rowptr[j + 1] - 1, kt = -1;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int c = col[mid];
+                if (c == (int)i) {
+                    kt = mid;
+                    break;
+                }
+                if (c < (int)i) lo = mid + 1;
+                else hi = mid - 1;
+            }
+            mask[k] = (keep[k] && kt >= 0 && keep[kt]) ? 1 : 0;
+        }
     }
 }
 
@@ -730,6 +821,15 @@ void soc_mask(const DCsr& A, const uint8_t* dir, const double* lval, const doubl
     MaskArgs a{A.rowptr.get(), A.col.get(), A.blk.get(), A.nblk, dir, lval, ldiag, theta * theta, S, mask};
     hipLaunchKernelGGL(k_soc_mask, dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a);
     MATAMG_LAUNCH_CHECK();
+}
+
+void cut_drop(const DCsr& A, const uint8_t* dir, const double* lval, const double* ldiag, double theta,
+              uint8_t* keep, uint8_t* mask, hipStream_t s) {
+    const int n = A.n;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_cut_keep, dim3(std::min(ceil_div(n, kBlock / 64), 8192)), dim3(kBlock), 0, s, n,
+                       A.rowptr.get(), A.col.get(), dir, lval, ldiag, theta * theta, keep);
+    LAUNCH(k_cut_symmetric, n, n, A.rowptr.get(), A.col.get(), (const uint8_t*)keep, mask);
 }
 
 void mis_init(int n, const uint8_t* dir, uint8_t* state, hipStream_t s) { LAUNCH(k_mis_init, n, n, dir, state); }

@@ -32,6 +32,10 @@ void soc_values(const DCsr& A, int dim, const double* x, const double* minv, con
 void soc_mask(const DCsr& A, const uint8_t* dir, const double* lval, const double* ldiag, double theta, double* S,
               uint8_t* mask, hipStream_t s);
 
+// cut-drop criterion in place of the pointwise mask: keep (nnz bytes of
+// scratch) holds each row's own choice, mask the symmetric result
+void cut_drop(const DCsr& A, const uint8_t* dir, const double* lval, const double* ldiag, double theta,
+              uint8_t* keep, uint8_t* mask, hipStream_t s);
 void mis_init(int n, const uint8_t* dir, uint8_t* state, hipStream_t s);
 // one synchronous round; *undecided (device) receives the number of nodes still undecided
 void mis_round(const DCsr& A, const uint8_t* mask, uint64_t key, uint8_t* state, uint64_t* t1, uint64_t* t2,

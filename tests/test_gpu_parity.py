@@ -250,3 +250,44 @@ def test_device_partition_equals_host_walk(amg, monkeypatch):
     prob = rotated_anisotropic_3d(n=24, block=8)
     h = amg.Hierarchy.from_problem(prob, max_coarse=50, precision="fp32")
     h.close()
+
+
+MODES = [("material", "cut"), ("sa", "pointwise"), ("sa", "cut"), ("distance", "pointwise"), ("distance", "cut")]
+
+
+@pytest.mark.parametrize("soc,drop", MODES)
+@pytest.mark.parametrize("name", ["checker64", "aniso16", "twodomain64"])
+def test_strength_modes_match_oracle(amg, name, soc, drop):
+    """The comparison strength measures (classical SA, Euclidean distance
+    Laplacian) and the cut-drop criterion: bitwise masks, aggregates and
+    patterns on every level, FP64 solution within 1e-6, iterations +-1."""
+    prob_fn, kw = CASES[name]
+    prob = prob_fn()
+    banner(f"{name}: soc={soc} drop={drop}")
+    try:
+        orc = oracle.Hierarchy(prob, soc=soc, drop=drop, **kw)
+    except oracle.OracleError as e:
+        # a measure that cannot coarsen this problem stagnates on both sides
+        assert e.code == oracle.STAGNATED
+        with pytest.raises(amg.AmgError) as ge:
+            amg.Hierarchy.from_problem(prob, soc=soc, drop=drop, **kw)
+        assert ge.value.status == "COARSENING_STAGNATED"
+        print(f"{name} {soc}/{drop}: coarsening stagnates (oracle and GPU)")
+        return
+    h = amg.Hierarchy.from_problem(prob, soc=soc, drop=drop, **kw)
+    st = h.stats()
+    assert st["levels"] == orc.nlev
+    for l in range(orc.nlev):
+        rp, ci, _ = h.level_csr(l, "A")
+        assert np.array_equal(rp, orc.get(l, "A_rowptr")) and np.array_equal(ci, orc.get(l, "A_col")), l
+        if l + 1 < orc.nlev:
+            assert np.array_equal(h.soc_mask(l), orc.get(l, "mask")), f"mask level {l}"
+            assert np.array_equal(h.aggregates(l), orc.get(l, "agg")), f"aggregates level {l}"
+    xo, io = orc.pcg(prob.b)
+    x, info = h.solve(prob.b)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"{name} {soc}/{drop}: levels {st['levels']} op.complexity {st['op_complexity']:.2f} "
+          f"iters gpu={info['iterations']} oracle={io['iterations']} rel_err={err:.1e}")
+    assert info["status"] == "OK"
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert err <= 1e-6
