@@ -198,6 +198,44 @@ def run_serving(args, amg, log):
     return out
 
 
+def run_compare(amg, log):
+    """The paper's central comparison (material vs classical SA vs Euclidean
+    distance measure, pointwise vs cut-drop) on the synthetic workloads:
+    levels, operator complexity C, PCG iterations to 1e-8 and cost C x iters."""
+    from workloads import (config1_checkerboard_2d, layered_stack_3d, rotated_anisotropic_3d, two_domain_2d)
+
+    cases = [
+        ("checkerboard 64^2, K in {1, 1e6}", lambda: config1_checkerboard_2d(), dict(max_coarse=100)),
+        ("two-domain h=1/128 kappa=1e2", lambda: two_domain_2d(n=256, kappa=1e2), dict()),
+        ("two-domain h=1/128 kappa=1e4", lambda: two_domain_2d(n=256, kappa=1e4), dict()),
+        ("two-domain h=1/512 kappa=1e4", lambda: two_domain_2d(n=1024, kappa=1e4), dict()),
+        ("rotated anisotropy 48^3", lambda: rotated_anisotropic_3d(n=48, block=8), dict()),
+        ("layered stack 64^3, 10 repeats", lambda: layered_stack_3d(n=64, repeats=10), dict()),
+    ]
+    rows = []
+    for name, fn, kw in cases:
+        prob = fn()
+        for soc in ("material", "distance", "sa"):
+            for drop in ("pointwise", "cut"):
+                rec = dict(workload=name, dof=prob.n, soc=soc, drop=drop, theta=0.08)
+                try:
+                    h = amg.Hierarchy.from_problem(prob, soc=soc, drop=drop, **kw)
+                except amg.AmgError as e:
+                    rec.update(status=e.status)
+                    rows.append(rec)
+                    continue
+                st = h.stats()
+                x, info = h.solve(prob.b, max_iter=1000, raise_on_error=False)
+                h.close()
+                rec.update(status=info["status"], levels=st["levels"], op_complexity=st["op_complexity"],
+                           iterations=info["iterations"], cost=st["op_complexity"] * info["iterations"],
+                           t_setup_ms=1e3 * st["t_setup_s"], t_solve_ms=1e3 * info["t_solve_s"])
+                rows.append(rec)
+                log(f"compare: {name} {soc}/{drop}: C={st['op_complexity']:.2f} iters={info['iterations']} "
+                    f"{info['status']}")
+    return {"metric": "strength-of-connection comparison", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +251,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream (its JSON object)")
+    ap.add_argument("--compare", action="store_true",
+                    help="run only the strength-measure / dropping comparison (its JSON object)")
     ap.add_argument("--serve-num", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
@@ -239,6 +279,9 @@ def main():
 
     if args.serving_only:
         print(json.dumps(run_serving(args, amg, log)), flush=True)
+        return
+    if args.compare:
+        print(json.dumps(run_compare(amg, log)), flush=True)
         return
 
     log(f"generating layered stack {args.n}^3, {args.repeats} repeats, {args.stretch:g}:1")
