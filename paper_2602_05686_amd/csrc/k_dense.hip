@@ -149,26 +149,27 @@ __global__ __launch_bounds__(kBlock) void k_syrk_update(double* A, int n, int kb
         }
 }
 
-// block row I of Y = L^{-1}: T_IJ = delta_IJ - sum_{K=J}^{I-1} L_IK Y_KJ, J <= I
-__global__ __launch_bounds__(kBlock) void k_trinv_rhs(const double* L, double* Y, int n, int I) {
+// Y = I (the right-hand side of L Y = I)
+__global__ void k_identity(double* Y, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) Y[(size_t)i * n + i] = 1.0;
+}
+
+// right-looking step after block row I of Y = L^{-1} is final:
+// Y_{I'J} -= L_{I'I} Y_{IJ} for every I' > I and J <= I (one tile per block)
+__global__ __launch_bounds__(kBlock) void k_trinv_update(const double* L, double* Y, int n, int nt, int I) {
     __shared__ double As[NB][KS + 1];
     __shared__ double Bs[KS][NB + 1];
-    const int J = blockIdx.x;
-    const int ri = I * NB, cj = J * NB;
-    const int rows = min(NB, n - ri), cols = min(NB, n - cj);
+    const int Ip = I + 1 + (int)blockIdx.x / (I + 1), J = (int)blockIdx.x % (I + 1);
+    if (Ip >= nt) return;
+    const int ri = Ip * NB, cj = J * NB, ok = I * NB;
+    const int rows = min(NB, n - ri), cols = min(NB, n - cj), kk = min(NB, n - ok);
     double acc[4][4] = {};
-    for (int K = J; K < I; ++K) {
-        const int ok = K * NB, kk = min(NB, n - ok);
-        tile_mac(acc, L + (size_t)ri * n + ok, n, false, rows, Y + (size_t)ok * n + cj, n, false, cols, kk, As, Bs);
-    }
+    tile_mac(acc, L + (size_t)ri * n + ok, n, false, rows, Y + (size_t)ok * n + cj, n, false, cols, kk, As, Bs);
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     for (int u = 0; u < 4; ++u)
         for (int v = 0; v < 4; ++v) {
             int i = ty * 4 + u, j = tx * 4 + v;
-            if (i < rows && j < cols) {
-                double delta = (I == J && i == j) ? 1.0 : 0.0;
-                Y[(size_t)(ri + i) * n + cj + j] = delta - acc[u][v];
-            }
+            if (i < rows && j < cols) Y[(size_t)(ri + i) * n + cj + j] -= acc[u][v];
         }
 }
 
@@ -249,12 +250,16 @@ bool dense_spd_inverse(int n, double* A, double* work, int* flag, hipStream_t s)
     int hflag = 0;
     d2h(&hflag, flag, 1, s);
     if (hflag) return false;
-    // Y = L^{-1}, block row by block row
+    // Y = L^{-1}, right-looking: block row I is solved with L_II once every
+    // earlier block row has been subtracted from it, then subtracted from all
+    // later block rows at once (a critical path of nt steps, not nt^2 / 2)
     MATAMG_HIP(hipMemsetAsync(work, 0, sizeof(double) * (size_t)n * n, s));
+    hipLaunchKernelGGL(k_identity, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, work, n);
     for (int I = 0; I < nt; ++I) {
-        hipLaunchKernelGGL(k_trinv_rhs, dim3(I + 1), dim3(kBlock), 0, s, A, work, n, I);
         const int ncols = min(n, (I + 1) * NB);
         hipLaunchKernelGGL(k_trinv_solve, dim3(ceil_div(ncols, kBlock)), dim3(kBlock), 0, s, A, work, n, I);
+        if (I + 1 < nt)
+            hipLaunchKernelGGL(k_trinv_update, dim3((nt - I - 1) * (I + 1)), dim3(kBlock), 0, s, A, work, n, nt, I);
     }
     // A^{-1} = Y^T Y
     hipLaunchKernelGGL(k_yty, dim3(nt * nt), dim3(kBlock), 0, s, work, A, n, nt);
