@@ -56,12 +56,15 @@ __device__ void tile_mac(double acc[4][4], const double* A, int lda, bool ta, in
     }
 }
 
-// factor the diagonal tile kb in LDS; flag <- 1 if not positive definite
-__global__ __launch_bounds__(kBlock) void k_potrf_diag(double* A, int n, int kb, int* flag) {
+// factor the diagonal tile kb in LDS; flag <- 1 if not positive definite.
+// One wavefront: its barriers cost next to nothing, and they dominate a
+// 64-step factorisation run by several waves.
+constexpr int kPotrfThreads = 64;
+__global__ __launch_bounds__(kPotrfThreads) void k_potrf_diag(double* A, int n, int kb, int* flag) {
     __shared__ double T[NB][NB + 1];
     const int o = kb * NB;
     const int nb = min(NB, n - o);
-    for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+    for (int e = threadIdx.x; e < nb * nb; e += kPotrfThreads) {
         int i = e / nb, j = e % nb;
         T[i][j] = A[(size_t)(o + i) * n + o + j];
     }
@@ -77,16 +80,16 @@ __global__ __launch_bounds__(kBlock) void k_potrf_diag(double* A, int n, int kb,
         }
         __syncthreads();
         const double ljj = T[j][j];
-        for (int i = j + 1 + threadIdx.x; i < nb; i += kBlock) T[i][j] = T[i][j] / ljj;
+        for (int i = j + 1 + threadIdx.x; i < nb; i += kPotrfThreads) T[i][j] = T[i][j] / ljj;
         __syncthreads();
         const int m = nb - j - 1;
-        for (int e = threadIdx.x; e < m * m; e += kBlock) {
+        for (int e = threadIdx.x; e < m * m; e += kPotrfThreads) {
             int i = j + 1 + e / m, k = j + 1 + e % m;
             if (k <= i) T[i][k] -= T[i][j] * T[k][j];
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < nb * nb; e += kBlock) {
+    for (int e = threadIdx.x; e < nb * nb; e += kPotrfThreads) {
         int i = e / nb, j = e % nb;
         A[(size_t)(o + i) * n + o + j] = (j <= i) ? T[i][j] : 0.0;
     }
@@ -237,7 +240,7 @@ bool dense_spd_inverse(int n, double* A, double* work, int* flag, hipStream_t s)
     MATAMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
     // Cholesky, lower triangle in place
     for (int kb = 0; kb < nt; ++kb) {
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(kBlock), 0, s, A, n, kb, flag);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(kPotrfThreads), 0, s, A, n, kb, flag);
         const int below = n - (kb + 1) * NB;
         if (below > 0) {
             hipLaunchKernelGGL(k_trsm_panel, dim3(ceil_div(below, kBlock)), dim3(kBlock), 0, s, A, n, kb);
