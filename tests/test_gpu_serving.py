@@ -220,3 +220,51 @@ def test_single_level_and_zero_rhs_requests(amg):
     assert t1["levels"] == 1 and i1["status"] == "OK" and true_relres(p1, x1) <= 1e-8
     x0, i0, _ = got[z]
     assert i0["status"] == "OK" and i0["iterations"] == 0 and not np.any(x0)
+
+
+def test_failed_setup_is_reported_and_the_server_goes_on(amg):
+    """A request whose setup fails (unsorted CSR columns, a non-SPD tensor)
+    finishes with that status and its message; requests around it are served."""
+    import copy
+
+    banner("server: failing requests in a stream")
+    good = poisson_box((8, 8, 8))
+    bad_csr = copy.deepcopy(good)
+    mid = good.n // 2  # an interior node: a full 27-entry row
+    lo = bad_csr.rowptr[mid]
+    assert bad_csr.rowptr[mid + 1] - lo == 27
+    bad_csr.col[lo], bad_csr.col[lo + 1] = bad_csr.col[lo + 1], bad_csr.col[lo]
+    bad_spd = copy.deepcopy(good)
+    bad_spd.elem_sigma[5] = -bad_spd.elem_sigma[5]
+    with amg.Server(precision="fp32", max_coarse=50) as srv:
+        ids = [srv.submit(p) for p in (good, bad_csr, good, bad_spd, good)]
+        got = {}
+        t0 = time.time()
+        while len(got) < len(ids):
+            for rid in srv.poll(timeout_s=5.0):
+                got[rid] = srv.result(rid)
+            assert time.time() - t0 < 60
+        st = srv.stats()
+    statuses = [got[r][1]["status"] for r in ids]
+    print(f"statuses {statuses}; messages {[got[r][1]['error'] for r in ids]}")
+    assert statuses == ["OK", "INVALID_ARG", "OK", "NOT_SPD", "OK"]
+    assert got[ids[1]][1]["error"] and got[ids[3]][1]["error"]
+    assert st["failed"] == 2 and st["completed"] == 3 and st["reserved_bytes"] == 0
+    for r in (ids[0], ids[2], ids[4]):
+        assert true_relres(good, got[r][0]) <= 1e-8
+
+
+def test_destroy_with_requests_in_flight(amg):
+    """Closing the server while requests wait, build or solve drops them
+    without hanging; a new server afterwards works."""
+    banner("server: destroy with work in flight")
+    probs = [layered_stack_3d(n=20, repeats=3, seed=s) for s in range(6)]
+    srv = amg.Server(precision="fp32", max_active=2, max_coarse=200)
+    for p in probs:
+        srv.submit(p)
+    time.sleep(0.05)
+    t0 = time.time()
+    srv.close()
+    assert time.time() - t0 < 30
+    out, st = serve(amg, probs[:2], "fp32", max_coarse=200)
+    assert st["completed"] == 2
