@@ -21,6 +21,7 @@ bounded sample of the same recipe.
 
 import argparse
 import json
+import math
 import os
 import platform
 import subprocess
@@ -206,9 +207,9 @@ def run_compare(amg, log):
 
     cases = [
         ("checkerboard 64^2, K in {1, 1e6}", lambda: config1_checkerboard_2d(), dict(max_coarse=100)),
-        ("two-domain h=1/128 kappa=1e2", lambda: two_domain_2d(n=256, kappa=1e2), dict()),
-        ("two-domain h=1/128 kappa=1e4", lambda: two_domain_2d(n=256, kappa=1e4), dict()),
-        ("two-domain h=1/512 kappa=1e4", lambda: two_domain_2d(n=1024, kappa=1e4), dict()),
+        ("two-domain h=1/128 kappa=1e2", lambda: two_domain_2d(n=128, kappa=1e2), dict()),
+        ("two-domain h=1/128 kappa=1e4", lambda: two_domain_2d(n=128, kappa=1e4), dict()),
+        ("two-domain h=1/512 kappa=1e4", lambda: two_domain_2d(n=512, kappa=1e4), dict()),
         ("rotated anisotropy 48^3", lambda: rotated_anisotropic_3d(n=48, block=8), dict()),
         ("layered stack 64^3, 10 repeats", lambda: layered_stack_3d(n=64, repeats=10), dict()),
     ]
@@ -236,6 +237,115 @@ def run_compare(amg, log):
     return {"metric": "strength-of-connection comparison", "rows": rows}
 
 
+SWEEP_THETAS = (0.0, 0.0025, 0.005, 0.01, 0.02, 0.04, 0.08, 0.16, 0.32, 0.64)
+MODES = (("material", "pointwise"), ("material", "cut"), ("distance", "pointwise"), ("distance", "cut"),
+         ("sa", "pointwise"), ("sa", "cut"))
+
+
+def _solve_record(amg, prob, rec, max_iter, **kw):
+    """setup + FP64 PCG to 1e-8 from zero; fills levels, C, iterations, cost, times"""
+    try:
+        h = amg.Hierarchy.from_problem(prob, **kw)
+    except amg.AmgError as e:
+        rec.update(status=e.status)
+        return rec
+    st = h.stats()
+    _, info = h.solve(prob.b, max_iter=max_iter, raise_on_error=False)
+    h.close()
+    rec.update(status=info["status"], levels=st["levels"], op_complexity=st["op_complexity"],
+               iterations=info["iterations"], cost=st["op_complexity"] * info["iterations"],
+               t_setup_ms=1e3 * st["t_setup_s"], t_solve_ms=1e3 * info["t_solve_s"])
+    return rec
+
+
+def run_sweep(args, amg, log):
+    """The two-domain study (section "Two domain problem", Figs. 6-7): PCG
+    iterations and cost C x iterations over the drop tolerance for every
+    strength measure x dropping criterion, h in {1/32, 1/128, 1/512} (h = 1 /
+    elements per direction), kappa in {1, 1e2, 1e4}."""
+    from workloads import two_domain_2d
+
+    rows = []
+    for n in args.sweep_n:
+        for kappa in (1.0, 1e2, 1e4):
+            prob = two_domain_2d(n=n, kappa=kappa)
+            for soc, drop in MODES:
+                line = []
+                for theta in SWEEP_THETAS:
+                    rec = _solve_record(amg, prob, dict(h=f"1/{n}", dof=prob.n, kappa=kappa, soc=soc, drop=drop,
+                                                         theta=theta), args.sweep_max_iter,
+                                        soc=soc, drop=drop, theta=theta)
+                    rows.append(rec)
+                    line.append(_cell(rec))
+                log(f"sweep h=1/{n} kappa={kappa:g} {soc}/{drop}: " + " ".join(line))
+    for line in _sweep_tables(rows):
+        log(line)
+    return {"metric": "two-domain drop-tolerance sweep", "thetas": list(SWEEP_THETAS), "rows": rows}
+
+
+def _cell(rec, cost=False):
+    if rec.get("status") != "OK":
+        return "-"
+    return f"{rec['cost']:.1f}" if cost else str(rec["iterations"])
+
+
+def _sweep_tables(rows):
+    """markdown tables: one per (h, kappa), a row per measure/criterion, a column per theta"""
+    out = []
+    keys = []
+    for r in rows:
+        if (r["h"], r["kappa"]) not in keys:
+            keys.append((r["h"], r["kappa"]))
+    for cost in (False, True):
+        for hh, kappa in keys:
+            out.append(f"{'cost C x iterations' if cost else 'iterations'}, h = {hh}, kappa = {kappa:g}")
+            out.append("| measure / criterion | " + " | ".join(f"{t:g}" for t in SWEEP_THETAS) + " |")
+            out.append("|---|" + "---|" * len(SWEEP_THETAS))
+            for soc, drop in MODES:
+                cells = {r["theta"]: _cell(r, cost) for r in rows
+                         if r["h"] == hh and r["kappa"] == kappa and r["soc"] == soc and r["drop"] == drop}
+                out.append(f"| {soc} / {drop} | " + " | ".join(cells.get(t, "") for t in SWEEP_THETAS) + " |")
+    return out
+
+
+def run_annulus(args, amg, log):
+    """The annulus parameter study (section "Anisotropic thermal diffusion",
+    Table 1): material distance Laplacian with pointwise dropping, theta in
+    {0.05, 0.1}, kappa = 10^0..10^4, the base mesh of 20 x 150 x 1 hexes and
+    its refinements down to h / 2^max_refine; iterations, levels and C."""
+    from workloads import annulus_3d
+
+    rows = []
+    kappas = (1.0, 10.0, 100.0, 1e3, 1e4)
+    for refine in range(args.annulus_max_refine + 1):
+        for kappa in kappas:
+            t0 = time.perf_counter()
+            prob = annulus_3d(refine, kappa=kappa)
+            t_asm = time.perf_counter() - t0
+            for theta in (0.05, 0.1):
+                rec = _solve_record(amg, prob, dict(refine=refine, h=f"h/{1 << refine}", dof=prob.n, nnz=prob.nnz,
+                                                    kappa=kappa, theta=theta), args.annulus_max_iter, theta=theta)
+                rows.append(rec)
+                log(f"annulus {rec['h']} ({prob.n} DOF, assembled in {t_asm:.1f} s) kappa={kappa:g} "
+                    f"theta={theta}: {rec.get('iterations')} its ({rec.get('levels')}, "
+                    f"{rec.get('op_complexity', float('nan')):.2f}) {rec['status']} "
+                    f"setup {rec.get('t_setup_ms', float('nan')):.0f} ms solve {rec.get('t_solve_ms', float('nan')):.0f} ms")
+            del prob
+    hs = [f"h/{1 << r}" if r else "h" for r in range(args.annulus_max_refine + 1)]
+    for theta in (0.05, 0.1):
+        log(f"theta = {theta}")
+        log("| log10 kappa | " + " | ".join(hs) + " |")
+        log("|---|" + "---|" * len(hs))
+        for kappa in kappas:
+            cells = []
+            for r in range(args.annulus_max_refine + 1):
+                rec = next(x for x in rows if x["refine"] == r and x["kappa"] == kappa and x["theta"] == theta)
+                cells.append(f"{rec['iterations']} ({rec['levels']}, {rec['op_complexity']:.2f})"
+                             if rec["status"] == "OK" else rec["status"])
+            log(f"| {math.log10(kappa):.0f} | " + " | ".join(cells) + " |")
+    return {"metric": "annulus parameter study", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +363,14 @@ def main():
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream (its JSON object)")
     ap.add_argument("--compare", action="store_true",
                     help="run only the strength-measure / dropping comparison (its JSON object)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run only the two-domain drop-tolerance sweep (its JSON object)")
+    ap.add_argument("--sweep-n", type=int, nargs="+", default=[32, 128, 512],
+                    help="two-domain elements per direction (h = 1/n)")
+    ap.add_argument("--sweep-max-iter", type=int, default=1000)
+    ap.add_argument("--annulus", action="store_true", help="run only the annulus parameter study (its JSON object)")
+    ap.add_argument("--annulus-max-refine", type=int, default=4)
+    ap.add_argument("--annulus-max-iter", type=int, default=1000)
     ap.add_argument("--serve-num", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
@@ -282,6 +400,12 @@ def main():
         return
     if args.compare:
         print(json.dumps(run_compare(amg, log)), flush=True)
+        return
+    if args.sweep:
+        print(json.dumps(run_sweep(args, amg, log)), flush=True)
+        return
+    if args.annulus:
+        print(json.dumps(run_annulus(args, amg, log)), flush=True)
         return
 
     log(f"generating layered stack {args.n}^3, {args.repeats} repeats, {args.stretch:g}:1")

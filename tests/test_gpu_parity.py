@@ -13,8 +13,8 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads.q1 import (config1_checkerboard_2d, layered_stack_3d, poisson_box, rotated_anisotropic_3d,
-                          two_domain_2d)
+from workloads.q1 import (annulus_3d, config1_checkerboard_2d, layered_stack_3d, poisson_box,
+                          rotated_anisotropic_3d, two_domain_2d)
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +41,9 @@ CASES = {
     "aniso16": (lambda: rotated_anisotropic_3d(n=16, block=8), dict(max_coarse=100)),
     "twodomain64": (lambda: two_domain_2d(n=64, kappa=1e4), dict(max_coarse=50)),
     "layered24_tall": (lambda: layered_stack_3d(n=24, repeats=3, stretch=0.1), dict(max_coarse=200)),
+    # the anisotropic annulus: base mesh (2 levels) and one refinement (3 levels)
+    "annulus_h": (lambda: annulus_3d(0, kappa=1e4), dict(theta=0.05)),
+    "annulus_h2": (lambda: annulus_3d(1, kappa=1e4), dict(theta=0.05)),
 }
 # Layered stacks with a 1e10 conductivity contrast are so ill conditioned that
 # FP64 determines the solution only to ~1e-5 in the modes of the floating

@@ -15,6 +15,9 @@ from .q1 import (  # noqa: F401
     rotated_anisotropic_3d,
     two_domain_2d,
     poisson_box,
+    structured_hex_nodes,
+    assemble_hex,
+    annulus_3d,
     serving_stream,
     problem_from_request,
 )

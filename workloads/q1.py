@@ -41,6 +41,9 @@ __all__ = [
     "rotated_anisotropic_3d",
     "two_domain_2d",
     "poisson_box",
+    "structured_hex_nodes",
+    "assemble_hex",
+    "annulus_3d",
     "serving_stream",
     "problem_from_request",
 ]
@@ -150,18 +153,26 @@ class _Q1Input(ctypes.Structure):
                 ("dmask", ctypes.c_void_p), ("g", ctypes.c_void_p)]
 
 
+class _HexInput(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int64), ("n1", ctypes.c_int64), ("n2", ctypes.c_int64),
+                ("periodic1", ctypes.c_int32), ("X", ctypes.c_void_p), ("sig", ctypes.c_void_p),
+                ("fe", ctypes.c_void_p), ("dmask", ctypes.c_void_p), ("g", ctypes.c_void_p)]
+
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "q1asm.c")
+_SRCS = [os.path.join(_HERE, "q1asm.c"), os.path.join(_HERE, "q1hex.c")]
 _SO = os.path.join(_HERE, "_q1asm.so")
 _lib_cache = []
 _lib_lock = threading.Lock()
 
 
 def build_fast(force=False):
-    """Compile q1asm.c into workloads/_q1asm.so (gcc, no contraction)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+    """Compile q1asm.c and q1hex.c into workloads/_q1asm.so (gcc, no contraction)."""
+    stale = not os.path.exists(_SO) or any(os.path.getmtime(_SO) < os.path.getmtime(src) for src in _SRCS)
+    if force or stale:
         tmp = _SO + f".{os.getpid()}.tmp"
-        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", _SRC, "-o", tmp], check=True)
+        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", *_SRCS, "-lm", "-o", tmp],
+                       check=True)
         os.replace(tmp, _SO)
     return _SO
 
@@ -177,6 +188,15 @@ def _fast_lib():
                 lib.q1_fill_3d.restype = None
                 lib.q1_fill_3d.argtypes = [ctypes.POINTER(_Q1Input), ctypes.c_void_p, ctypes.c_int64,
                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+                lib.hex_elements.restype = ctypes.c_int
+                lib.hex_elements.argtypes = [ctypes.POINTER(_HexInput), ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_void_p]
+                lib.hex_rowptr.restype = ctypes.c_int64
+                lib.hex_rowptr.argtypes = [ctypes.POINTER(_HexInput), ctypes.c_void_p]
+                lib.hex_fill.restype = None
+                lib.hex_fill.argtypes = [ctypes.POINTER(_HexInput), ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]
             except (OSError, subprocess.CalledProcessError, FileNotFoundError):
                 lib = None
             _lib_cache.append(lib)
@@ -355,6 +375,134 @@ def assemble_q1(name, shape, lengths, elem_sigma, f_elem, dirichlet_fn, meta=Non
         dirichlet=dmask, g=g, meta=dict(meta or {}),
     )
     return prob
+
+
+def _split_run(fn, count, threads, serial_below=100000):
+    """fn(lo, hi) over [0, count) in `threads` contiguous ranges (ctypes calls release the GIL)."""
+    threads = max(1, min(threads or min(8, os.cpu_count() or 1), count))
+    if threads == 1 or count < serial_below:
+        return [fn(0, count)]
+    cuts = np.linspace(0, count, threads + 1).astype(np.int64)
+    out = [None] * threads
+
+    def work(t):
+        out[t] = fn(int(cuts[t]), int(cuts[t + 1]))
+
+    ths = [threading.Thread(target=work, args=(t,)) for t in range(threads)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    return out
+
+
+def structured_hex_nodes(shape, periodic1=False):
+    """Element connectivity [nelem, 8] of a structured hex index space whose
+    second direction may wrap around (node j = n1 is node 0)."""
+    n0, n1, n2 = (int(v) for v in shape)
+    N0, N1 = n0 + 1, (n1 if periodic1 else n1 + 1)
+    e2, e1, e0 = np.meshgrid(np.arange(n2), np.arange(n1), np.arange(n0), indexing="ij")
+    e0, e1, e2 = (v.reshape(-1).astype(np.int64) for v in (e0, e1, e2))
+    nodes = np.empty((e0.shape[0], 8), dtype=np.int32)
+    for a in range(8):
+        j = e1 + ((a >> 1) & 1)
+        if periodic1:
+            j = j % n1
+        nodes[:, a] = e0 + (a & 1) + N0 * (j + N1 * (e2 + ((a >> 2) & 1)))
+    return nodes
+
+
+def assemble_hex(name, shape, coords, elem_sigma, f_elem, dmask, g, periodic1=False, lengths=None, meta=None,
+                 threads=None):
+    """Q1 on a structured mesh of general (trilinear) hexahedra, assembled by
+    q1hex.c: 2x2x2 Gauss quadrature, symmetric Dirichlet elimination as in
+    assemble_q1.  coords [n, 3] in the node order of structured_hex_nodes;
+    f_elem [nelem] or None (no source)."""
+    lib = _fast_lib()
+    if lib is None:
+        raise RuntimeError("the C assembler (workloads/q1hex.c) did not build")
+    n0, n1, n2 = (int(v) for v in shape)
+    if min(n0, n1, n2) < 1 or (periodic1 and n1 < 3):
+        raise ValueError("need at least one element per direction (three around a periodic direction)")
+    N1 = n1 if periodic1 else n1 + 1
+    n = (n0 + 1) * N1 * (n2 + 1)
+    nelem = n0 * n1 * n2
+    X = np.ascontiguousarray(coords, dtype=np.float64)
+    sig = np.ascontiguousarray(elem_sigma, dtype=np.float64).reshape(nelem, 9)
+    if X.shape != (n, 3):
+        raise ValueError("coords must be [n, 3]")
+    dm = np.ascontiguousarray(np.asarray(dmask, dtype=bool).astype(np.uint8))
+    gg = np.ascontiguousarray(np.where(dm != 0, np.asarray(g, dtype=np.float64), 0.0))
+    fe = None if f_elem is None else np.ascontiguousarray(f_elem, dtype=np.float64)
+    inp = _HexInput(n0, n1, n2, int(bool(periodic1)), X.ctypes.data, sig.ctypes.data,
+                    None if fe is None else fe.ctypes.data, dm.ctypes.data, gg.ctypes.data)
+    Ke = np.empty((nelem, 64))
+    Le = None if fe is None else np.empty((nelem, 8))
+    rcs = _split_run(lambda lo, hi: lib.hex_elements(ctypes.byref(inp), lo, hi, Ke.ctypes.data,
+                                                      None if Le is None else Le.ctypes.data),
+                     nelem, threads, serial_below=20000)
+    if any(rc != 0 for rc in rcs):
+        raise ValueError("degenerate hexahedron (zero or non-finite Jacobian)")
+    rp = np.empty(n + 1, dtype=np.int64)
+    nnz = lib.hex_rowptr(ctypes.byref(inp), rp.ctypes.data)
+    if nnz >= 2**31:
+        raise ValueError("nnz exceeds int32 indexing")
+    col = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    b = np.empty(n, dtype=np.float64)
+    _split_run(lambda lo, hi: lib.hex_fill(ctypes.byref(inp), Ke.ctypes.data,
+                                           None if Le is None else Le.ctypes.data, rp.ctypes.data, lo, hi,
+                                           col.ctypes.data, val.ctypes.data, b.ctypes.data), n, threads)
+    del Ke, Le
+    return Problem(
+        name=name, dim=3, shape=(n0, n1, n2), lengths=tuple(lengths) if lengths else (0.0, 0.0, 0.0),
+        rowptr=rp.astype(np.int32), col=col, val=val, b=b, coords=X,
+        elem_nodes=structured_hex_nodes(shape, periodic1), elem_sigma=sig.reshape(nelem, 3, 3),
+        dirichlet=dm.astype(bool), g=gg, meta=dict(meta or {}),
+    )
+
+
+ANNULUS_BASE = (20, 150, 1)
+
+
+def annulus_3d(refine=0, kappa=1e4, r_in=0.5, r_out=1.0, thickness=0.1, base=ANNULUS_BASE, g_in=0.0, g_out=1.0,
+               g_cos=0.5, threads=None):
+    """The paper's anisotropic thermal-diffusion annulus (section "Anisotropic
+    thermal diffusion"): r_in < r < r_out, 0 < z < thickness, base mesh
+    base = (radial, circumferential, thickness) hexahedra, each direction
+    refined 2^refine times.  Nodes lie on the circles r_i = r_in + (r_out -
+    r_in) i / n_r at angles 2 pi j / n_phi; elements are the trilinear hexes
+    through them.  sigma_e = kappa t t^T + r r^T + z z^T with t the
+    circumferential and r the radial unit vector at the element's centre
+    angle (high conductivity around the ring).  Dirichlet u = g_in on the
+    inner and u = g_out + g_cos cos(phi) on the outer surface, natural
+    conditions on the two flat faces, no source."""
+    f = 1 << int(refine)
+    n0, n1, n2 = base[0] * f, base[1] * f, base[2] * f
+    N0, N1, N2 = n0 + 1, n1, n2 + 1
+    k, j, i = np.meshgrid(np.arange(N2), np.arange(N1), np.arange(N0), indexing="ij")
+    i, j, k = (v.reshape(-1) for v in (i, j, k))
+    r = r_in + (r_out - r_in) * (i / n0)
+    phi = (2.0 * math.pi) * (j / n1)
+    coords = np.stack([r * np.cos(phi), r * np.sin(phi), thickness * (k / n2)], axis=1)
+    del k, j, r
+    e1 = np.tile(np.repeat(np.arange(n1), n0), n2)
+    pc = (2.0 * math.pi) * ((e1 + 0.5) / n1)
+    c, s = np.cos(pc), np.sin(pc)
+    sig = np.zeros((e1.shape[0], 3, 3))
+    sig[:, 0, 0] = kappa * (s * s) + c * c
+    sig[:, 1, 1] = kappa * (c * c) + s * s
+    sig[:, 0, 1] = (1.0 - kappa) * (c * s)
+    sig[:, 1, 0] = sig[:, 0, 1]
+    sig[:, 2, 2] = 1.0
+    del e1, pc, c, s
+    dmask = (i == 0) | (i == n0)
+    g = np.where(i == n0, float(g_out) + float(g_cos) * np.cos(phi), float(g_in))
+    return assemble_hex("annulus3d", (n0, n1, n2), coords, sig, None, dmask, g, periodic1=True,
+                        lengths=(r_out - r_in, 2.0 * math.pi, thickness),
+                        meta=dict(refine=int(refine), kappa=float(kappa), r_in=r_in, r_out=r_out,
+                                  thickness=thickness, base=tuple(base), g_in=g_in, g_out=g_out, g_cos=g_cos),
+                        threads=threads)
 
 
 def _iso(kvals, dim):
