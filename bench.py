@@ -262,7 +262,8 @@ def run_sweep(args, amg, log):
     """The two-domain study (section "Two domain problem", Figs. 6-7): PCG
     iterations and cost C x iterations over the drop tolerance for every
     strength measure x dropping criterion, h in {1/32, 1/128, 1/512} (h = 1 /
-    elements per direction), kappa in {1, 1e2, 1e4}."""
+    elements per direction), kappa in {1, 1e2, 1e4}, coarsening down to at
+    most 50 unknowns so that even the 33 x 33 node mesh has several levels."""
     from workloads import two_domain_2d
 
     rows = []
@@ -274,7 +275,7 @@ def run_sweep(args, amg, log):
                 for theta in SWEEP_THETAS:
                     rec = _solve_record(amg, prob, dict(h=f"1/{n}", dof=prob.n, kappa=kappa, soc=soc, drop=drop,
                                                          theta=theta), args.sweep_max_iter,
-                                        soc=soc, drop=drop, theta=theta)
+                                        soc=soc, drop=drop, theta=theta, max_coarse=50)
                     rows.append(rec)
                     line.append(_cell(rec))
                 log(f"sweep h=1/{n} kappa={kappa:g} {soc}/{drop}: " + " ".join(line))

@@ -470,10 +470,14 @@ static int cmp_desc(const void *a, const void *b)
  * entries whose strength is at least s_k; drop nothing when no such k exists.
  *
  * Readings (the paper leaves them open):
- *  - the ordered row includes the diagonal, S_ii = 1;
+ *  - the ordered row holds the off-diagonal entries only; the diagonal is
+ *    always kept.  The two-domain study reports cut-drop as the robust
+ *    criterion at large tolerances, where the pointwise one stagnates: that
+ *    holds only if the strongest off-diagonal entry always survives, which
+ *    an ordered diagonal (S_ii = 1 above every S_ij) would prevent;
  *  - the row's strengths are compared through the square-free key
  *      t_ij = (l_ij * l_ij) / L_jj   (= S_ij^2 L_ii, L_ii common to the row),
- *    with t_ii = L_ii for the diagonal and for coincident points (S = 1), and
+ *    with t = L_ii for coincident points (S = 1), and
  *    theta * s_k >= s_{k+1} as (theta*theta) * t_k >= t_{k+1};  an entry with
  *    L_jj <= 0 has S = 1 like the pointwise form, so t = L_ii;
  *  - a row with L_ii <= 0 (no positive coupling) keeps every entry;
@@ -512,7 +516,8 @@ static int cut_drop(int n, const int32_t *rowptr, const int32_t *col, const unsi
         for (int k = k0; k < k1; ++k) {
             const int j = col[k];
             tk[k] = -1.0;  /* not ordered */
-            if (j == i || coinc[k]) tk[k] = lii;
+            if (j == i) continue;
+            if (coinc[k]) tk[k] = lii;
             else if (dir && dir[j]) continue;
             else tk[k] = (ldiag[j] > 0.0) ? (lval[k] * lval[k]) / ldiag[j] : lii;
             ord[m++] = tk[k];

@@ -338,8 +338,10 @@ __global__ __launch_bounds__(kBlock) void k_soc_mask(MaskArgs a) {
 // entries whose strength is at least s_k, s_k the first value of the
 // decreasingly ordered row with theta * s_k >= s_{k+1} (all if none).  The
 // row's strengths are compared through t_ij = (l_ij * l_ij) / L_jj (S_ij^2 L_ii
-// with the common L_ii dropped), t = L_ii for the diagonal and coincident
-// points, and the test is (theta*theta) * t_k >= t_{k+1}.  Instead of sorting,
+// with the common L_ii dropped), t = L_ii for coincident points, and the test
+// is (theta*theta) * t_k >= t_{k+1}.  Only off-diagonal entries are ordered
+// (the diagonal is always kept), so the strongest connection of a row always
+// survives the row's own cut.  Instead of sorting,
 // every ordered entry a finds the next smaller key nxt(a) in its row: a gap
 // sits after a iff th2 * t_a >= nxt(a), and the first gap in decreasing order
 // is the one with the largest t_a.  One wavefront per row.
@@ -347,7 +349,7 @@ __device__ __forceinline__ double cut_key(const int* col, const uint8_t* dir, co
                                           const double* ldiag, int i, double lii, int k, int hi) {
     if (k >= hi) return -1.0;
     const int j = col[k];
-    if (j == i) return lii;
+    if (j == i) return -1.0;         // the diagonal is not ordered (always kept)
     if (dir && dir[j]) return -1.0;  // not ordered, never kept
     const double l = lval[k];
     if (l < 0.0) return lii;         // coincident points: S = 1

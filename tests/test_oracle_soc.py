@@ -178,10 +178,10 @@ def test_clement_2d_corner_edge_counts():
 # ----------------------------------------------------------------- cut-drop
 def literal_cut_drop(prob, S, dirichlet, theta):
     """The cut-drop criterion as the paper states it, on the strength values
-    S (with the square root): per row, order |S_ij| decreasingly (diagonal
-    S_ii = 1 included), k = first position with theta*s_k >= s_{k+1}, keep
-    |S_ij| >= s_k (everything if no such k); then keep (i, j) only if both
-    rows keep it.  Edges touching a Dirichlet node are dropped."""
+    S (with the square root): per row, order the off-diagonal |S_ij|
+    decreasingly, k = first position with theta*s_k >= s_{k+1}, keep
+    |S_ij| >= s_k (everything if no such k) and the diagonal; then keep (i, j)
+    only if both rows keep it.  Edges touching a Dirichlet node are dropped."""
     n = prob.n
     keep = np.zeros(len(prob.col), dtype=bool)
     for i in range(n):
@@ -189,7 +189,8 @@ def literal_cut_drop(prob, S, dirichlet, theta):
         if dirichlet[i]:
             keep[lo:hi] = prob.col[lo:hi] == i
             continue
-        ks = [k for k in range(lo, hi) if prob.col[k] == i or not dirichlet[prob.col[k]]]
+        ks = [k for k in range(lo, hi) if prob.col[k] != i and not dirichlet[prob.col[k]]]
+        keep[lo:hi] = prob.col[lo:hi] == i
         vals = sorted((abs(S[k]) for k in ks), reverse=True)
         cut = -1.0
         for p in range(len(vals) - 1):
@@ -261,12 +262,50 @@ def test_cut_drop_equals_the_literal_definition(soc, theta):
 
 
 def test_cut_drop_with_theta_one_keeps_the_largest_only():
-    """theta = 1: the first gap is at the largest value, so each row keeps
-    only its strongest entries (here the diagonal, S = 1 > every |S_ij|)."""
+    """theta = 1: the first gap follows the largest value, so each row keeps
+    only its strongest off-diagonal entries (all of them on a tie); an edge
+    survives when it is the strongest for both of its nodes."""
     prob = config1_checkerboard_2d(n=8, cells=2)
     sig = oracle.clement(prob.n, 2, prob.elem_nodes, prob.elem_sigma)
     d = oracle.detect_dirichlet(prob.rowptr, prob.col, prob.val)
     _, _, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 2, prob.coords, sig, dirichlet=d,
                                     theta=1.0, drop="cut")
-    rows = np.repeat(np.arange(prob.n), np.diff(prob.rowptr))
-    assert np.array_equal(mask, rows == prob.col)
+    n = prob.n
+    rows = np.repeat(np.arange(n), np.diff(prob.rowptr))
+    ordered = (rows != prob.col) & ~d[rows] & ~d[prob.col]
+    best = np.zeros(n)
+    np.maximum.at(best, rows[ordered], np.abs(S[ordered]))
+    strongest = np.zeros((n, n), dtype=bool)
+    strongest[rows[ordered], prob.col[ordered]] = np.abs(S[ordered]) == best[rows[ordered]]
+    expect = (strongest & strongest.T)[rows, prob.col] | (rows == prob.col)
+    assert np.array_equal(mask, expect)
+    assert (mask & (rows != prob.col)).any()
+
+
+def test_cut_drop_uniform_grid_closed_form():
+    """Uniform 2D Q1 grid, isotropic material: an interior row has four axis
+    edges with S = 1/6 and four diagonal edges with S = 1/12 (distance
+    Laplacian weights 1/h^2 and 1/(2h^2), L_ii = 6/h^2).  The single gap, of
+    ratio 1/2, opens once theta > 1/2: below that every edge stays, above it
+    only the axis edges do.  Pointwise dropping at such tolerances keeps no
+    edge at all (1/6 < theta)."""
+    prob = poisson_box((10, 10), lengths=(1.0, 1.0), dirichlet="none")
+    x = prob.coords
+    n = prob.n
+    sig = np.tile([1.0, 0.0, 1.0], (n, 1))
+    rows = np.repeat(np.arange(n), np.diff(prob.rowptr))
+    side = 11
+    ix, iy = np.arange(n) % side, np.arange(n) // side
+    interior = (ix > 1) & (ix < side - 2) & (iy > 1) & (iy < side - 2)
+    sel = interior[rows] & (rows != prob.col)
+    axis = (ix[rows] == ix[prob.col]) | (iy[rows] == iy[prob.col])
+    for theta, keep_diag in ((0.4, True), (0.49, True), (0.51, False), (0.64, False)):
+        _, _, S, mask = oracle.strength(prob.rowptr, prob.col, prob.val, 2, x, sig, soc="material",
+                                        theta=theta, drop="cut")
+        assert np.allclose(np.abs(S[sel & axis]), 1 / 6, rtol=1e-14)
+        assert np.allclose(np.abs(S[sel & ~axis]), 1 / 12, rtol=1e-14)
+        assert mask[sel & axis].all()
+        assert bool(mask[sel & ~axis].all()) == keep_diag and bool(mask[sel & ~axis].any()) == keep_diag
+        _, _, _, pw = oracle.strength(prob.rowptr, prob.col, prob.val, 2, x, sig, soc="material",
+                                      theta=theta, drop="pointwise")
+        assert not pw[sel].any()
