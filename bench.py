@@ -313,33 +313,35 @@ def run_annulus(args, amg, log):
     """The annulus parameter study (section "Anisotropic thermal diffusion",
     Table 1): material distance Laplacian with pointwise dropping, theta in
     {0.05, 0.1}, kappa = 10^0..10^4, the base mesh of 20 x 150 x 1 hexes and
-    its refinements down to h / 2^max_refine; iterations, levels and C."""
+    its refinements h / 2^k; iterations, levels and C."""
     from workloads import annulus_3d
 
     rows = []
     kappas = (1.0, 10.0, 100.0, 1e3, 1e4)
-    for refine in range(args.annulus_max_refine + 1):
+    for refine in args.annulus_refine:
         for kappa in kappas:
             t0 = time.perf_counter()
             prob = annulus_3d(refine, kappa=kappa)
             t_asm = time.perf_counter() - t0
             for theta in (0.05, 0.1):
-                rec = _solve_record(amg, prob, dict(refine=refine, h=f"h/{1 << refine}", dof=prob.n, nnz=prob.nnz,
-                                                    kappa=kappa, theta=theta), args.annulus_max_iter, theta=theta)
+                label = f"h/{1 << refine}" if refine else "h"
+                rec = _solve_record(amg, prob, dict(refine=refine, h=label, dof=prob.n, nnz=prob.nnz, kappa=kappa,
+                                                    theta=theta), args.annulus_max_iter, theta=theta,
+                                    max_coarse=args.annulus_max_coarse)
                 rows.append(rec)
                 log(f"annulus {rec['h']} ({prob.n} DOF, assembled in {t_asm:.1f} s) kappa={kappa:g} "
                     f"theta={theta}: {rec.get('iterations')} its ({rec.get('levels')}, "
                     f"{rec.get('op_complexity', float('nan')):.2f}) {rec['status']} "
                     f"setup {rec.get('t_setup_ms', float('nan')):.0f} ms solve {rec.get('t_solve_ms', float('nan')):.0f} ms")
             del prob
-    hs = [f"h/{1 << r}" if r else "h" for r in range(args.annulus_max_refine + 1)]
+    hs = [f"h/{1 << r}" if r else "h" for r in args.annulus_refine]
     for theta in (0.05, 0.1):
         log(f"theta = {theta}")
         log("| log10 kappa | " + " | ".join(hs) + " |")
         log("|---|" + "---|" * len(hs))
         for kappa in kappas:
             cells = []
-            for r in range(args.annulus_max_refine + 1):
+            for r in args.annulus_refine:
                 rec = next(x for x in rows if x["refine"] == r and x["kappa"] == kappa and x["theta"] == theta)
                 cells.append(f"{rec['iterations']} ({rec['levels']}, {rec['op_complexity']:.2f})"
                              if rec["status"] == "OK" else rec["status"])
@@ -370,8 +372,10 @@ def main():
                     help="two-domain elements per direction (h = 1/n)")
     ap.add_argument("--sweep-max-iter", type=int, default=1000)
     ap.add_argument("--annulus", action="store_true", help="run only the annulus parameter study (its JSON object)")
-    ap.add_argument("--annulus-max-refine", type=int, default=4)
+    ap.add_argument("--annulus-refine", type=int, nargs="+", default=[0, 1, 2, 3, 4],
+                    help="refinement levels k of the annulus base mesh (element size h / 2^k)")
     ap.add_argument("--annulus-max-iter", type=int, default=1000)
+    ap.add_argument("--annulus-max-coarse", type=int, default=5000, help="coarsest-level size target")
     ap.add_argument("--serve-num", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
