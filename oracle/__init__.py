@@ -75,6 +75,7 @@ def lib():
         L.orc_strength.argtypes = [i32, P, P, P, i32, P, P, P, i32, i32, f64, P, P, P, P]
         L.orc_aggregate.argtypes = [i32, P, P, P, P, u64, i32, P, P, P, P]
         L.orc_setup.argtypes = [i32, P, P, P, i32, i32, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(P)]
+        L.orc_setup_reuse.argtypes = [P, P, P, P, ctypes.POINTER(P)]
         L.orc_free.argtypes = [P]
         L.orc_free.restype = None
         L.orc_num_levels.argtypes = [P]
@@ -211,7 +212,24 @@ class Hierarchy:
                  agg=9, mask=10, x=11, sig=12, ldiag=13, S=14, dirichlet=15, dinv=16, lval=17, chol=18)
 
     def __init__(self, prob=None, *, rowptr=None, col=None, val=None, elem_nodes=None, elem_sigma=None,
-                 coords=None, options=None, **kw):
+                 coords=None, options=None, reuse=None, **kw):
+        """reuse: an oracle Hierarchy on the same sparsity pattern whose
+        coordinates, tensors, masks, aggregates and depth are kept; only the
+        value-dependent steps run on the new values (its options apply)."""
+        if reuse is not None:
+            if prob is not None:
+                rowptr, col, val = prob.rowptr, prob.col, prob.val
+            rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+            ci = np.ascontiguousarray(col, dtype=np.int32)
+            va = np.ascontiguousarray(val, dtype=np.float64)
+            h = ctypes.c_void_p()
+            code = lib().orc_setup_reuse(reuse._h, _p(rp), _p(ci), _p(va), ctypes.byref(h))
+            self._h = h
+            _check(code, "setup_reuse")
+            self.options = reuse.options
+            self.nlev = lib().orc_num_levels(h)
+            self.n = rp.shape[0] - 1
+            return
         if prob is not None:
             rowptr, col, val = prob.rowptr, prob.col, prob.val
             elem_nodes, elem_sigma, coords = prob.elem_nodes, prob.elem_sigma, prob.coords

@@ -920,13 +920,31 @@ static int csr_copy(Csr *dst, int n, int m, const int32_t *rp, const int32_t *ci
  * level cap leaves more than max_coarse unknowns, or a level fails to shrink,
  * the status is ORC_STAGNATED.  The coarsest operator is factored densely.
  */
-int orc_setup(int n, const int32_t *rowptr, const int32_t *col, const double *val, int nelem, int npe,
-              const int32_t *elem_nodes, const double *elem_sigma, const double *coords,
-              const OrcOptions *opt, void **out)
+static void *dup_bytes(const void *src, size_t bytes)
+{
+    void *p = malloc(bytes > 0 ? bytes : 1);
+    if (p && bytes) memcpy(p, src, bytes);
+    return p;
+}
+
+/*
+ * With prev == NULL: the full setup.  With prev: the same construction for
+ * new values of A on prev's sparsity pattern, where everything that does not
+ * depend on A's values is taken from prev instead of being recomputed --
+ * coordinates and nodal tensors, strength values, drop masks, aggregates and
+ * the number of levels -- and everything else (diagonals, filtered matrix,
+ * damping, prolongator, Galerkin products, smoother bounds, coarse factor) is
+ * computed from the new values as above.  The Dirichlet rows found in the new
+ * values must be prev's.
+ */
+static int setup_impl(int n, const int32_t *rowptr, const int32_t *col, const double *val, int nelem, int npe,
+                      const int32_t *elem_nodes, const double *elem_sigma, const double *coords,
+                      const OrcOptions *opt, const Hier *prev, void **out)
 {
     *out = NULL;
     if (n <= 0 || !opt || opt->dim < 1 || opt->dim > 3 || opt->max_levels < 1 || opt->max_levels > 16)
         return ORC_INVALID_ARG;
+    if (prev && (prev->lev[0].A.n != n || prev->lev[0].A.rowptr[n] != rowptr[n])) return ORC_INVALID_ARG;
     Hier *h = (Hier *)calloc(1, sizeof(Hier));
     if (!h) return ORC_OUT_OF_MEMORY;
     h->opt = *opt;
@@ -937,12 +955,22 @@ int orc_setup(int n, const int32_t *rowptr, const int32_t *col, const double *va
     L0->dim = d;
     rc = csr_copy(&L0->A, n, n, rowptr, col, val);
     if (rc) goto fail;
-    L0->x = (double *)malloc(sizeof(double) * (size_t)n * d);
-    L0->sig = (double *)malloc(sizeof(double) * (size_t)n * ncomp);
-    if (!L0->x || !L0->sig) { rc = ORC_OUT_OF_MEMORY; goto fail; }
-    memcpy(L0->x, coords, sizeof(double) * (size_t)n * d);
-    rc = orc_clement(n, d, nelem, npe, elem_nodes, elem_sigma, L0->sig);
-    if (rc) goto fail;
+    if (prev) {
+        for (int k = 0; k <= n; ++k)
+            if (rowptr[k] != prev->lev[0].A.rowptr[k]) { rc = ORC_INVALID_ARG; goto fail; }
+        for (int k = 0; k < rowptr[n]; ++k)
+            if (col[k] != prev->lev[0].A.col[k]) { rc = ORC_INVALID_ARG; goto fail; }
+        L0->x = (double *)dup_bytes(prev->lev[0].x, sizeof(double) * (size_t)n * d);
+        L0->sig = (double *)dup_bytes(prev->lev[0].sig, sizeof(double) * (size_t)n * ncomp);
+        if (!L0->x || !L0->sig) { rc = ORC_OUT_OF_MEMORY; goto fail; }
+    } else {
+        L0->x = (double *)malloc(sizeof(double) * (size_t)n * d);
+        L0->sig = (double *)malloc(sizeof(double) * (size_t)n * ncomp);
+        if (!L0->x || !L0->sig) { rc = ORC_OUT_OF_MEMORY; goto fail; }
+        memcpy(L0->x, coords, sizeof(double) * (size_t)n * d);
+        rc = orc_clement(n, d, nelem, npe, elem_nodes, elem_sigma, L0->sig);
+        if (rc) goto fail;
+    }
 
     for (int l = 0;; ++l) {
         Level *L = &h->lev[l];
@@ -956,7 +984,7 @@ int orc_setup(int n, const int32_t *rowptr, const int32_t *col, const double *va
                 if (L->A.col[k] == i) di = L->A.val[k];
             L->dinv[i] = (di != 0.0) ? 1.0 / di : 0.0;
         }
-        if (nl <= opt->max_coarse || l + 1 >= opt->max_levels) {
+        if (prev ? l + 1 == prev->nlev : (nl <= opt->max_coarse || l + 1 >= opt->max_levels)) {
             if (nl > opt->max_coarse) { rc = ORC_STAGNATED; goto fail; }
             break;
         }
@@ -968,12 +996,25 @@ int orc_setup(int n, const int32_t *rowptr, const int32_t *col, const double *va
         L->agg = (int *)malloc(sizeof(int) * (size_t)nl);
         if (!L->dir || !L->lval || !L->ldiag || !L->S || !L->mask || !L->agg) { rc = ORC_OUT_OF_MEMORY; goto fail; }
         if (l == 0) orc_detect_dirichlet(nl, L->A.rowptr, L->A.col, L->A.val, L->dir);
-        rc = orc_strength(nl, L->A.rowptr, L->A.col, L->A.val, d, L->x, L->sig, L->dir, opt->soc, opt->drop,
-                          opt->theta, L->lval, L->ldiag, L->S, L->mask);
-        if (rc) goto fail;
-        rc = orc_aggregate(nl, L->A.rowptr, L->A.col, L->mask, L->dir, opt->seed, l, L->agg, &L->nc,
-                           &L->mis_rounds, NULL);
-        if (rc) goto fail;
+        if (prev) {
+            const Level *Q = &prev->lev[l];
+            if (Q->A.n != nl || Q->A.rowptr[nl] != nnz) { rc = ORC_INVALID_ARG; goto fail; }
+            if (memcmp(L->dir, Q->dir, (size_t)nl) != 0) { rc = ORC_INVALID_ARG; goto fail; }
+            memcpy(L->lval, Q->lval, sizeof(double) * (size_t)nnz);
+            memcpy(L->ldiag, Q->ldiag, sizeof(double) * (size_t)nl);
+            memcpy(L->S, Q->S, sizeof(double) * (size_t)nnz);
+            memcpy(L->mask, Q->mask, (size_t)nnz);
+            memcpy(L->agg, Q->agg, sizeof(int) * (size_t)nl);
+            L->nc = Q->nc;
+            L->mis_rounds = Q->mis_rounds;
+        } else {
+            rc = orc_strength(nl, L->A.rowptr, L->A.col, L->A.val, d, L->x, L->sig, L->dir, opt->soc, opt->drop,
+                              opt->theta, L->lval, L->ldiag, L->S, L->mask);
+            if (rc) goto fail;
+            rc = orc_aggregate(nl, L->A.rowptr, L->A.col, L->mask, L->dir, opt->seed, l, L->agg, &L->nc,
+                               &L->mis_rounds, NULL);
+            if (rc) goto fail;
+        }
         if (L->nc <= 0 || L->nc >= nl) { rc = ORC_STAGNATED; goto fail; }
         rc = build_prolongator(L, opt, l);
         if (rc) goto fail;
@@ -1021,6 +1062,23 @@ int orc_setup(int n, const int32_t *rowptr, const int32_t *col, const double *va
 fail:
     orc_free(h);
     return rc;
+}
+
+int orc_setup(int n, const int32_t *rowptr, const int32_t *col, const double *val, int nelem, int npe,
+              const int32_t *elem_nodes, const double *elem_sigma, const double *coords,
+              const OrcOptions *opt, void **out)
+{
+    return setup_impl(n, rowptr, col, val, nelem, npe, elem_nodes, elem_sigma, coords, opt, NULL, out);
+}
+
+/* Setup for new values of A reusing prev's coordinates, tensors, masks,
+ * aggregates and depth (setup_impl above); prev's options apply. */
+int orc_setup_reuse(const void *prev, const int32_t *rowptr, const int32_t *col, const double *val, void **out)
+{
+    const Hier *p = (const Hier *)prev;
+    *out = NULL;
+    if (!p || p->nlev < 1) return ORC_INVALID_ARG;
+    return setup_impl(p->lev[0].A.n, rowptr, col, val, 0, 0, NULL, NULL, NULL, &p->opt, p, out);
 }
 
 /*
