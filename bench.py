@@ -349,6 +349,86 @@ def run_annulus(args, amg, log):
     return {"metric": "annulus parameter study", "rows": rows}
 
 
+def run_reuse(args, amg, log):
+    """Setup reuse on the bench workload: a material update (the layer
+    conductivities redrawn) applied with amg_update_values on the kept
+    coarsening against a fresh setup, and successive right-hand sides on one
+    hierarchy (setup cost amortised over K solves)."""
+    import torch
+
+    from workloads.q1 import layered_stack_3d
+
+    dev = torch.device("cuda:0")
+
+    def to_dev(prob):
+        return dict(rowptr=torch.from_numpy(prob.rowptr).to(dev), col=torch.from_numpy(prob.col).to(dev),
+                    val=torch.from_numpy(prob.val).to(dev), en=torch.from_numpy(prob.elem_nodes).to(dev),
+                    es=torch.from_numpy(prob.elem_sigma).to(dev), xc=torch.from_numpy(prob.coords).to(dev),
+                    b=torch.from_numpy(prob.b).to(dev))
+
+    def setup(d, opts):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = amg.Hierarchy(d["rowptr"], d["col"], d["val"], d["en"], d["es"], d["xc"], opts)
+        torch.cuda.synchronize()
+        return h, time.perf_counter() - t0
+
+    def solve(h, b):
+        x = torch.zeros_like(b)
+        _, info = h.solve(b, x, max_iter=args.reuse_max_iter, raise_on_error=False)
+        return x, info
+
+    log(f"reuse: generating layered stack {args.n}^3 with seeds 0 and 1")
+    p0 = layered_stack_3d(n=args.n, repeats=args.repeats, stretch=args.stretch, seed=0)
+    p1 = layered_stack_3d(n=args.n, repeats=args.repeats, stretch=args.stretch, seed=1)
+    d0, d1 = to_dev(p0), to_dev(p1)
+    del p0
+    opts = amg.options(dim=3)
+    h, _ = setup(d0, opts)  # warm-up of the allocator and the kernels
+    h.close()
+    h, t_setup0 = setup(d0, opts)
+    _, i0 = solve(h, d0["b"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.update_values(d1["val"])
+    t_update = time.perf_counter() - t0
+    _, ir = solve(h, d1["b"])
+    st_r = h.stats()
+    h.close()
+    f, t_setup1 = setup(d1, opts)
+    _, if_ = solve(f, d1["b"])
+    st_f = f.stats()
+    log(f"reuse: setup {t_setup0 * 1e3:.0f} ms (seed 0, {i0['iterations']} its); update {t_update * 1e3:.0f} ms "
+        f"-> {ir['iterations']} its {ir['status']}; fresh setup {t_setup1 * 1e3:.0f} ms -> {if_['iterations']} its")
+    # successive right-hand sides b_k = A x_k, x_k seeded uniform, on the fresh hierarchy
+    rng = np.random.default_rng(7)
+    solves = []
+    for k in range(args.reuse_rhs):
+        xk = torch.from_numpy(rng.uniform(-1.0, 1.0, p1.n)).to(dev)
+        bk = torch.empty_like(xk)
+        f.level_spmv(0, xk, bk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = solve(f, bk)
+        torch.cuda.synchronize()
+        solves.append(dict(t_s=time.perf_counter() - t0, iterations=info["iterations"], status=info["status"]))
+    f.close()
+    amort = []
+    for K in (1, 2, 4, 8, 16):
+        if K <= len(solves):
+            t = t_setup1 + sum(x["t_s"] for x in solves[:K])
+            amort.append(dict(rhs=K, dof_per_s=p1.n * K / t, setup_share=t_setup1 / t))
+    log("reuse: " + ", ".join(f"K={a['rhs']}: {a['dof_per_s'] / 1e6:.2f} M DOF/s (setup {100 * a['setup_share']:.0f}%)"
+                               for a in amort))
+    return {"metric": "setup reuse", "workload": f"layered stack {args.n}^3, {args.repeats} repeats, "
+                                                 f"{args.stretch:g}:1, seeds 0 -> 1",
+            "dof": p1.n, "t_setup_s": t_setup0, "t_update_s": t_update, "t_update_lib_s": st_r["t_update_s"],
+            "iterations_before": i0["iterations"], "iterations_updated": ir["iterations"],
+            "status_updated": ir["status"], "op_complexity_updated": st_r["op_complexity"],
+            "t_setup_fresh_s": t_setup1, "iterations_fresh": if_["iterations"],
+            "op_complexity_fresh": st_f["op_complexity"], "rhs_solves": solves, "amortised": amort}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,6 +456,10 @@ def main():
                     help="refinement levels k of the annulus base mesh (element size h / 2^k)")
     ap.add_argument("--annulus-max-iter", type=int, default=1000)
     ap.add_argument("--annulus-max-coarse", type=int, default=5000, help="coarsest-level size target")
+    ap.add_argument("--reuse", action="store_true",
+                    help="run only the setup-reuse measurement (material update, successive right-hand sides)")
+    ap.add_argument("--reuse-rhs", type=int, default=16)
+    ap.add_argument("--reuse-max-iter", type=int, default=1000)
     ap.add_argument("--serve-num", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
@@ -411,6 +495,9 @@ def main():
         return
     if args.annulus:
         print(json.dumps(run_annulus(args, amg, log)), flush=True)
+        return
+    if args.reuse:
+        print(json.dumps(run_reuse(args, amg, log)), flush=True)
         return
 
     log(f"generating layered stack {args.n}^3, {args.repeats} repeats, {args.stretch:g}:1")

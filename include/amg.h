@@ -104,6 +104,7 @@ typedef struct {
     double t_setup_s;
     int64_t device_bytes;              /* device memory held by the hierarchy */
     int64_t device_peak_bytes;         /* most device memory held at once during setup and solves */
+    double t_update_s;                 /* duration of the last amg_update_values (0: none yet) */
 } amg_hierarchy_stats;
 
 /* Fill *o with the defaults listed above (dim = 3). */
@@ -147,6 +148,31 @@ amg_status amg_setup(int64_t n, const int32_t* rowptr, const int32_t* col, const
  */
 amg_status amg_pcg_solve(amg_hierarchy* h, const double* b, double* x, double tol, int32_t max_iter,
                          amg_ptr_kind kind, void* hip_stream, amg_solve_info* info);
+
+/*
+ * New values of A on the setup's sparsity pattern, for instance after a
+ * change of material.  The paper weighs the material measure's higher setup
+ * cost against solves that reuse one hierarchy (numerical results, thermally
+ * activated batteries); this keeps the costly, value-independent part of the
+ * setup.  The drop masks, aggregates,
+ * number of levels, coordinates and nodal tensors of amg_setup are kept; the
+ * diagonals, filtered matrices, damping factors, prolongators, restrictions,
+ * Galerkin products, smoother bounds, coarse inverse and FP32 copies are
+ * recomputed from val exactly as amg_setup computes them.  For a material
+ * that leaves the strength measure unchanged the result is the hierarchy
+ * amg_setup would build; otherwise it is a valid preconditioner built on the
+ * old coarsening (its quality may differ from a fresh setup's).
+ *
+ * val   FP64 [nnz] values on the rowptr/col pattern given to amg_setup
+ * kind  whether val is a host or a device pointer; the call returns after
+ *       the update is complete on hip_stream
+ * Errors: INVALID_ARG (null arguments, bad kind, or the rows whose
+ * off-diagonals are all exactly zero -- the Dirichlet rows -- differ from
+ * the setup's; the hierarchy is left unchanged), NOT_SPD (the new coarsest
+ * operator is not positive definite; the hierarchy must then be freed), HIP.
+ * Not to be called while a solve on the same hierarchy is running.
+ */
+amg_status amg_update_values(amg_hierarchy* h, const double* val, amg_ptr_kind kind, void* hip_stream);
 
 /* z = M^{-1} r: one V-cycle.  r, z FP64 [n] device pointers. */
 amg_status amg_vcycle(amg_hierarchy* h, const double* r, double* z, void* hip_stream);

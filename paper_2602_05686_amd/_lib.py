@@ -27,7 +27,8 @@ PRECISION = {"fp64": 0, "fp32": 1}
 DROP = {"pointwise": 0, "cut": 1}
 
 EXPORTED = [
-    "amg_options_default", "amg_setup", "amg_pcg_solve", "amg_vcycle", "amg_level_spmv", "amg_hierarchy_info",
+    "amg_options_default", "amg_setup", "amg_pcg_solve", "amg_update_values", "amg_vcycle", "amg_level_spmv",
+    "amg_hierarchy_info",
     "amg_get_aggregates", "amg_get_soc_mask", "amg_get_level_csr", "amg_get_level_aux", "amg_time_smoother",
     "amg_free", "amg_status_string", "amg_last_error",
     "amg_server_create", "amg_server_submit", "amg_server_poll", "amg_server_result", "amg_server_info",
@@ -83,6 +84,7 @@ class HierStats(ctypes.Structure):
         ("t_setup_s", ctypes.c_double),
         ("device_bytes", ctypes.c_int64),
         ("device_peak_bytes", ctypes.c_int64),
+        ("t_update_s", ctypes.c_double),
     ]
 
 
@@ -122,6 +124,7 @@ def load():
     L.amg_setup.argtypes = [i64, P, P, P, i64, i32, P, P, P, ctypes.POINTER(Options), i32, P, ctypes.POINTER(P)]
     L.amg_pcg_solve.argtypes = [P, P, P, f64, i32, i32, P, ctypes.POINTER(SolveInfo)]
     L.amg_vcycle.argtypes = [P, P, P, P]
+    L.amg_update_values.argtypes = [P, P, i32, P]
     L.amg_level_spmv.argtypes = [P, i32, P, P, P]
     L.amg_hierarchy_info.argtypes = [P, ctypes.POINTER(HierStats)]
     L.amg_get_aggregates.argtypes = [P, i32, P]
@@ -249,6 +252,17 @@ class Hierarchy:
         return x, dict(status=STATUS[code], iterations=info.iterations, rel_res=info.rel_res_true,
                        t_solve_s=info.t_solve_s)
 
+    def update_values(self, val, stream=None):
+        """New values of A on the setup's pattern (numpy array or device
+        tensor): masks, aggregates, coordinates and tensors are kept, the
+        value-dependent parts of the setup are recomputed."""
+        if isinstance(val, np.ndarray):
+            va = np.ascontiguousarray(val, dtype=np.float64)
+            code = load().amg_update_values(self._h, _hp(va), PTR_HOST, _stream(stream))
+        else:
+            code = load().amg_update_values(self._h, _dp(val), PTR_DEVICE, _stream(stream))
+        check(code, "amg_update_values")
+
     def vcycle(self, r, z, stream=None):
         check(load().amg_vcycle(self._h, _dp(r), _dp(z), _stream(stream)), "amg_vcycle")
 
@@ -271,7 +285,7 @@ class Hierarchy:
                     mis_rounds=list(s.mis_rounds[:L]), omega=list(s.omega[:L]), lam_pf=list(s.lam_pf[:L]),
                     lam_cheb=list(s.lam_cheb[:L]), op_complexity=s.op_complexity,
                     vcycle_alg_bytes=s.vcycle_alg_bytes, t_setup_s=s.t_setup_s, device_bytes=s.device_bytes,
-                    device_peak_bytes=s.device_peak_bytes)
+                    device_peak_bytes=s.device_peak_bytes, t_update_s=s.t_update_s)
 
     def aggregates(self, level):
         n = self.stats()["n"][level]

@@ -154,6 +154,16 @@ amg_status amg_pcg_solve(amg_hierarchy* hh, const double* b, double* x, double t
     });
 }
 
+amg_status amg_update_values(amg_hierarchy* hh, const double* val, amg_ptr_kind kind, void* hip_stream) {
+    return guarded([&]() -> amg_status {
+        Hierarchy& h = H(hh);
+        if (!val) fail(AMG_ERR_INVALID_ARG, "null values");
+        if (kind != AMG_PTR_HOST && kind != AMG_PTR_DEVICE) fail(AMG_ERR_INVALID_ARG, "bad pointer kind");
+        update_values(h, val, kind == AMG_PTR_HOST, (hipStream_t)hip_stream);
+        return AMG_OK;
+    });
+}
+
 amg_status amg_vcycle(amg_hierarchy* hh, const double* r, double* z, void* hip_stream) {
     return guarded([&]() -> amg_status {
         Hierarchy& h = H(hh);
@@ -198,6 +208,7 @@ amg_status amg_hierarchy_info(const amg_hierarchy* hh, amg_hierarchy_stats* st) 
         st->t_setup_s = h.t_setup;
         st->device_bytes = h.mem.bytes;
         st->device_peak_bytes = h.mem.peak;
+        st->t_update_s = h.t_update;
         return AMG_OK;
     });
 }

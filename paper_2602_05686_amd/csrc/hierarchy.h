@@ -44,6 +44,7 @@ struct Hierarchy {
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // captured CG steps, by parity
     bool use_graphs = true;
     double t_setup = 0.0;
+    double t_update = 0.0;   // duration of the last update_values
     bool fp32 = false;
 
     ~Hierarchy();
@@ -65,6 +66,10 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n, const int* rowptr, const i
                                            int64_t nelem, int npe, const int* elem_nodes,
                                            const double* elem_sigma, const double* coords,
                                            const amg_options& opt, bool host_ptrs, hipStream_t s);
+
+// new values of A on the setup's pattern; masks, aggregates, coordinates and
+// tensors are kept, every value-dependent quantity is recomputed
+void update_values(Hierarchy& h, const double* val, bool host_ptrs, hipStream_t s);
 
 amg_status pcg_solve(Hierarchy& h, const double* b, double* x, double tol, int max_iter, bool host_ptrs,
                      hipStream_t s, amg_solve_info* info);

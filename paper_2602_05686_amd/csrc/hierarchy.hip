@@ -226,21 +226,112 @@ void Hierarchy::release_setup_data() {
 
 DotTarget Hierarchy::dt(int slot) const { return DotTarget{partial.get(), counter.get(), scal.get() + slot}; }
 
+namespace {
+
+// filtered matrix, 1-norm diagonal, damping and smoothed prolongator of
+// level l from its operator, drop mask and aggregates; sets lam_pf and omega
+void smoothed_prolongator(Hierarchy& h, int l, DCsr& P, hipStream_t s) {
+    Level& L = h.lev[l];
+    const amg_options& opt = h.opt;
+    MemCounter* mc = &h.mem;
+    const int nl = L.A.n;
+    DCsr F;
+    F.n = F.m = nl;
+    DBuf<int> cnt(nl, mc), tmp(scan_tmp_size(nl), mc);
+    filter_count(L.A, L.mask.get(), cnt.get(), s);
+    F.rowptr.alloc((size_t)nl + 1, mc);
+    exclusive_scan(cnt.get(), F.rowptr.get(), nl, tmp.get(), s);
+    int fnnz = 0;
+    d2h(&fnnz, F.rowptr.get() + nl, 1, s);
+    F.nnz = fnnz;
+    F.col.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
+    F.val.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
+    DBuf<double> dt(nl, mc), dtinv(nl, mc);
+    filter_fill(L.A, L.mask.get(), F.rowptr.get(), F.col.get(), F.val.get(), dt.get(), dtinv.get(), s);
+    make_blocks(F, mc, s);
+    ensure_partial(h, std::max(stream_partials(F), stream_partials(L.A)));
+    L.lam_pf = power_method(F, dtinv.get(), opt.power_iters, stream_key(opt.seed, kPurposePf, l), h, s);
+    L.omega = L.lam_pf > 0.0 ? opt.omega_sym / L.lam_pf : 0.0;
+    DCsr Ph;
+    Ph.n = nl;
+    Ph.m = L.nc;
+    phat_counts(nl, L.agg.get(), cnt.get(), s);
+    Ph.rowptr.alloc((size_t)nl + 1, mc);
+    exclusive_scan(cnt.get(), Ph.rowptr.get(), nl, tmp.get(), s);
+    int pn = 0;
+    d2h(&pn, Ph.rowptr.get() + nl, 1, s);
+    Ph.nnz = pn;
+    Ph.col.alloc((size_t)(pn > 0 ? pn : 1), mc);
+    Ph.val.alloc((size_t)(pn > 0 ? pn : 1), mc);
+    phat_fill(nl, L.agg.get(), Ph.rowptr.get(), Ph.col.get(), Ph.val.get(), s);
+    spgemm(F, Ph, P, mc, s);
+    prolongator_finalize(nl, P.rowptr.get(), P.col.get(), P.val.get(), L.agg.get(), dt.get(), L.omega, s);
+}
+
+// Chebyshev bounds and coefficients of every smoothing level
+void smoother_bounds(Hierarchy& h, hipStream_t s) {
+    for (int k = 0; k + 1 < h.nlev; ++k) {
+        Level& L = h.lev[k];
+        L.lam_cheb = power_method(L.A, L.dinv.get(), h.opt.power_iters, stream_key(h.opt.seed, kPurposeCheb, k), h,
+                                  s);
+        smoother_coefficients(L, h.opt);
+    }
+}
+
+// dense inverse of the coarsest operator through its Cholesky factor
+void coarse_inverse(Hierarchy& h, int* flag, hipStream_t s) {
+    Level& C = h.lev[h.nlev - 1];
+    const int nc = C.A.n;
+    h.nL = nc;
+    if (h.Ainv.size() != (size_t)nc * nc) h.Ainv.alloc((size_t)nc * nc, &h.mem);
+    MATAMG_HIP(hipMemsetAsync(h.Ainv.get(), 0, sizeof(double) * (size_t)nc * nc, s));
+    densify(nc, C.A.rowptr.get(), C.A.col.get(), C.A.val.get(), h.Ainv.get(), s);
+    DBuf<double> work((size_t)nc * nc, &h.mem);
+    if (!dense_spd_inverse(nc, h.Ainv.get(), work.get(), flag, s))
+        fail(AMG_ERR_NOT_SPD, "coarsest operator is not positive definite (n=" + std::to_string(nc) + ")");
+}
+
+// FP32 copies of A, D^{-1}, P and R on the smoothing levels
+void cast_fp32(Hierarchy& h, hipStream_t s) {
+    MemCounter* mc = &h.mem;
+    for (int k = 0; k + 1 < h.nlev; ++k) {
+        Level& L = h.lev[k];
+        const int nl = L.A.n;
+        if (!L.A.val32) L.A.val32.alloc((size_t)(L.A.nnz > 0 ? L.A.nnz : 1), mc);
+        cast_vec<double, float>(L.A.nnz, L.A.val.get(), L.A.val32.get(), s);
+        if (!L.dinv32) L.dinv32.alloc(nl, mc);
+        cast_vec<double, float>(nl, L.dinv.get(), L.dinv32.get(), s);
+        if (!L.P.val32) L.P.val32.alloc((size_t)(L.P.nnz > 0 ? L.P.nnz : 1), mc);
+        cast_vec<double, float>(L.P.nnz, L.P.val.get(), L.P.val32.get(), s);
+        if (!L.R.val32) L.R.val32.alloc((size_t)(L.R.nnz > 0 ? L.R.nnz : 1), mc);
+        cast_vec<double, float>(L.R.nnz, L.R.val.get(), L.R.val32.get(), s);
+    }
+}
+
+// a setup's or update's temporaries come from the pool in the order of its
+// stream, unless the caller's thread already set a scope (the solve
+// server's workers do)
+struct SetupAllocScope {
+    AllocStreamScope scope;
+    static hipStream_t pick(hipStream_t s) {
+        if (!alloc_mode().pooled && pool_enabled()) {
+            int dev = 0;
+            MATAMG_HIP(hipGetDevice(&dev));
+            keep_pool_memory(dev);
+        }
+        return alloc_mode().pooled ? alloc_mode().stream : s;
+    }
+    explicit SetupAllocScope(hipStream_t s) : scope(pick(s), alloc_mode().pooled || pool_enabled()) {}
+};
+
+}  // namespace
+
 std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const int* col, const double* val,
                                            int64_t nelem, int npe, const int* elem_nodes,
                                            const double* elem_sigma, const double* coords,
                                            const amg_options& opt, bool host_ptrs, hipStream_t s) {
     const double t0 = now_s();
-    // setup allocates and frees many temporaries: take them from the pool in
-    // the order of the setup stream (unless the caller's thread already set a
-    // scope, as the solve server's workers do)
-    const bool scoped = alloc_mode().pooled;
-    if (!scoped && pool_enabled()) {
-        int dev = 0;
-        MATAMG_HIP(hipGetDevice(&dev));
-        keep_pool_memory(dev);
-    }
-    AllocStreamScope scope(scoped ? alloc_mode().stream : s, scoped || pool_enabled());
+    SetupAllocScope scope(s);
     auto hp = std::make_unique<Hierarchy>();
     Hierarchy& h = *hp;
     h.opt = opt;
@@ -383,41 +474,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
                        phase2.get(), L.agg.get(), flags.get(), und.get(), s);
         }
 
-        // filtered matrix, 1-norm diagonal, damping, smoothed prolongator
-        {
-            DCsr F;
-            F.n = F.m = nl;
-            DBuf<int> cnt(nl, mc), tmp(scan_tmp_size(nl), mc);
-            filter_count(L.A, L.mask.get(), cnt.get(), s);
-            F.rowptr.alloc((size_t)nl + 1, mc);
-            exclusive_scan(cnt.get(), F.rowptr.get(), nl, tmp.get(), s);
-            int fnnz = 0;
-            d2h(&fnnz, F.rowptr.get() + nl, 1, s);
-            F.nnz = fnnz;
-            F.col.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
-            F.val.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
-            DBuf<double> dt(nl, mc), dtinv(nl, mc);
-            filter_fill(L.A, L.mask.get(), F.rowptr.get(), F.col.get(), F.val.get(), dt.get(), dtinv.get(), s);
-            make_blocks(F, mc, s);
-            ensure_partial(h, std::max(stream_partials(F), stream_partials(L.A)));
-            L.lam_pf = power_method(F, dtinv.get(), opt.power_iters, stream_key(opt.seed, kPurposePf, l), h, s);
-            L.omega = L.lam_pf > 0.0 ? opt.omega_sym / L.lam_pf : 0.0;
-            DCsr Ph;
-            Ph.n = nl;
-            Ph.m = L.nc;
-            phat_counts(nl, L.agg.get(), cnt.get(), s);
-            Ph.rowptr.alloc((size_t)nl + 1, mc);
-            exclusive_scan(cnt.get(), Ph.rowptr.get(), nl, tmp.get(), s);
-            int pn = 0;
-            d2h(&pn, Ph.rowptr.get() + nl, 1, s);
-            Ph.nnz = pn;
-            Ph.col.alloc((size_t)(pn > 0 ? pn : 1), mc);
-            Ph.val.alloc((size_t)(pn > 0 ? pn : 1), mc);
-            phat_fill(nl, L.agg.get(), Ph.rowptr.get(), Ph.col.get(), Ph.val.get(), s);
-            spgemm(F, Ph, L.P, mc, s);
-            prolongator_finalize(nl, L.P.rowptr.get(), L.P.col.get(), L.P.val.get(), L.agg.get(), dt.get(),
-                                 L.omega, s);
-        }
+        smoothed_prolongator(h, l, L.P, s);
         transpose(L.P, L.R, mc, s);
         Level& C = h.lev[l + 1];
         {
@@ -442,25 +499,8 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
     h.nlev = l + 1;
     ensure_partial(h, stream_partials(h.lev[0].A));
 
-    // smoother spectral bounds and coefficients
-    for (int k = 0; k + 1 < h.nlev; ++k) {
-        Level& L = h.lev[k];
-        L.lam_cheb = power_method(L.A, L.dinv.get(), opt.power_iters, stream_key(opt.seed, kPurposeCheb, k), h, s);
-        smoother_coefficients(L, opt);
-    }
-
-    // coarsest level: dense inverse through the Cholesky factor
-    {
-        Level& C = h.lev[h.nlev - 1];
-        const int nc = C.A.n;
-        h.nL = nc;
-        h.Ainv.alloc((size_t)nc * nc, mc);
-        MATAMG_HIP(hipMemsetAsync(h.Ainv.get(), 0, sizeof(double) * (size_t)nc * nc, s));
-        densify(nc, C.A.rowptr.get(), C.A.col.get(), C.A.val.get(), h.Ainv.get(), s);
-        DBuf<double> work((size_t)nc * nc, mc);
-        if (!dense_spd_inverse(nc, h.Ainv.get(), work.get(), flag.get(), s))
-            fail(AMG_ERR_NOT_SPD, "coarsest operator is not positive definite (n=" + std::to_string(nc) + ")");
-    }
+    smoother_bounds(h, s);
+    coarse_inverse(h, flag.get(), s);
 
     // work vectors and reduced-precision copies
     for (int k = 0; k < h.nlev; ++k) {
@@ -468,20 +508,9 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
         const int nl = L.A.n;
         const bool coarsest = (k == h.nlev - 1);
         alloc_work<double>(L, nl, coarsest, mc);
-        if (h.fp32) {
-            alloc_work<float>(L, nl, coarsest, mc);
-            if (!coarsest) {
-                L.A.val32.alloc((size_t)(L.A.nnz > 0 ? L.A.nnz : 1), mc);
-                cast_vec<double, float>(L.A.nnz, L.A.val.get(), L.A.val32.get(), s);
-                L.dinv32.alloc(nl, mc);
-                cast_vec<double, float>(nl, L.dinv.get(), L.dinv32.get(), s);
-                L.P.val32.alloc((size_t)(L.P.nnz > 0 ? L.P.nnz : 1), mc);
-                cast_vec<double, float>(L.P.nnz, L.P.val.get(), L.P.val32.get(), s);
-                L.R.val32.alloc((size_t)(L.R.nnz > 0 ? L.R.nnz : 1), mc);
-                cast_vec<double, float>(L.R.nnz, L.R.val.get(), L.R.val32.get(), s);
-            }
-        }
+        if (h.fp32) alloc_work<float>(L, nl, coarsest, mc);
     }
+    if (h.fp32) cast_fp32(h, s);
     const size_t n0 = (size_t)h.lev[0].A.n;
     h.cx.alloc(n0, mc);
     h.cr.alloc(n0, mc);
@@ -491,6 +520,73 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
     MATAMG_HIP(hipStreamSynchronize(s));
     h.t_setup = now_s() - t0;
     return hp;
+}
+
+// New values of A on the setup's pattern: the value-dependent steps run again
+// on the kept masks, aggregates, coordinates and tensors (every pattern stays
+// as it is, so the new values are written into the existing arrays).
+void update_values(Hierarchy& h, const double* val, bool host_ptrs, hipStream_t s) {
+    const double t0 = now_s();
+    SetupAllocScope scope(s);
+    MemCounter* mc = &h.mem;
+    Level& L0 = h.lev[0];
+    const int n = L0.A.n;
+    for (int l = 0; l + 1 < h.nlev; ++l)
+        if (!h.lev[l].mask || !h.lev[l].agg || !h.lev[l].dir)
+            fail(AMG_ERR_INVALID_ARG, "the hierarchy no longer holds the masks and aggregates an update reuses");
+    DBuf<int> flag(1, mc);
+    MATAMG_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int), s));
+    {
+        // checked before anything of the hierarchy changes
+        const size_t nnz = (size_t)L0.A.nnz;
+        DBuf<double> v(nnz > 0 ? nnz : 1, mc);
+        MATAMG_HIP(hipMemcpyAsync(v.get(), val, sizeof(double) * nnz,
+                                  host_ptrs ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+        if (h.nlev > 1) {
+            DBuf<uint8_t> dir(n > 0 ? n : 1, mc);
+            detect_dirichlet(n, L0.A.rowptr.get(), L0.A.col.get(), v.get(), dir.get(), s);
+            bytes_differ(n, dir.get(), L0.dir.get(), flag.get(), s);
+            if (read_flag(flag.get(), s))
+                fail(AMG_ERR_INVALID_ARG, "the Dirichlet rows of the new values differ from the setup's");
+        }
+        MATAMG_HIP(hipMemcpyAsync(L0.A.val.get(), v.get(), sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+    }
+    auto take_values = [&](DCsr& dst, const DCsr& src, const char* what) {
+        if (src.nnz != dst.nnz || src.n != dst.n)
+            fail(AMG_ERR_HIP, std::string("the pattern of ") + what + " changed in an update");
+        MATAMG_HIP(hipMemcpyAsync(dst.val.get(), src.val.get(), sizeof(double) * (size_t)dst.nnz,
+                                  hipMemcpyDeviceToDevice, s));
+    };
+    for (int l = 0; l < h.nlev; ++l) {
+        Level& L = h.lev[l];
+        diag_inverse(L.A.n, L.A.rowptr.get(), L.A.col.get(), L.A.val.get(), L.dinv.get(), s);
+        if (l + 1 == h.nlev) break;
+        {
+            DCsr P;
+            smoothed_prolongator(h, l, P, s);
+            take_values(L.P, P, "P");
+        }
+        {
+            DCsr R;
+            transpose(L.P, R, mc, s);
+            take_values(L.R, R, "R");
+        }
+        DCsr AP, Ac;
+        spgemm(L.A, L.P, AP, mc, s);
+        spgemm(L.R, AP, Ac, mc, s);
+        take_values(h.lev[l + 1].A, Ac, "a coarse operator");
+    }
+    smoother_bounds(h, s);
+    coarse_inverse(h, flag.get(), s);
+    if (h.fp32) cast_fp32(h, s);
+    // the captured CG steps hold the old smoother coefficients as kernel arguments
+    for (auto& g : h.graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    MATAMG_HIP(hipStreamSynchronize(s));
+    h.t_update = now_s() - t0;
 }
 
 template <typename T>

@@ -756,6 +756,11 @@ __global__ void k_validate_csr(int n, const int* rowptr, const int* col, int64_t
     }
 }
 
+// flag = 1 where the two byte arrays differ
+__global__ void k_bytes_differ(int n, const uint8_t* a, const uint8_t* b, int* flag) {
+    ROW_LOOP(i, n) if (a[i] != b[i]) *flag = 1;
+}
+
 }  // namespace
 
 #define LAUNCH(kern, n, ...)                                                              \
@@ -898,6 +903,10 @@ void prolongator_finalize(int n, const int* prowptr, const int* pcol, double* pv
 void coarse_aux(int nc, int dim, const Incidence& m, const double* x, const double* sig, double* xc, double* sigc,
                 hipStream_t s) {
     LAUNCH(k_coarse_aux, nc, nc, dim, m.rowptr.get(), m.items.get(), x, sig, xc, sigc);
+}
+
+void bytes_differ(int n, const uint8_t* a, const uint8_t* b, int* flag, hipStream_t s) {
+    LAUNCH(k_bytes_differ, n, n, a, b, flag);
 }
 
 void diag_inverse(int n, const int* rowptr, const int* col, const double* val, double* dinv, hipStream_t s) {

@@ -61,6 +61,8 @@ void diag_inverse(int n, const int* rowptr, const int* col, const double* val, d
 void densify(int n, const int* rowptr, const int* col, const double* val, double* D, hipStream_t s);
 // CSR sanity: columns in range and strictly ascending; *flag set on violation
 void validate_csr(int n, const int* rowptr, const int* col, int64_t nnz, int* flag, hipStream_t s);
+// *flag = 1 if a[i] != b[i] for some i < n (flag is not cleared)
+void bytes_differ(int n, const uint8_t* a, const uint8_t* b, int* flag, hipStream_t s);
 
 // ----------------------------------------------------------------- SpGEMM ---
 // C = A * B with the symbolic pattern (zeros kept), ascending columns, and

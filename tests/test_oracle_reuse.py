@@ -1,6 +1,7 @@
 """Pins of the oracle's setup for new values of A on a kept coarsening (a
-material update that reuses the aggregates; the setup cost the paper's
-conclusions weigh against successive solves with a fixed matrix).
+material update that reuses the aggregates; the paper weighs the material
+measure's setup cost against solves with a fixed hierarchy in its battery
+results).
 
 Everything that does not depend on A's values (coordinates, tensors, masks,
 aggregates, depth) is kept; the value-dependent steps run on the new values.
