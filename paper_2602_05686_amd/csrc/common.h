@@ -147,9 +147,18 @@ struct DCsr {
 constexpr int kBlock = 256;          // threads per block in streaming kernels
 constexpr int kStreamCap = 2048;     // nnz staged in LDS per streaming block
 constexpr int kMaxRowsPerBlock = kBlock;
-constexpr int kLongRow = 96;         // single-thread rows: longer rows get a whole block
-// rows longer than this are reduced by a whole block, for `group` threads per row
-constexpr int long_row_limit(int group) { return group == 1 ? kLongRow : (32 * group < kStreamCap ? 32 * group : kStreamCap); }
+constexpr int kLongRow = 96;         // setup kernels: longer single-row blocks take the whole-block path
+constexpr int kWideRow = 32;         // streaming, one thread per row: wider rows are summed by 8 lanes of its wavefront
+// rows longer than this are reduced by a whole block (a block of their own),
+// for `group` threads per row
+constexpr int long_row_limit(int group) { return group == 1 ? 256 : (32 * group < kStreamCap ? 32 * group : kStreamCap); }
+// 8 threads per row instead of one (with 8-lane help for wide rows) on
+// matrices that have rows longer than kLongRow and hold more than this share
+// (in percent) of their entries in rows wider than kWideRow
+constexpr int kGroup8WidePercent = 45;
+constexpr int stream_group_rule(int max_len, int64_t wide_nnz, int64_t nnz) {
+    return (max_len > kLongRow && wide_nnz * 100 > (int64_t)kGroup8WidePercent * nnz) ? 8 : 1;
+}
 // rows each group of `group` threads reduces in a block (one after the other)
 constexpr int rows_per_group(int group) { return group == 1 ? 1 : 4; }
 // most rows in one row block

@@ -39,9 +39,7 @@ void make_blocks(DCsr& A, MemCounter* mc, hipStream_t s) {
     if (chk && chk[0] == '1') {
         std::vector<int> rp((size_t)A.n + 1);
         d2h(rp.data(), A.rowptr.get(), rp.size(), s);
-        int max_len = 0;
-        for (int i = 0; i < A.n; ++i) max_len = std::max(max_len, rp[i + 1] - rp[i]);
-        const int group = stream_group(max_len);
+        const int group = stream_group(rp.data(), A.n);
         std::vector<int> blk = stream_blocks(rp.data(), A.n, group);
         std::vector<int> dev((size_t)A.nblk + 1);
         d2h(dev.data(), A.blk.get(), dev.size(), s);

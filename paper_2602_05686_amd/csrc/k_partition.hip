@@ -2,9 +2,9 @@
 // the device.
 //
 // The partition is the greedy one: walking the rows in order, a block takes
-// rows while it holds fewer than 256/G rows and its stored entries stay
-// within kStreamCap; a row longer than long_row_limit(G) forms a block of its
-// own.  The walk is sequential, but the block that starts at row r ends at a
+// rows while it holds fewer than max_block_rows(G) rows and its stored
+// entries stay within kStreamCap; a row longer than long_row_limit(G) forms a
+// block of its own.  The walk is sequential, but the block that starts at row r ends at a
 // row next(r) that depends on r alone, so every next(r) is computed in
 // parallel (binary searches over the row pointer and the list of long rows)
 // and the block starts -- the orbit of row 0 under next -- are marked by
@@ -25,24 +25,41 @@ inline int grid1(int64_t n) {
 
 #define FOR_ROWS(i, n) for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (n); i += (int64_t)gridDim.x * kBlock)
 
-// longest row; launched with a small grid so that few blocks meet at the atomic
+// longest row (out[0]) and the entries in rows wider than kWideRow (out[6]);
+// launched with a small grid so that few blocks meet at the atomics (both
+// results are order-independent)
 __global__ __launch_bounds__(kBlock) void k_max_row_len(int n, const int* rp, int* out) {
-    __shared__ int sm[kBlock / 64];
-    int m = 0;
-    FOR_ROWS(i, n) m = max(m, rp[i + 1] - rp[i]);
-    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __shared__ int sm[kBlock / 64], sw[kBlock / 64];
+    int m = 0, w = 0;
+    FOR_ROWS(i, n) {
+        const int len = rp[i + 1] - rp[i];
+        m = max(m, len);
+        if (len > kWideRow) w += len;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        m = max(m, __shfl_xor(m, off, 64));
+        w += __shfl_xor(w, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sm[threadIdx.x >> 6] = m;
+        sw[threadIdx.x >> 6] = w;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kBlock / 64; ++w) m = max(m, sm[w]);
+        for (int k = 1; k < kBlock / 64; ++k) {
+            m = max(m, sm[k]);
+            w += sw[k];
+        }
         if (m > 0) atomicMax(out, m);
+        if (w > 0) atomicAdd(out + 6, w);
     }
 }
 
-// par[0] = longest row -> par[1] = threads per row, par[2] = long-row
-// limit, par[3] = most rows per block (the host's stream_group rule)
-__global__ void k_group_params(int* par) {
-    const int group = par[0] <= kLongRow ? 1 : 8;
+// par[0] = longest row, par[6] = entries in wide rows -> par[1] = threads per
+// row, par[2] = long-row limit, par[3] = most rows per block (the host's
+// stream_group rule)
+__global__ void k_group_params(int n, const int* rp, int* par) {
+    const int group = stream_group_rule(par[0], par[6], rp[n]);
     par[1] = group;
     par[2] = long_row_limit(group);
     par[3] = max_block_rows(group);
@@ -132,7 +149,7 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s) {
     DBuf<int> par(8, mc);
     MATAMG_HIP(hipMemsetAsync(par.get(), 0, 8 * sizeof(int), s));
     hipLaunchKernelGGL(k_max_row_len, dim3(std::min(grid1(n), 256)), dim3(kBlock), 0, s, n, rp, par.get());
-    hipLaunchKernelGGL(k_group_params, dim3(1), dim3(1), 0, s, par.get());
+    hipLaunchKernelGGL(k_group_params, dim3(1), dim3(1), 0, s, n, rp, par.get());
     MATAMG_LAUNCH_CHECK();
 
     const size_t n1 = (size_t)n + 1;

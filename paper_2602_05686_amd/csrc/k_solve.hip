@@ -3,13 +3,16 @@
 // dense coarse-level GEMV, and the integer prefix scan used by setup.
 //
 // Streaming CSR layout: rows are cut into blocks of at most kStreamCap
-// stored entries and kMaxRowsPerBlock rows; a row longer than kLongRow gets a
-// block of its own.  A 256-thread block first streams
-// its contiguous val/col range (fully coalesced) and stores val*x[col] in
-// LDS, then one thread per row sums its products in ascending stored order
-// and applies the epilogue.  A long row is reduced by the whole block: strided
-// partial sums and a fixed tree.  Every sum therefore has a fixed
-// order for a given matrix: results are bitwise reproducible run to run.
+// stored entries and kMaxRowsPerBlock rows; a row longer than
+// long_row_limit(1) gets a block of its own.  A 256-thread block first
+// streams its contiguous val/col range (fully coalesced) and stores
+// val*x[col] in LDS, then one thread per row sums its products in ascending
+// stored order and applies the epilogue; rows wider than kWideRow are summed
+// by 8-lane groups of their thread's wavefront (lane-strided partial sums, a
+// fixed butterfly) so that a few wide rows do not hold up the block.  A long
+// row is reduced by the whole block: strided partial sums and a fixed tree.
+// Every sum therefore has a fixed order for a given matrix: results are
+// bitwise reproducible run to run.
 #include "solve_device.h"
 
 namespace matamg {
@@ -138,7 +141,16 @@ template void dot<double>(const double*, const double*, int64_t, double*, unsign
 template void dot<float>(const float*, const float*, int64_t, double*, unsigned*, double*, hipStream_t);
 
 // =============================================================== streaming
-int stream_group(int max_len) { return max_len <= kLongRow ? 1 : 8; }
+int stream_group(const int* rp, int n) {
+    int max_len = 0;
+    int64_t wide = 0;
+    for (int i = 0; i < n; ++i) {
+        const int len = rp[i + 1] - rp[i];
+        max_len = std::max(max_len, len);
+        if (len > kWideRow) wide += len;
+    }
+    return stream_group_rule(max_len, wide, n > 0 ? rp[n] : 0);
+}
 
 std::vector<int> stream_blocks(const int* rp, int n, int group) {
     const int max_rows = max_block_rows(group);

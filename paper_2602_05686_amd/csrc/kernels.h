@@ -20,8 +20,8 @@ void dot(const T* a, const T* b, int64_t n, double* partial, unsigned* counter, 
 // --------------------------------------------------------------- streaming ---
 // row blocks for the streaming CSR kernels, computed from a host row pointer
 std::vector<int> stream_blocks(const int* rowptr_host, int n, int group);
-// threads per row for a matrix whose longest row has `max_len` entries
-int stream_group(int max_len);
+// threads per row for a matrix (host row pointer): stream_group_rule
+int stream_group(const int* rowptr_host, int n);
 // A.group, A.nblk and A.blk from A's device row pointer (the same greedy
 // partition as stream_blocks, computed on the device); reads back the block
 // count, so s is synchronised once

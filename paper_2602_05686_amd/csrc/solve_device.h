@@ -166,9 +166,33 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
         }
         __syncthreads();
         if constexpr (G == 1) {
+            // a row up to kWideRow wide is summed by its own thread; the
+            // wider rows of a wavefront (at most long_row_limit(1) wide) by
+            // 8-lane groups of it, eight rows at a time: lane-strided
+            // partial sums, then a butterfly that leaves the same bits in
+            // the group's eight lanes
+            const bool wide = owner && (e1 - e0) > kWideRow;
             T s = 0;
-            if (owner)
+            if (owner && !wide)
                 for (int k = e0 - k0; k < e1 - k0; ++k) s += S.prod[k];
+            const int lane = (int)threadIdx.x & 63, grp = lane >> 3, gl = lane & 7;
+            unsigned long long wm = __ballot(wide);
+            // rank of this lane's row among the wide rows of the wavefront
+            const int rank = __popcll(wm & ((1ull << lane) - 1ull));
+            for (int base = 0; wm; base += 8) {
+                unsigned long long m = wm;
+                for (int j = 0; j < grp; ++j) m &= m - 1ull;  // the grp-th remaining wide row
+                const int l = m ? __builtin_ctzll(m) : 0;
+                const int f0 = __shfl(e0, l, 64) - k0, f1 = __shfl(e1, l, 64) - k0;
+                T ps = 0;
+                if (m)
+                    for (int k = f0 + gl; k < f1; k += 8) ps += S.prod[k];
+                for (int off = 4; off > 0; off >>= 1) ps += __shfl_xor(ps, off, 64);
+                const int src = (rank >= base && rank < base + 8) ? (rank - base) * 8 : 0;
+                const T got = __shfl(ps, src, 64);
+                if (wide && rank >= base && rank < base + 8) s = got;
+                for (int j = 0; j < 8; ++j) wm &= wm - 1ull;
+            }
             if (owner) dp = epilogue<T, MODE, HAS_DOT>(a, r, s, ops);
         } else {
             // G threads per row, rows_per_group(G) rows per group: strided
