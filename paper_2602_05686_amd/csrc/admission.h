@@ -15,14 +15,15 @@ namespace matamg {
 // built (the setup peak), from the fine-level sizes.  Per stored entry of A:
 // the matrix (12 B), strength values and drop mask (9 B), the strength
 // numerators during the drop (8 B), the filtered matrix (12 B), the FP32
-// copies (4 B) and the SpGEMM products of the first level (bounded by 12 B);
+// copies (4 B), the SpGEMM products of the first level (bounded by 12 B) and
+// the packed 16-bit columns of the operators and transfers (6 B);
 // per node: coordinates, nodal and inverse tensors, aggregation state,
 // tentative and smoothed prolongator rows, work and Krylov vectors; per
 // element: the connectivity and tensors staged for the nodal averages; plus
 // the dense coarsest inverse and its workspace for up to max_coarse unknowns.
 inline int64_t estimate_setup_bytes(int64_t n, int64_t nnz, int64_t nelem, int npe, int dim, int max_coarse) {
     const int64_t ncomp = (int64_t)dim * (dim + 1) / 2;
-    const int64_t per_nnz = 12 + 9 + 8 + 12 + 4 + 12;
+    const int64_t per_nnz = 12 + 9 + 8 + 12 + 4 + 12 + 6;
     const int64_t per_node = 8 * dim + 16 * ncomp + 64 + 2 * 12 * 8 + 10 * 8 + 6 * 8 + 64;
     const int64_t per_elem = 4 * (int64_t)npe + 8 * (int64_t)dim * dim + 8 * (int64_t)npe;
     const int64_t nl = n < (int64_t)max_coarse ? n : (int64_t)max_coarse;

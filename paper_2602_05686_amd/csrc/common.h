@@ -142,6 +142,12 @@ struct DCsr {
     DBuf<int> blk;
     int nblk = 0;
     int group = 1;
+    // packed columns for the streaming SpMV (when every row block's columns
+    // span fewer than 2^16 values): col = cbase[b] + col16 within block b
+    DBuf<uint16_t> col16;
+    DBuf<int> cbase;
+    // column bytes per stored entry the streaming kernels read
+    double col_bytes() const { return col16 ? 2.0 : 4.0; }
 };
 
 constexpr int kBlock = 256;          // threads per block in streaming kernels

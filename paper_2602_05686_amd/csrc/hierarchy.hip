@@ -30,11 +30,12 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Row blocks of A for the streaming kernels, computed on the device.
-// MATAMG_CHECK_PARTITION=1 also runs the host walk and fails on any
-// difference (used by the tests).
-void make_blocks(DCsr& A, MemCounter* mc, hipStream_t s) {
+// Row blocks of A for the streaming kernels, computed on the device, and
+// (if `pack`) the 16-bit packed columns.  MATAMG_CHECK_PARTITION=1 also runs
+// the host walk and fails on any difference (used by the tests).
+void make_blocks(DCsr& A, MemCounter* mc, hipStream_t s, bool pack = true) {
     stream_partition(A, mc, s);
+    if (pack) pack_columns(A, mc, s);
     const char* chk = std::getenv("MATAMG_CHECK_PARTITION");
     if (chk && chk[0] == '1') {
         std::vector<int> rp((size_t)A.n + 1);
@@ -195,8 +196,12 @@ double Hierarchy::time_smoother(int level, int reps, hipStream_t s, double* byte
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     const double sz = fp32 ? 4.0 : 8.0;
-    // val + col + rowptr once, the gathered iterate once, b, D^{-1}, d read, d and x written
-    if (bytes_per_launch) *bytes_per_launch = (double)L.A.nnz * (sz + 4.0) + 4.0 * (L.A.n + 1) + 6.0 * sz * L.A.n;
+    // val + col (as stored: 4 bytes, or 2 plus a base per block when packed)
+    // + rowptr once, the gathered iterate once, b, D^{-1}, d read, d and x
+    // written
+    if (bytes_per_launch)
+        *bytes_per_launch = (double)L.A.nnz * (sz + L.A.col_bytes()) + 4.0 * (L.A.n + 1) +
+                            (L.A.col16 ? 4.0 * L.A.nblk : 0.0) + 6.0 * sz * L.A.n;
     return ms_total / reps;
 }
 
@@ -246,7 +251,7 @@ void smoothed_prolongator(Hierarchy& h, int l, DCsr& P, hipStream_t s) {
     F.val.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
     DBuf<double> dt(nl, mc), dtinv(nl, mc);
     filter_fill(L.A, L.mask.get(), F.rowptr.get(), F.col.get(), F.val.get(), dt.get(), dtinv.get(), s);
-    make_blocks(F, mc, s);
+    make_blocks(F, mc, s, false);  // ten power steps: not worth packing
     ensure_partial(h, std::max(stream_partials(F), stream_partials(L.A)));
     L.lam_pf = power_method(F, dtinv.get(), opt.power_iters, stream_key(opt.seed, kPurposePf, l), h, s);
     L.omega = L.lam_pf > 0.0 ? opt.omega_sym / L.lam_pf : 0.0;
@@ -665,14 +670,18 @@ double Hierarchy::vcycle_alg_bytes() const {
     double bytes = 0.0;
     for (int l = 0; l + 1 < nlev; ++l) {
         const Level& L = lev[l];
-        const double n = L.A.n, nnz = (double)L.A.nnz, nc = L.nc, nnzp = (double)L.P.nnz;
+        const double n = L.A.n, nc = L.nc;
         const double steps = (double)L.c1.size();
-        const double mat = nnz * (s + 4.0) + 4.0 * (n + 1);
+        // a matrix: values, columns as stored for the streaming kernels (4
+        // bytes, or 2 when packed, plus one base per row block), row pointer
+        auto matrix = [&](const DCsr& M) {
+            return (double)M.nnz * (s + M.col_bytes()) + 4.0 * (M.n + 1) + (M.col16 ? 4.0 * M.nblk : 0.0);
+        };
         // smoother SpMVs: (steps-1) pre + steps post; one residual SpMV
         const double n_spmv = (steps - 1.0) + steps + 1.0;
-        bytes += n_spmv * mat;
-        bytes += nnzp * (s + 4.0) + 4.0 * (nc + 1);  // R r
-        bytes += nnzp * (s + 4.0) + 4.0 * (n + 1);   // x += P e
+        bytes += n_spmv * matrix(L.A);
+        bytes += matrix(L.R);  // R r
+        bytes += matrix(L.P);  // x += P e
         // vectors: first step reads b, dinv, writes d, x (4); each smoother
         // SpMV reads x, b, dinv, d and writes d, x (6); residual reads x, b,
         // writes r (3); restriction reads r, writes b_c; prolongation reads

@@ -131,7 +131,70 @@ __global__ void k_fill_starts(int n, const int* mark, const int* pos, int* blk) 
     if (blockIdx.x == 0 && threadIdx.x == 0) blk[pos[n]] = n;
 }
 
+// cbase[b] = smallest column of block b; flag = 1 if a block's columns span
+// 2^16 values or more
+__global__ __launch_bounds__(kBlock) void k_block_col_range(int nblk, const int* rp, const int* col, const int* blk,
+                                                            int* cbase, int* flag) {
+    __shared__ int smin[kBlock / 64], smax[kBlock / 64];
+    for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int k0 = rp[blk[b]], k1 = rp[blk[b + 1]];
+        int lo = 0x7fffffff, hi = -1;
+        for (int k = k0 + (int)threadIdx.x; k < k1; k += kBlock) {
+            const int c = col[k];
+            lo = min(lo, c);
+            hi = max(hi, c);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = min(lo, __shfl_xor(lo, off, 64));
+            hi = max(hi, __shfl_xor(hi, off, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            smin[threadIdx.x >> 6] = lo;
+            smax[threadIdx.x >> 6] = hi;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < kBlock / 64; ++w) {
+                lo = min(lo, smin[w]);
+                hi = max(hi, smax[w]);
+            }
+            cbase[b] = k1 > k0 ? lo : 0;
+            if (k1 > k0 && hi - lo > 0xffff) *flag = 1;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_cols(int nblk, const int* rp, const int* col, const int* blk,
+                                                      const int* cbase, uint16_t* col16) {
+    for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int k0 = rp[blk[b]], k1 = rp[blk[b + 1]], base = cbase[b];
+        for (int k = k0 + (int)threadIdx.x; k < k1; k += kBlock) col16[k] = (uint16_t)(col[k] - base);
+    }
+}
+
 }  // namespace
+
+void pack_columns(DCsr& A, MemCounter* mc, hipStream_t s) {
+    A.col16.release();
+    A.cbase.release();
+    if (A.nblk <= 0 || A.nnz <= 0) return;
+    DBuf<int> flag(1, mc);
+    MATAMG_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int), s));
+    DBuf<int> cbase((size_t)A.nblk, mc);
+    const int grid = std::min(A.nblk, 65535);
+    hipLaunchKernelGGL(k_block_col_range, dim3(grid), dim3(kBlock), 0, s, A.nblk, A.rowptr.get(), A.col.get(),
+                       A.blk.get(), cbase.get(), flag.get());
+    MATAMG_LAUNCH_CHECK();
+    int wide = 0;
+    d2h(&wide, flag.get(), 1, s);
+    if (wide) return;
+    A.col16.alloc((size_t)A.nnz, mc);
+    hipLaunchKernelGGL(k_pack_cols, dim3(grid), dim3(kBlock), 0, s, A.nblk, A.rowptr.get(), A.col.get(),
+                       A.blk.get(), (const int*)cbase.get(), A.col16.get());
+    MATAMG_LAUNCH_CHECK();
+    A.cbase = std::move(cbase);
+}
 
 void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s) {
     const int n = A.n;

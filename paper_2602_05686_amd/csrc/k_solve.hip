@@ -205,6 +205,8 @@ SArgs<T> base_args(const DCsr& A, const T* val, const T* x) {
     SArgs<T> a{};
     a.rowptr = A.rowptr.get();
     a.col = A.col.get();
+    a.col16 = A.col16.get();
+    a.cbase = A.cbase.get();
     a.val = val;
     a.blk = A.blk.get();
     a.x = x;

@@ -27,6 +27,10 @@ int stream_group(const int* rowptr_host, int n);
 // count, so s is synchronised once
 void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s);
 
+// A.col16 and A.cbase from A's row blocks when every block's columns span
+// fewer than 2^16 values (otherwise both stay empty); reads back one flag
+void pack_columns(DCsr& A, MemCounter* mc, hipStream_t s);
+
 // dot partials of a streaming launch: one per wavefront of each row block
 constexpr int kStreamPartials = kBlock / 64;
 inline int stream_partials(const DCsr& A) { return A.nblk * kStreamPartials; }

@@ -66,6 +66,8 @@ SArgs<T> sargs(const DCsr& M, const T* val, const T* x) {
     SArgs<T> a{};
     a.rowptr = M.rowptr.get();
     a.col = M.col.get();
+    a.col16 = M.col16.get();
+    a.cbase = M.cbase.get();
     a.val = val;
     a.blk = M.blk.get();
     a.x = x;

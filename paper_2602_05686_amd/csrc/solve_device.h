@@ -23,6 +23,8 @@ template <typename T>
 struct SArgs {
     const int* rowptr;
     const int* col;
+    const uint16_t* col16;  // packed columns (or null): col = cbase[block] + col16
+    const int* cbase;
     const T* val;
     const int* blk;
     const T* x;        // gathered operand
@@ -105,15 +107,18 @@ struct StreamShared {
 // prod[t] = val[k0 + t] * x[col[k0 + t]] for t < cnt, with NU = ceil(cnt /
 // kBlock) strides per thread: all loads first (indices past the end clamped
 // to the last entry, results discarded), then the gathers, then the stores.
-template <typename T, int NU>
-__device__ __forceinline__ void stage_products(const SArgs<T>& a, int k0, int cnt, T* prod) {
+// PACKED: the columns come from the 16-bit col16 plus the block's base.
+template <typename T, int NU, bool PACKED>
+__device__ __forceinline__ void stage_products(const SArgs<T>& a, int bid, int k0, int cnt, T* prod) {
     int c[NU];
     T v[NU];
+    const int base = PACKED ? a.cbase[bid] : 0;
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
         const int t = (int)threadIdx.x + u * kBlock;
         const int tc = t < cnt ? t : cnt - 1;
-        c[u] = __builtin_nontemporal_load(a.col + k0 + tc);
+        if constexpr (PACKED) c[u] = base + (int)__builtin_nontemporal_load(a.col16 + k0 + tc);
+        else c[u] = __builtin_nontemporal_load(a.col + k0 + tc);
         v[u] = __builtin_nontemporal_load(a.val + k0 + tc);
     }
     T xv[NU];
@@ -152,17 +157,33 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
         // with G > 1 only the row's first thread needs them, after the sum
         RowOperands<T> ops{};
         if constexpr (G == 1) ops = row_operands<T, MODE>(a, rc);
-        // ceil(cnt / kBlock) strides of the block's entries (block-uniform)
-        switch ((cnt + kBlock - 1) / kBlock) {
-            case 1: stage_products<T, 1>(a, k0, cnt, S.prod); break;
-            case 2: stage_products<T, 2>(a, k0, cnt, S.prod); break;
-            case 3: stage_products<T, 3>(a, k0, cnt, S.prod); break;
-            case 4: stage_products<T, 4>(a, k0, cnt, S.prod); break;
-            case 5: stage_products<T, 5>(a, k0, cnt, S.prod); break;
-            case 6: stage_products<T, 6>(a, k0, cnt, S.prod); break;
-            case 7: stage_products<T, 7>(a, k0, cnt, S.prod); break;
-            case 8: stage_products<T, 8>(a, k0, cnt, S.prod); break;
-            default: break;
+        // ceil(cnt / kBlock) strides of the block's entries (block-uniform),
+        // from packed or plain columns (uniform per matrix)
+        const int nu = (cnt + kBlock - 1) / kBlock;
+        if (a.col16) {
+            switch (nu) {
+                case 1: stage_products<T, 1, true>(a, bid, k0, cnt, S.prod); break;
+                case 2: stage_products<T, 2, true>(a, bid, k0, cnt, S.prod); break;
+                case 3: stage_products<T, 3, true>(a, bid, k0, cnt, S.prod); break;
+                case 4: stage_products<T, 4, true>(a, bid, k0, cnt, S.prod); break;
+                case 5: stage_products<T, 5, true>(a, bid, k0, cnt, S.prod); break;
+                case 6: stage_products<T, 6, true>(a, bid, k0, cnt, S.prod); break;
+                case 7: stage_products<T, 7, true>(a, bid, k0, cnt, S.prod); break;
+                case 8: stage_products<T, 8, true>(a, bid, k0, cnt, S.prod); break;
+                default: break;
+            }
+        } else {
+            switch (nu) {
+                case 1: stage_products<T, 1, false>(a, bid, k0, cnt, S.prod); break;
+                case 2: stage_products<T, 2, false>(a, bid, k0, cnt, S.prod); break;
+                case 3: stage_products<T, 3, false>(a, bid, k0, cnt, S.prod); break;
+                case 4: stage_products<T, 4, false>(a, bid, k0, cnt, S.prod); break;
+                case 5: stage_products<T, 5, false>(a, bid, k0, cnt, S.prod); break;
+                case 6: stage_products<T, 6, false>(a, bid, k0, cnt, S.prod); break;
+                case 7: stage_products<T, 7, false>(a, bid, k0, cnt, S.prod); break;
+                case 8: stage_products<T, 8, false>(a, bid, k0, cnt, S.prod); break;
+                default: break;
+            }
         }
         __syncthreads();
         if constexpr (G == 1) {
