@@ -284,6 +284,13 @@ amg_status amg_server_poll(amg_server* s, double timeout_s, uint64_t* ids, int32
  * Returns INVALID_ARG for an unknown, unfinished or already taken id. */
 amg_status amg_server_result(amg_server* s, uint64_t id, double* x, amg_solve_info* info, amg_request_stats* rs);
 amg_status amg_server_info(amg_server* s, amg_server_stats* out);
+/* Dynamic batching delay: when no request is being solved and the first
+ * ones become ready while others are still in setup, the engine waits up to
+ * `seconds` (in [0, 10]; 0 = start at once, the default) for those setups so
+ * that they join the first round; it starts as soon as none is left in
+ * setup.  Trades the first requests' latency for larger rounds.  Errors:
+ * INVALID_ARG. */
+amg_status amg_server_set_batch_wait(amg_server* s, double seconds);
 void amg_server_destroy(amg_server* s);
 const char* amg_status_string(amg_status s);
 const char* amg_last_error(void);

@@ -32,7 +32,7 @@ EXPORTED = [
     "amg_get_aggregates", "amg_get_soc_mask", "amg_get_level_csr", "amg_get_level_aux", "amg_time_smoother",
     "amg_free", "amg_status_string", "amg_last_error",
     "amg_server_create", "amg_server_submit", "amg_server_poll", "amg_server_result", "amg_server_info",
-    "amg_server_destroy",
+    "amg_server_set_batch_wait", "amg_server_destroy",
 ]
 
 
@@ -140,6 +140,7 @@ def load():
     L.amg_server_poll.argtypes = [P, f64, P, i32, ctypes.POINTER(i32)]
     L.amg_server_result.argtypes = [P, ctypes.c_uint64, P, ctypes.POINTER(SolveInfo), ctypes.POINTER(RequestStats)]
     L.amg_server_info.argtypes = [P, ctypes.POINTER(ServerStats)]
+    L.amg_server_set_batch_wait.argtypes = [P, f64]
     L.amg_server_destroy.argtypes = [P]
     L.amg_server_destroy.restype = None
     L.amg_status_string.argtypes = [i32]
@@ -338,7 +339,7 @@ class Server:
     (x, info, timeline).
     """
 
-    def __init__(self, budget_bytes=8 << 30, max_active=32, setup_workers=2, dim=3, **kw):
+    def __init__(self, budget_bytes=8 << 30, max_active=32, setup_workers=2, dim=3, batch_wait_s=0.0, **kw):
         L = load()
         self.opts = options(dim=dim, **kw)
         s = ctypes.c_void_p()
@@ -346,6 +347,8 @@ class Server:
                                   ctypes.byref(s)), "amg_server_create")
         self._s = s
         self._n = {}
+        if batch_wait_s:
+            check(L.amg_server_set_batch_wait(s, float(batch_wait_s)), "amg_server_set_batch_wait")
 
     def submit(self, prob, b=None, x0=None, tol=1e-8, max_iter=1000):
         """Submit a workloads.Problem (right-hand side prob.b unless b is given)."""

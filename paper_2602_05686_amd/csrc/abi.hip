@@ -20,6 +20,12 @@ thread_local std::string g_last_error;
 thread_local AllocMode g_alloc_mode;
 AllocMode& alloc_mode() { return g_alloc_mode; }
 
+void* readback_buffer() {
+    thread_local void* buf = nullptr;
+    if (!buf) MATAMG_HIP(hipHostMalloc(&buf, kReadbackBytes, hipHostMallocDefault));
+    return buf;
+}
+
 bool pool_enabled() {
     const char* e = std::getenv("MATAMG_NO_POOL");
     return !(e && e[0] == '1');
@@ -386,6 +392,15 @@ amg_status amg_server_info(amg_server* s, amg_server_stats* out) {
         out->mean_batch = st.steps > 0 ? (double)st.batch_sum / (double)st.steps : 0.0;
         out->max_batch = st.max_batch;
         out->estimate_exceeded = st.estimate_exceeded;
+        return AMG_OK;
+    });
+}
+
+amg_status amg_server_set_batch_wait(amg_server* s, double seconds) {
+    return guarded([&]() -> amg_status {
+        if (!s || !s->s) fail(AMG_ERR_INVALID_ARG, "null server");
+        if (!(seconds >= 0.0 && seconds <= 10.0)) fail(AMG_ERR_INVALID_ARG, "batch wait must lie in [0, 10] s");
+        s->s->set_batch_wait(seconds);
         return AMG_OK;
     });
 }

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <string>
 #include <utility>
 #include <vector>
@@ -172,11 +173,25 @@ constexpr int max_block_rows(int group) { return kBlock / group * rows_per_group
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// pinned host memory of at least `bytes` (<= kReadbackBytes) owned by the
+// calling thread, kept until the process ends: small read-backs through it
+// take the direct DMA path instead of a staged copy into pageable memory
+constexpr size_t kReadbackBytes = 64 << 10;
+void* readback_buffer();
+
 // synchronous device->host copy of a small array on a stream
 template <typename T>
 void d2h(T* host, const T* dev, size_t n, hipStream_t s) {
     if (n == 0) return;
-    MATAMG_HIP(hipMemcpyAsync(host, dev, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    const size_t bytes = n * sizeof(T);
+    if (bytes <= kReadbackBytes) {
+        void* pin = readback_buffer();
+        MATAMG_HIP(hipMemcpyAsync(pin, dev, bytes, hipMemcpyDeviceToHost, s));
+        MATAMG_HIP(hipStreamSynchronize(s));
+        std::memcpy(host, pin, bytes);
+        return;
+    }
+    MATAMG_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
     MATAMG_HIP(hipStreamSynchronize(s));
 }
 template <typename T>

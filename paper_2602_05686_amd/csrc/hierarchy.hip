@@ -34,8 +34,7 @@ double now_s() {
 // (if `pack`) the 16-bit packed columns.  MATAMG_CHECK_PARTITION=1 also runs
 // the host walk and fails on any difference (used by the tests).
 void make_blocks(DCsr& A, MemCounter* mc, hipStream_t s, bool pack = true) {
-    stream_partition(A, mc, s);
-    if (pack) pack_columns(A, mc, s);
+    stream_partition(A, mc, s, pack);
     const char* chk = std::getenv("MATAMG_CHECK_PARTITION");
     if (chk && chk[0] == '1') {
         std::vector<int> rp((size_t)A.n + 1);

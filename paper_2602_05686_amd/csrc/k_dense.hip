@@ -57,9 +57,11 @@ __device__ void tile_mac(double acc[4][4], const double* A, int lda, bool ta, in
 }
 
 // factor the diagonal tile kb in LDS; flag <- 1 if not positive definite.
-// One wavefront: its barriers cost next to nothing, and they dominate a
-// 64-step factorisation run by several waves.
-constexpr int kPotrfThreads = 64;
+// One wavefront, left-looking, thread i owning row i: at step j thread j
+// forms the diagonal from its own row, then every row i > j forms L_ij from
+// the dot product of rows i and j over the finished columns k < j.  Each step
+// is a single chain of j multiply-adds per thread, with no index arithmetic.
+constexpr int kPotrfThreads = NB;
 __global__ __launch_bounds__(kPotrfThreads) void k_potrf_diag(double* A, int n, int kb, int* flag) {
     __shared__ double T[NB][NB + 1];
     const int o = kb * NB;
@@ -69,9 +71,11 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf_diag(double* A, int n, 
         T[i][j] = A[(size_t)(o + i) * n + o + j];
     }
     __syncthreads();
+    const int i = threadIdx.x;
     for (int j = 0; j < nb; ++j) {
-        if (threadIdx.x == 0) {
+        if (i == j) {
             double d = T[j][j];
+            for (int k = 0; k < j; ++k) d -= T[j][k] * T[j][k];
             if (!(d > 0.0) || !isfinite(d)) {
                 *flag = 1;
                 d = 1.0;
@@ -79,19 +83,16 @@ __global__ __launch_bounds__(kPotrfThreads) void k_potrf_diag(double* A, int n, 
             T[j][j] = sqrt(d);
         }
         __syncthreads();
-        const double ljj = T[j][j];
-        for (int i = j + 1 + threadIdx.x; i < nb; i += kPotrfThreads) T[i][j] = T[i][j] / ljj;
-        __syncthreads();
-        const int m = nb - j - 1;
-        for (int e = threadIdx.x; e < m * m; e += kPotrfThreads) {
-            int i = j + 1 + e / m, k = j + 1 + e % m;
-            if (k <= i) T[i][k] -= T[i][j] * T[k][j];
+        if (i > j && i < nb) {
+            double v = T[i][j];
+            for (int k = 0; k < j; ++k) v -= T[i][k] * T[j][k];
+            T[i][j] = v / T[j][j];
         }
         __syncthreads();
     }
     for (int e = threadIdx.x; e < nb * nb; e += kPotrfThreads) {
-        int i = e / nb, j = e % nb;
-        A[(size_t)(o + i) * n + o + j] = (j <= i) ? T[i][j] : 0.0;
+        int r = e / nb, c = e % nb;
+        A[(size_t)(o + r) * n + o + c] = (c <= r) ? T[r][c] : 0.0;
     }
 }
 

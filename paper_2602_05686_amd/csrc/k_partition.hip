@@ -132,10 +132,11 @@ __global__ void k_fill_starts(int n, const int* mark, const int* pos, int* blk) 
 }
 
 // cbase[b] = smallest column of block b; flag = 1 if a block's columns span
-// 2^16 values or more
-__global__ __launch_bounds__(kBlock) void k_block_col_range(int nblk, const int* rp, const int* col, const int* blk,
-                                                            int* cbase, int* flag) {
+// 2^16 values or more (the block count *nblk_dev is read on the device)
+__global__ __launch_bounds__(kBlock) void k_block_col_range(const int* nblk_dev, const int* rp, const int* col,
+                                                            const int* blk, int* cbase, int* flag) {
     __shared__ int smin[kBlock / 64], smax[kBlock / 64];
+    const int nblk = *nblk_dev;
     for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
         const int k0 = rp[blk[b]], k1 = rp[blk[b + 1]];
         int lo = 0x7fffffff, hi = -1;
@@ -175,29 +176,10 @@ __global__ __launch_bounds__(kBlock) void k_pack_cols(int nblk, const int* rp, c
 
 }  // namespace
 
-void pack_columns(DCsr& A, MemCounter* mc, hipStream_t s) {
+void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack) {
+    const int n = A.n;
     A.col16.release();
     A.cbase.release();
-    if (A.nblk <= 0 || A.nnz <= 0) return;
-    DBuf<int> flag(1, mc);
-    MATAMG_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int), s));
-    DBuf<int> cbase((size_t)A.nblk, mc);
-    const int grid = std::min(A.nblk, 65535);
-    hipLaunchKernelGGL(k_block_col_range, dim3(grid), dim3(kBlock), 0, s, A.nblk, A.rowptr.get(), A.col.get(),
-                       A.blk.get(), cbase.get(), flag.get());
-    MATAMG_LAUNCH_CHECK();
-    int wide = 0;
-    d2h(&wide, flag.get(), 1, s);
-    if (wide) return;
-    A.col16.alloc((size_t)A.nnz, mc);
-    hipLaunchKernelGGL(k_pack_cols, dim3(grid), dim3(kBlock), 0, s, A.nblk, A.rowptr.get(), A.col.get(),
-                       A.blk.get(), (const int*)cbase.get(), A.col16.get());
-    MATAMG_LAUNCH_CHECK();
-    A.cbase = std::move(cbase);
-}
-
-void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s) {
-    const int n = A.n;
     if (n <= 0) {
         A.group = 1;
         A.nblk = 0;
@@ -238,17 +220,35 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s) {
     }
     MATAMG_LAUNCH_CHECK();
     exclusive_scan(flags.get(), pos.get(), n, tmp.get(), s);
+    // block starts (at most n blocks) and, for packing, every block's
+    // column range, all before the one read-back of {blocks, group, wide}
+    DBuf<int> blk(n1 + 1, mc), cbase;
+    hipLaunchKernelGGL(k_fill_starts, dim3(grid1(n)), dim3(kBlock), 0, s, n, (const int*)flags.get(),
+                       (const int*)pos.get(), blk.get());
+    if (pack && A.nnz > 0) {
+        cbase.alloc(n1, mc);
+        hipLaunchKernelGGL(k_block_col_range, dim3(std::min(grid1(n) * 4, 65535)), dim3(kBlock), 0, s,
+                           (const int*)pos.get() + n, rp, A.col.get(), (const int*)blk.get(), cbase.get(),
+                           par.get() + 7);
+    }
     hipLaunchKernelGGL(k_partition_result, dim3(1), dim3(1), 0, s, n, (const int*)pos.get(), (const int*)par.get(),
                        par.get() + 4);
-    int res[2] = {0, 0};
-    d2h(res, par.get() + 4, 2, s);
+    MATAMG_LAUNCH_CHECK();
+    int res[4] = {0, 0, 0, 0};
+    d2h(res, par.get() + 4, 4, s);
     const int nblk = res[0];
     A.group = res[1];
     A.nblk = nblk;
     A.blk.alloc((size_t)nblk + 1, mc);
-    hipLaunchKernelGGL(k_fill_starts, dim3(grid1(n)), dim3(kBlock), 0, s, n, (const int*)flags.get(),
-                       (const int*)pos.get(), A.blk.get());
-    MATAMG_LAUNCH_CHECK();
+    MATAMG_HIP(hipMemcpyAsync(A.blk.get(), blk.get(), sizeof(int) * ((size_t)nblk + 1), hipMemcpyDeviceToDevice, s));
+    if (pack && A.nnz > 0 && res[3] == 0) {
+        A.cbase.alloc((size_t)nblk, mc);
+        MATAMG_HIP(hipMemcpyAsync(A.cbase.get(), cbase.get(), sizeof(int) * (size_t)nblk, hipMemcpyDeviceToDevice, s));
+        A.col16.alloc((size_t)A.nnz, mc);
+        hipLaunchKernelGGL(k_pack_cols, dim3(std::min(nblk, 65535)), dim3(kBlock), 0, s, nblk, rp, A.col.get(),
+                           (const int*)A.blk.get(), (const int*)A.cbase.get(), A.col16.get());
+        MATAMG_LAUNCH_CHECK();
+    }
 }
 
 }  // namespace matamg

@@ -148,15 +148,11 @@ __device__ __forceinline__ unsigned hash_find_fresh(const int* keys, unsigned ma
     return 0;
 }
 
+// one row (list position ridx) of the symbolic phase, by one wavefront
 template <bool GLOBAL>
-__global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int* rows, const int* arp,
-                                                            const int* acol, const int* brp, const int* bcol,
-                                                            int* cnt, int* gkeys, const int64_t* goff,
-                                                            int* pcount) {
-    __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kHS];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ridx = blockIdx.x * kWaves + w;
-    if (ridx >= nrows) return;
+__device__ void symbolic_row(int ridx, const int* rows, const int* arp, const int* acol, const int* brp,
+                             const int* bcol, int* cnt, int* gkeys, const int64_t* goff, int* pcount, int* lds_keys) {
+    const int lane = threadIdx.x & 63;
     const int i = rows ? rows[ridx] : ridx;
     int* keys;
     unsigned mask;
@@ -165,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int
         keys = gkeys + o;
         mask = (unsigned)(goff[ridx + 1] - o) - 1;
     } else {
-        keys = skeys[w];
+        keys = lds_keys;
         const int m = row_products(arp, acol, brp, i);
         if (lane == 0) pcount[i] = m;
         mask = lds_table_mask(m);
@@ -191,23 +187,28 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int
     }
 }
 
-// LDS path (GLOBAL = false): the rows whose product count m lies in
-// (mlo, mhi] and that did not overflow (skip), with HS hash slots per wave
-// (HS >= 2 * mhi unless HS = kHS); GLOBAL: the listed overflow rows.
+// rows [0, nrows) of the list (all rows if rows is null), a wavefront per
+// row, grid-stride; nrows_dev (if set) holds the row count on the device
+template <bool GLOBAL>
+__global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int* nrows_dev, const int* rows,
+                                                            const int* arp, const int* acol, const int* brp,
+                                                            const int* bcol, int* cnt, int* gkeys,
+                                                            const int64_t* goff, int* pcount) {
+    __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kHS];
+    const int w = threadIdx.x >> 6;
+    const int nr = nrows_dev ? *nrows_dev : nrows;
+    for (int ridx = blockIdx.x * kWaves + w; ridx < nr; ridx += gridDim.x * kWaves)
+        symbolic_row<GLOBAL>(ridx, rows, arp, acol, brp, bcol, cnt, gkeys, goff, pcount, skeys[GLOBAL ? 0 : w]);
+}
+
+// one row (list position ridx) of the numeric phase, by one wavefront
 template <bool GLOBAL, int HS>
-__global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int* rows, const int* arp,
-                                                           const int* acol, const double* aval, const int* brp,
-                                                           const int* bcol, const double* bval, const int* crp,
-                                                           int* ccol, double* cval, const int* skip, int* gkeys,
-                                                           int* gvals, double* gacc, const int64_t* goff,
-                                                           const int* pcount, int mlo, int mhi) {
-    __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS];
-    __shared__ int svals[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS];
-    __shared__ double sacc[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS / 2];
-    __shared__ int stile[GLOBAL ? kWaves : 1][GLOBAL ? kRankTile : 1];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ridx = blockIdx.x * kWaves + w;
-    if (ridx >= nrows) return;
+__device__ void numeric_row(int ridx, const int* rows, const int* arp, const int* acol, const double* aval,
+                            const int* brp, const int* bcol, const double* bval, const int* crp, int* ccol,
+                            double* cval, const int* skip, int* gkeys, int* gvals, double* gacc, const int64_t* goff,
+                            const int* pcount, int mlo, int mhi, int* lds_keys, int* lds_vals, double* lds_acc,
+                            int* lds_tile) {
+    const int lane = threadIdx.x & 63;
     const int i = rows ? rows[ridx] : ridx;
     int m = 0;
     if constexpr (!GLOBAL) {
@@ -225,9 +226,9 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
         acc = gacc + o;
         mask = (unsigned)(goff[ridx + 1] - o) - 1;
     } else {
-        keys = skeys[w];
-        vals = svals[w];
-        acc = sacc[w];
+        keys = lds_keys;
+        vals = lds_vals;
+        acc = lds_acc;
         mask = lds_table_mask(m);
     }
     for (unsigned h = lane; h <= mask; h += 64) {
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
     } else {
         // long rows: kRankKeys keys per lane at a time, compared against the
         // list staged through LDS in tiles
-        int* tile = stile[w];
+        int* tile = lds_tile;
         for (int e0 = 0; e0 < d; e0 += 64 * kRankKeys) {
             int c[kRankKeys], r[kRankKeys];
 #pragma unroll
@@ -331,6 +332,161 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
     for (int e = lane; e < d; e += 64) cval[base + e] = acc[e];
 }
 
+// LDS path (GLOBAL = false): the rows of the list whose product count m lies
+// in (mlo, mhi] and that did not overflow (skip), with HS hash slots per
+// wave (HS >= 2 * mhi unless HS = kHS); GLOBAL: the listed overflow rows.
+// A wavefront per row, grid-stride; nrows_dev (if set) holds the count.
+template <bool GLOBAL, int HS>
+__global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int* nrows_dev, const int* rows,
+                                                           const int* arp, const int* acol, const double* aval,
+                                                           const int* brp, const int* bcol, const double* bval,
+                                                           const int* crp, int* ccol, double* cval, const int* skip,
+                                                           int* gkeys, int* gvals, double* gacc,
+                                                           const int64_t* goff, const int* pcount, int mlo, int mhi) {
+    __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS];
+    __shared__ int svals[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS];
+    __shared__ double sacc[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS / 2];
+    __shared__ int stile[GLOBAL ? kWaves : 1][GLOBAL ? kRankTile : 1];
+    const int w = threadIdx.x >> 6;
+    const int nr = nrows_dev ? *nrows_dev : nrows;
+    for (int ridx = blockIdx.x * kWaves + w; ridx < nr; ridx += gridDim.x * kWaves)
+        numeric_row<GLOBAL, HS>(ridx, rows, arp, acol, aval, brp, bcol, bval, crp, ccol, cval, skip, gkeys, gvals,
+                                gacc, goff, pcount, mlo, mhi, skeys[GLOBAL ? 0 : w], svals[GLOBAL ? 0 : w],
+                                sacc[GLOBAL ? 0 : w], stile[GLOBAL ? w : 0]);
+}
+
+// --------------------------------------------------- one thread per row
+// Rows with at most kThreadCols distinct output columns (most rows of the
+// finer levels' products) are multiplied by one thread each: the thread walks
+// its row's products in the canonical order and keeps the distinct columns,
+// in order of first appearance, in registers with their running sums; the
+// sorted output position of each is its rank among them.  Every entry
+// therefore gets the same additions, in the same order, as on the wavefront
+// path.
+constexpr int kThreadCols = 32;
+constexpr int kThreadRow = -3;  // pcount marker of a row on the thread path
+
+// add product (c, v) to the row's column list key/acc[0..d) (v when VAL);
+// returns false when a new column does not fit
+template <bool VAL>
+__device__ __forceinline__ bool thread_row_add(int (&key)[kThreadCols], double (&acc)[kThreadCols], int& d, int c,
+                                               double v) {
+    bool found = false;
+#pragma unroll
+    for (int j = 0; j < kThreadCols; ++j)
+        if (key[j] == c) {
+            found = true;
+            if constexpr (VAL) acc[j] += v;
+        }
+    if (found) return true;
+    if (d == kThreadCols) return false;
+#pragma unroll
+    for (int j = 0; j < kThreadCols; ++j)
+        if (j == d) {
+            key[j] = c;
+            if constexpr (VAL) acc[j] = 0.0 + v;  // as the wavefront path: a zeroed sum plus the first product
+        }
+    ++d;
+    return true;
+}
+
+// the products of row i in canonical order, f(column, value): A's row in
+// chunks of CH entries whose column, B-row bounds and first B entry are all
+// loaded before any is used (P rows mostly hold one entry), so a chunk costs
+// three memory latencies instead of three per entry
+template <bool VAL, int CH, typename F>
+__device__ __forceinline__ void thread_row_products(const int* arp, const int* acol, const double* aval,
+                                                    const int* brp, const int* bcol, const double* bval, int i,
+                                                    F&& f) {
+    const int a0 = arp[i], a1 = arp[i + 1];
+    for (int c0 = a0; c0 < a1; c0 += CH) {
+        int kk[CH], b0[CH], b1[CH], fc[CH];
+        double av[CH], fv[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int ka = min(c0 + u, a1 - 1);
+            kk[u] = acol[ka];
+            av[u] = VAL ? aval[ka] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            b0[u] = brp[kk[u]];
+            b1[u] = brp[kk[u] + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int kb = b0[u] < b1[u] ? b0[u] : 0;
+            fc[u] = bcol[kb];
+            fv[u] = VAL ? bval[kb] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            if (c0 + u >= a1 || b0[u] >= b1[u]) continue;
+            f(fc[u], VAL ? av[u] * fv[u] : 0.0);
+            for (int kb = b0[u] + 1; kb < b1[u]; ++kb) f(bcol[kb], VAL ? av[u] * bval[kb] : 0.0);
+        }
+    }
+}
+
+// symbolic: cnt[i] = distinct columns and pcount[i] = kThreadRow for rows
+// that fit; wide[i] = 1 (and cnt[i] untouched) for the others
+__global__ __launch_bounds__(kBlock) void k_spgemm_symbolic_thread(int n, const int* arp, const int* acol,
+                                                                   const int* brp, const int* bcol, int* cnt,
+                                                                   int* pcount, int* wide) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int key[kThreadCols];
+        double acc[kThreadCols];
+#pragma unroll
+        for (int j = 0; j < kThreadCols; ++j) key[j] = -1;
+        int d = 0;
+        bool fits = true;
+        thread_row_products<false, 8>(arp, acol, nullptr, brp, bcol, nullptr, i, [&](int c, double) {
+            if (fits && !thread_row_add<false>(key, acc, d, c, 0.0)) fits = false;
+        });
+        wide[i] = fits ? 0 : 1;
+        if (fits) {
+            cnt[i] = d;
+            pcount[i] = kThreadRow;
+        }
+    }
+}
+
+// numeric for the rows the thread symbolic pass kept
+__global__ __launch_bounds__(kBlock) void k_spgemm_numeric_thread(int n, const int* arp, const int* acol,
+                                                                  const double* aval, const int* brp,
+                                                                  const int* bcol, const double* bval,
+                                                                  const int* pcount, const int* crp, int* ccol,
+                                                                  double* cval) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (pcount[i] != kThreadRow) continue;
+        int key[kThreadCols];
+        double acc[kThreadCols];
+#pragma unroll
+        for (int j = 0; j < kThreadCols; ++j) {
+            key[j] = -1;
+            acc[j] = 0.0;
+        }
+        int d = 0;
+        thread_row_products<true, 4>(arp, acol, aval, brp, bcol, bval, i,
+                                     [&](int c, double v) { (void)thread_row_add<true>(key, acc, d, c, v); });
+        const int base = crp[i];
+#pragma unroll
+        for (int j = 0; j < kThreadCols; ++j) {
+            if (key[j] < 0) continue;
+            int r = 0;
+#pragma unroll
+            for (int q = 0; q < kThreadCols; ++q) r += (key[q] >= 0 && key[q] < key[j]) ? 1 : 0;
+            ccol[base + r] = key[j];
+            cval[base + r] = acc[j];
+        }
+    }
+}
+
+__global__ void k_list_flagged(int n, const int* flags, const int* pos, int* list) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        if (flags[i]) list[pos[i]] = i;
+}
+
 // product-count upper bound of each listed row, as a hash table size (power of two >= 2*m)
 __global__ void k_row_table_size(int nrows, const int* rows, const int* arp, const int* acol, const int* brp,
                                  int ncols, int64_t* size) {
@@ -345,9 +501,18 @@ __global__ void k_row_table_size(int nrows, const int* rows, const int* arp, con
     }
 }
 
-__global__ void k_overflow_flags(int n, const int* cnt, int* flags) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+// flags[i] = row i overflowed the LDS table; cntc[i] = its count, 0 if it did
+__global__ void k_overflow_flags(int n, const int* cnt, int* flags, int* cntc) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         flags[i] = cnt[i] < 0 ? 1 : 0;
+        cntc[i] = cnt[i] < 0 ? 0 : cnt[i];
+    }
+}
+
+// out = {*a, *b}, for one read-back of two device values
+__global__ void k_pair(const int* a, const int* b, int* out) {
+    out[0] = *a;
+    out[1] = *b;
 }
 
 __global__ void k_overflow_list(int n, const int* flags, const int* pos, int* list) {
@@ -416,18 +581,36 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
     C.m = B.m;
     const int nn = n > 0 ? n : 1;
     DBuf<int> cnt((size_t)nn, mc), flags((size_t)nn, mc), pos((size_t)n + 1, mc), pcount((size_t)nn, mc);
+    DBuf<int> wide((size_t)nn, mc), wpos((size_t)n + 1, mc), wl((size_t)nn, mc), cntc((size_t)nn, mc);
     DBuf<int> tmp(scan_tmp_size(n), mc);
-    const int nb = ceil_div(nn, kWaves);
+    C.rowptr.alloc((size_t)n + 1, mc);
+    // wavefront launches loop over a row list whose length stays on the device
+    const int wgrid = std::max(1, std::min(ceil_div(nn, kWaves), 8192));
+    const int* nwide_dev = wpos.get() + n;
     if (n > 0) {
-        hipLaunchKernelGGL((k_spgemm_symbolic<false>), dim3(nb), dim3(kBlock), 0, s, n, (const int*)nullptr,
-                           A.rowptr.get(), A.col.get(), B.rowptr.get(), B.col.get(), cnt.get(), (int*)nullptr,
-                           (const int64_t*)nullptr, pcount.get());
-        hipLaunchKernelGGL(k_overflow_flags, dim3(g1(n)), dim3(kBlock), 0, s, n, cnt.get(), flags.get());
+        // one thread per row where at most kThreadCols columns come out; the
+        // remaining (wide) rows take a wavefront each
+        hipLaunchKernelGGL(k_spgemm_symbolic_thread, dim3(g1(n)), dim3(kBlock), 0, s, n, A.rowptr.get(),
+                           A.col.get(), B.rowptr.get(), B.col.get(), cnt.get(), pcount.get(), wide.get());
+        exclusive_scan(wide.get(), wpos.get(), n, tmp.get(), s);
+        hipLaunchKernelGGL(k_list_flagged, dim3(g1(n)), dim3(kBlock), 0, s, n, (const int*)wide.get(),
+                           (const int*)wpos.get(), wl.get());
+        hipLaunchKernelGGL((k_spgemm_symbolic<false>), dim3(wgrid), dim3(kBlock), 0, s, 0, nwide_dev,
+                           (const int*)wl.get(), A.rowptr.get(), A.col.get(), B.rowptr.get(), B.col.get(), cnt.get(),
+                           (int*)nullptr, (const int64_t*)nullptr, pcount.get());
+        // overflow flags, and the row pointer as if no row overflowed
+        hipLaunchKernelGGL(k_overflow_flags, dim3(g1(n)), dim3(kBlock), 0, s, n, (const int*)cnt.get(), flags.get(),
+                           cntc.get());
         MATAMG_LAUNCH_CHECK();
     }
     exclusive_scan(flags.get(), pos.get(), n, tmp.get(), s);
-    int novf = 0;
-    d2h(&novf, pos.get() + n, 1, s);
+    exclusive_scan(cntc.get(), C.rowptr.get(), n, tmp.get(), s);
+    int head[2] = {0, 0};  // overflow rows, stored entries
+    hipLaunchKernelGGL(k_pair, dim3(1), dim3(1), 0, s, (const int*)pos.get() + n, (const int*)C.rowptr.get() + n,
+                       cntc.get());
+    d2h(head, cntc.get(), 2, s);
+    const int novf = head[0];
+    int nnz = head[1];
     DBuf<int> list;
     DBuf<int64_t> tsize, toff;
     DBuf<int> gkeys, gvals;
@@ -447,36 +630,37 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
         gvals.alloc((size_t)tot, mc);
         gacc.alloc((size_t)tot, mc);
         hipLaunchKernelGGL((k_spgemm_symbolic<true>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
-                           list.get(), A.rowptr.get(), A.col.get(), B.rowptr.get(), B.col.get(), cnt.get(),
-                           gkeys.get(), toff.get(), (int*)nullptr);
+                           (const int*)nullptr, list.get(), A.rowptr.get(), A.col.get(), B.rowptr.get(), B.col.get(),
+                           cnt.get(), gkeys.get(), toff.get(), (int*)nullptr);
         MATAMG_LAUNCH_CHECK();
+        exclusive_scan(cnt.get(), C.rowptr.get(), n, tmp.get(), s);
+        d2h(&nnz, C.rowptr.get() + n, 1, s);
     }
-    C.rowptr.alloc((size_t)n + 1, mc);
-    exclusive_scan(cnt.get(), C.rowptr.get(), n, tmp.get(), s);
-    int nnz = 0;
-    d2h(&nnz, C.rowptr.get() + n, 1, s);
     C.nnz = nnz;
     C.col.alloc((size_t)(nnz > 0 ? nnz : 1), mc);
     C.val.alloc((size_t)(nnz > 0 ? nnz : 1), mc);
     if (n > 0) {
-        // rows with few products: small tables, so more wavefronts fit a CU
-        hipLaunchKernelGGL((k_spgemm_numeric<false, kHSSmall>), dim3(nb), dim3(kBlock), 0, s, n, (const int*)nullptr,
-                           A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(), B.val.get(),
-                           C.rowptr.get(), C.col.get(), C.val.get(), (const int*)flags.get(), (int*)nullptr,
-                           (int*)nullptr, (double*)nullptr, (const int64_t*)nullptr, (const int*)pcount.get(), -1,
-                           kHSSmall / 2);
-        hipLaunchKernelGGL((k_spgemm_numeric<false, kHS>), dim3(nb), dim3(kBlock), 0, s, n, (const int*)nullptr,
-                           A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(), B.val.get(),
-                           C.rowptr.get(), C.col.get(), C.val.get(), (const int*)flags.get(), (int*)nullptr,
-                           (int*)nullptr, (double*)nullptr, (const int64_t*)nullptr, (const int*)pcount.get(),
-                           kHSSmall / 2, 0x7fffffff);
+        hipLaunchKernelGGL(k_spgemm_numeric_thread, dim3(g1(n)), dim3(kBlock), 0, s, n, A.rowptr.get(), A.col.get(),
+                           A.val.get(), B.rowptr.get(), B.col.get(), B.val.get(), (const int*)pcount.get(),
+                           C.rowptr.get(), C.col.get(), C.val.get());
+        // wide rows with few products: small tables, so more wavefronts fit a CU
+        hipLaunchKernelGGL((k_spgemm_numeric<false, kHSSmall>), dim3(wgrid), dim3(kBlock), 0, s, 0, nwide_dev,
+                           (const int*)wl.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(),
+                           B.val.get(), C.rowptr.get(), C.col.get(), C.val.get(), (const int*)flags.get(),
+                           (int*)nullptr, (int*)nullptr, (double*)nullptr, (const int64_t*)nullptr,
+                           (const int*)pcount.get(), -1, kHSSmall / 2);
+        hipLaunchKernelGGL((k_spgemm_numeric<false, kHS>), dim3(wgrid), dim3(kBlock), 0, s, 0, nwide_dev,
+                           (const int*)wl.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(),
+                           B.val.get(), C.rowptr.get(), C.col.get(), C.val.get(), (const int*)flags.get(),
+                           (int*)nullptr, (int*)nullptr, (double*)nullptr, (const int64_t*)nullptr,
+                           (const int*)pcount.get(), kHSSmall / 2, 0x7fffffff);
         MATAMG_LAUNCH_CHECK();
     }
     if (novf > 0) {
         hipLaunchKernelGGL((k_spgemm_numeric<true, 1>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
-                           list.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(),
-                           B.val.get(), C.rowptr.get(), C.col.get(), C.val.get(), (const int*)nullptr, gkeys.get(),
-                           gvals.get(), gacc.get(), toff.get(), (const int*)nullptr, 0, 0);
+                           (const int*)nullptr, list.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(),
+                           B.col.get(), B.val.get(), C.rowptr.get(), C.col.get(), C.val.get(), (const int*)nullptr,
+                           gkeys.get(), gvals.get(), gacc.get(), toff.get(), (const int*)nullptr, 0, 0);
         MATAMG_LAUNCH_CHECK();
     }
     // no synchronisation: temporaries go back to the pool in stream order

@@ -23,13 +23,11 @@ std::vector<int> stream_blocks(const int* rowptr_host, int n, int group);
 // threads per row for a matrix (host row pointer): stream_group_rule
 int stream_group(const int* rowptr_host, int n);
 // A.group, A.nblk and A.blk from A's device row pointer (the same greedy
-// partition as stream_blocks, computed on the device); reads back the block
-// count, so s is synchronised once
-void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s);
-
-// A.col16 and A.cbase from A's row blocks when every block's columns span
-// fewer than 2^16 values (otherwise both stay empty); reads back one flag
-void pack_columns(DCsr& A, MemCounter* mc, hipStream_t s);
+// partition as stream_blocks, computed on the device), and with `pack`
+// A.col16 and A.cbase when every block's columns span fewer than 2^16
+// values (otherwise both stay empty); reads back the block count, so s is
+// synchronised once
+void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack);
 
 // dot partials of a streaming launch: one per wavefront of each row block
 constexpr int kStreamPartials = kBlock / 64;

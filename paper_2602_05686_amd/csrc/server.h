@@ -64,6 +64,9 @@ class Server {
     std::unique_ptr<Request> take(uint64_t id);
     void stats(ServerStats* st, int64_t* budget, int64_t* used, int64_t* peak_used, int* active, int64_t* waiting);
     double now() const;
+    // an idle engine waits up to this long for requests still in setup
+    // before it starts solving the ready ones (0: start at once)
+    void set_batch_wait(double seconds);
 
   private:
     void worker_main();
@@ -86,6 +89,8 @@ class Server {
     std::deque<uint64_t> done_q_;
     uint64_t next_id_ = 1;
     bool stop_ = false;
+    int in_setup_ = 0;         // admitted requests whose setup has not finished
+    double batch_wait_ = 0.0;
     ServerStats st_;
     std::vector<std::thread> workers_;
     std::thread engine_;

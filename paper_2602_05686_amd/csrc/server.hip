@@ -352,12 +352,18 @@ amg_status Server::submit(int64_t n, const int* rowptr, const int* col, const do
     return AMG_OK;
 }
 
+void Server::set_batch_wait(double seconds) {
+    std::lock_guard<std::mutex> lk(mu_);
+    batch_wait_ = seconds;
+}
+
 void Server::admit_locked() {
     const double t = now();
     for (uint64_t id : adm_.admit()) {
         Request* R = reqs_.at(id).get();
         R->t_admit = t;
         setup_q_.push_back(R);
+        ++in_setup_;
     }
     if (!setup_q_.empty()) cv_setup_.notify_all();
 }
@@ -451,6 +457,7 @@ void Server::worker_main() {
             std::vector<double>().swap(R->coords);
             std::lock_guard<std::mutex> lk(mu_);
             R->t_setup_done = now();
+            --in_setup_;
             if (code != AMG_OK) {
                 R->status = code;
                 R->error = msg;
@@ -465,8 +472,8 @@ void Server::worker_main() {
                 adm_.resize(R->id, R->resident);
                 ready_.push_back(R);
                 admit_locked();
-                cv_engine_.notify_one();
             }
+            cv_engine_.notify_one();  // a waiting engine counts the requests still in setup
         }
     }
     (void)hipStreamSynchronize(s);
@@ -649,6 +656,14 @@ void Server::engine_main() {
             std::unique_lock<std::mutex> lk(mu_);
             cv_engine_.wait(lk, [&] { return stop_ || !ready_.empty() || !solving.empty(); });
             if (stop_) break;
+            if (solving.empty() && batch_wait_ > 0.0 && in_setup_ > 0) {
+                // idle: give the requests still in setup a moment to join the first round
+                const auto until = std::chrono::steady_clock::now() +
+                                   std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                                       std::chrono::duration<double>(batch_wait_));
+                cv_engine_.wait_until(lk, until, [&] { return stop_ || in_setup_ == 0; });
+                if (stop_) break;
+            }
             fresh.swap(ready_);
         }
         try {

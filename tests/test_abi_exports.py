@@ -108,4 +108,6 @@ def test_server_argument_checks_precede_device_work(lib):
     assert lib.amg_server_create(ctypes.byref(o), 1 << 30, 4, 0, ctypes.byref(s)) == 1
     nd = ctypes.c_int32()
     assert lib.amg_server_poll(None, 0.0, None, 0, ctypes.byref(nd)) == 1
+    lib.amg_server_set_batch_wait.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    assert lib.amg_server_set_batch_wait(None, 0.5) == 1
     lib.amg_server_destroy(None)

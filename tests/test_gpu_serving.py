@@ -93,7 +93,9 @@ def stream():
 @pytest.fixture(scope="module")
 def mixed(amg, stream):
     banner("serving the mixed stream (all submitted at once)")
-    return serve(amg, stream, "fp32", max_active=8, max_coarse=200)
+    # setups of requests this small take longer than their solves: the
+    # engine waits for the ones still in setup so that the rounds are shared
+    return serve(amg, stream, "fp32", max_active=8, max_coarse=200, batch_wait_s=2.0)
 
 
 def test_mixed_stream_batches_and_completes(amg, stream, mixed):
