@@ -376,8 +376,21 @@ __device__ __forceinline__ void gemv_body(const GemvArgs<T>& a, int lb) {
     const int row = lb * (kBlock / 64) + (threadIdx.x >> 6);
     if (row >= a.n) return;
     const double* m = a.M + (size_t)row * a.n;
+    // lane-strided sum (columns lane, lane + 64, ... in order), eight loads
+    // of the row in flight at a time
     double s = 0.0;
-    for (int j = lane; j < a.n; j += 64) s += m[j] * (double)a.in[j];
+    int j = lane;
+    for (; j + 7 * 64 < a.n; j += 8 * 64) {
+        double mv[8], iv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            mv[u] = m[j + u * 64];
+            iv[u] = (double)a.in[j + u * 64];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += mv[u] * iv[u];
+    }
+    for (; j < a.n; j += 64) s += m[j] * (double)a.in[j];
     s = wave_sum(s);
     if (lane == 0) a.out[row] = (T)s;
 }
