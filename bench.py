@@ -596,6 +596,8 @@ def main():
         h32.close()
         fp32 = dict(t_solve_s=info32["t_solve_s"], iterations=info32["iterations"], rel_res=info32["rel_res"],
                     status=info32["status"], speedup_vs_fp64_solve=t_solve / info32["t_solve_s"],
+                    speedup_per_iteration=(t_solve / infos[-1]["iterations"]) /
+                    (info32["t_solve_s"] / max(1, info32["iterations"])),
                     rel_err_vs_fp64_form=float(np.linalg.norm(x32 - x64) / np.linalg.norm(x64)),
                     rel_err_vs_closed_form=float(np.linalg.norm(x32 - exact) / np.linalg.norm(exact)))
         log(f"fp32 form: solve {info32['t_solve_s'] * 1e3:.1f} ms, iters {info32['iterations']}")
