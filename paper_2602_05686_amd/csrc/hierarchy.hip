@@ -405,8 +405,8 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
         const int nl = L.A.n;
         const int64_t nzl = L.A.nnz;
         L.dinv.alloc(nl, mc);
-        diag_inverse(nl, L.A.rowptr.get(), L.A.col.get(), L.A.val.get(), L.dinv.get(), s);
         make_blocks(L.A, mc, s);
+        diag_inverse_blocks(L.A, L.dinv.get(), s);
         if (nl <= opt.max_coarse || l + 1 >= opt.max_levels) {
             if (nl > opt.max_coarse)
                 fail(AMG_ERR_COARSENING_STAGNATED, "level cap reached with " + std::to_string(nl) + " unknowns");
@@ -561,7 +561,7 @@ void update_values(Hierarchy& h, const double* val, bool host_ptrs, hipStream_t 
     };
     for (int l = 0; l < h.nlev; ++l) {
         Level& L = h.lev[l];
-        diag_inverse(L.A.n, L.A.rowptr.get(), L.A.col.get(), L.A.val.get(), L.dinv.get(), s);
+        diag_inverse_blocks(L.A, L.dinv.get(), s);
         if (l + 1 == h.nlev) break;
         {
             DCsr P;

@@ -733,6 +733,37 @@ __global__ void k_diag_inverse(int n, const int* rowptr, const int* col, const d
     }
 }
 
+// the same over the streaming row blocks: the block's columns are staged in
+// LDS with coalesced loads, then each row's thread finds its diagonal there
+__global__ __launch_bounds__(kBlock) void k_diag_inverse_blocks(const int* rowptr, const int* col, const double* val,
+                                                                const int* blk, int nblk, double* dinv) {
+    __shared__ int cs[kStreamCap];
+    const int bid = xcd_block(nblk);
+    if (bid >= nblk) return;
+    const RowBlock rb = row_block(rowptr, blk, bid);
+    if (!rb.longrow) {
+        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) cs[t] = col[rb.k0 + t];
+        __syncthreads();
+        const int r = rb.r0 + (int)threadIdx.x;
+        if (r < rb.r1) {
+            double d = 0.0;
+            for (int k = rowptr[r]; k < rowptr[r + 1]; ++k)
+                if (cs[k - rb.k0] == r) d = val[k];
+            dinv[r] = d != 0.0 ? 1.0 / d : 0.0;
+        }
+    } else {
+        // one long row: the lane that holds the diagonal writes it (the
+        // columns are distinct), after the row is set to "none"
+        const int i = rb.r0;
+        if (threadIdx.x == 0) dinv[i] = 0.0;
+        __syncthreads();
+        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) {
+            const int k = rb.k0 + t;
+            if (col[k] == i) dinv[i] = val[k] != 0.0 ? 1.0 / val[k] : 0.0;
+        }
+    }
+}
+
 __global__ void k_densify(int n, const int* rowptr, const int* col, const double* val, double* D) {
     ROW_LOOP(i, n) {
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) D[(size_t)i * n + col[k]] = val[k];
@@ -903,6 +934,13 @@ void prolongator_finalize(int n, const int* prowptr, const int* pcol, double* pv
 void coarse_aux(int nc, int dim, const Incidence& m, const double* x, const double* sig, double* xc, double* sigc,
                 hipStream_t s) {
     LAUNCH(k_coarse_aux, nc, nc, dim, m.rowptr.get(), m.items.get(), x, sig, xc, sigc);
+}
+
+void diag_inverse_blocks(const DCsr& A, double* dinv, hipStream_t s) {
+    if (A.nblk <= 0) return;
+    hipLaunchKernelGGL(k_diag_inverse_blocks, dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, A.rowptr.get(),
+                       A.col.get(), A.val.get(), A.blk.get(), A.nblk, dinv);
+    MATAMG_LAUNCH_CHECK();
 }
 
 void bytes_differ(int n, const uint8_t* a, const uint8_t* b, int* flag, hipStream_t s) {

@@ -58,6 +58,8 @@ void prolongator_finalize(int n, const int* prowptr, const int* pcol, double* pv
 void coarse_aux(int nc, int dim, const Incidence& members, const double* x, const double* sig, double* xc,
                 double* sigc, hipStream_t s);
 void diag_inverse(int n, const int* rowptr, const int* col, const double* val, double* dinv, hipStream_t s);
+// the same over A's streaming row blocks (A.blk must be set)
+void diag_inverse_blocks(const DCsr& A, double* dinv, hipStream_t s);
 void densify(int n, const int* rowptr, const int* col, const double* val, double* D, hipStream_t s);
 // CSR sanity: columns in range and strictly ascending; *flag set on violation
 void validate_csr(int n, const int* rowptr, const int* col, int64_t nnz, int* flag, hipStream_t s);
