@@ -108,6 +108,70 @@ struct StreamShared {
 // kBlock) strides per thread: all loads first (indices past the end clamped
 // to the last entry, results discarded), then the gathers, then the stores.
 // PACKED: the columns come from the 16-bit col16 plus the block's base.
+// packed columns, two entries per load: the block's entries from its first
+// even position are read as aligned pairs (a pair of values, a pair of
+// 16-bit columns), NP = ceil(pairs / kBlock) strides per thread; an entry left
+// over at either end (odd start, odd length) is read alone by thread 0 or 1.
+template <typename T>
+struct PairOf;
+template <>
+struct PairOf<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct PairOf<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int stage_head(int k0, int cnt) { return cnt > 0 ? (k0 & 1) : 0; }
+
+template <typename T, int NP>
+__device__ __forceinline__ void stage_pairs(const SArgs<T>& a, int bid, int k0, int cnt, T* prod) {
+    using P2 = typename PairOf<T>::type;
+    const int base = a.cbase[bid];
+    const int head = stage_head(k0, cnt);  // entry 0 alone when the block starts at an odd position
+    const int body = cnt - head;
+    const int np = body >> 1;  // whole pairs from the even position k0 + head
+    const int kp = k0 + head;
+    const int tid = (int)threadIdx.x;
+    u16x2 c[NP > 0 ? NP : 1];
+    P2 v[NP > 0 ? NP : 1];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+        const int p = tid + u * kBlock;
+        const int pc = p < np ? p : np - 1;
+        c[u] = __builtin_nontemporal_load(reinterpret_cast<const u16x2*>(a.col16 + kp + 2 * pc));
+        v[u] = __builtin_nontemporal_load(reinterpret_cast<const P2*>(a.val + kp + 2 * pc));
+    }
+    // the single entries: the head (thread 0) and, for an odd body, the tail (thread 1)
+    int ts = -1;
+    if (tid == 0 && head) ts = 0;
+    if (tid == 1 && (body & 1)) ts = cnt - 1;
+    int cs = 0;
+    T vs = 0;
+    if (ts >= 0) {
+        cs = base + (int)a.col16[k0 + ts];
+        vs = a.val[k0 + ts];
+    }
+    T x0[NP > 0 ? NP : 1], x1[NP > 0 ? NP : 1];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+        x0[u] = a.x[base + (int)c[u].x];
+        x1[u] = a.x[base + (int)c[u].y];
+    }
+    const T xs = ts >= 0 ? a.x[cs] : T(0);
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+        const int p = tid + u * kBlock;
+        if (p < np) {
+            prod[head + 2 * p] = v[u].x * x0[u];
+            prod[head + 2 * p + 1] = v[u].y * x1[u];
+        }
+    }
+    if (ts >= 0) prod[ts] = vs * xs;
+}
+
 template <typename T, int NU, bool PACKED>
 __device__ __forceinline__ void stage_products(const SArgs<T>& a, int bid, int k0, int cnt, T* prod) {
     int c[NU];
@@ -161,15 +225,13 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
         // from packed or plain columns (uniform per matrix)
         const int nu = (cnt + kBlock - 1) / kBlock;
         if (a.col16) {
-            switch (nu) {
-                case 1: stage_products<T, 1, true>(a, bid, k0, cnt, S.prod); break;
-                case 2: stage_products<T, 2, true>(a, bid, k0, cnt, S.prod); break;
-                case 3: stage_products<T, 3, true>(a, bid, k0, cnt, S.prod); break;
-                case 4: stage_products<T, 4, true>(a, bid, k0, cnt, S.prod); break;
-                case 5: stage_products<T, 5, true>(a, bid, k0, cnt, S.prod); break;
-                case 6: stage_products<T, 6, true>(a, bid, k0, cnt, S.prod); break;
-                case 7: stage_products<T, 7, true>(a, bid, k0, cnt, S.prod); break;
-                case 8: stage_products<T, 8, true>(a, bid, k0, cnt, S.prod); break;
+            // pairs of entries: ceil(pairs / kBlock) strides (block-uniform)
+            switch (((cnt - stage_head(k0, cnt)) / 2 + kBlock - 1) / kBlock) {
+                case 0: stage_pairs<T, 0>(a, bid, k0, cnt, S.prod); break;
+                case 1: stage_pairs<T, 1>(a, bid, k0, cnt, S.prod); break;
+                case 2: stage_pairs<T, 2>(a, bid, k0, cnt, S.prod); break;
+                case 3: stage_pairs<T, 3>(a, bid, k0, cnt, S.prod); break;
+                case 4: stage_pairs<T, 4>(a, bid, k0, cnt, S.prod); break;
                 default: break;
             }
         } else {
