@@ -141,6 +141,9 @@ struct DCsr {
     // row blocks for the streaming SpMV: blk[b] .. blk[b+1] rows of block b;
     // `group` threads reduce each row (1 for short rows, 8 when rows are long)
     DBuf<int> blk;
+    // blkk[b] = rowptr[blk[b]]: first stored entry of block b (nblk + 1
+    // values), so a streaming block knows its entry range from its index
+    DBuf<int> blkk;
     int nblk = 0;
     int group = 1;
     // packed columns for the streaming SpMV (when every row block's columns

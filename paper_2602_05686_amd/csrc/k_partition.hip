@@ -174,6 +174,11 @@ __global__ __launch_bounds__(kBlock) void k_pack_cols(int nblk, const int* rp, c
     }
 }
 
+// blkk[b] = rp[blk[b]] for b <= nblk
+__global__ void k_block_entries(int nblk, const int* rp, const int* blk, int* blkk) {
+    FOR_ROWS(b, (int64_t)nblk + 1) blkk[b] = rp[blk[b]];
+}
+
 }  // namespace
 
 void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack) {
@@ -184,7 +189,9 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack) {
         A.group = 1;
         A.nblk = 0;
         A.blk.alloc(1, mc);
+        A.blkk.alloc(1, mc);
         MATAMG_HIP(hipMemsetAsync(A.blk.get(), 0, sizeof(int), s));
+        MATAMG_HIP(hipMemsetAsync(A.blkk.get(), 0, sizeof(int), s));
         MATAMG_HIP(hipStreamSynchronize(s));
         return;
     }
@@ -241,6 +248,10 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack) {
     A.nblk = nblk;
     A.blk.alloc((size_t)nblk + 1, mc);
     MATAMG_HIP(hipMemcpyAsync(A.blk.get(), blk.get(), sizeof(int) * ((size_t)nblk + 1), hipMemcpyDeviceToDevice, s));
+    A.blkk.alloc((size_t)nblk + 1, mc);
+    hipLaunchKernelGGL(k_block_entries, dim3(grid1((int64_t)nblk + 1)), dim3(kBlock), 0, s, nblk, rp,
+                       (const int*)A.blk.get(), A.blkk.get());
+    MATAMG_LAUNCH_CHECK();
     if (pack && A.nnz > 0 && res[3] == 0) {
         A.cbase.alloc((size_t)nblk, mc);
         MATAMG_HIP(hipMemcpyAsync(A.cbase.get(), cbase.get(), sizeof(int) * (size_t)nblk, hipMemcpyDeviceToDevice, s));

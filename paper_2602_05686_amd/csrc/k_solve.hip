@@ -209,6 +209,7 @@ SArgs<T> base_args(const DCsr& A, const T* val, const T* x) {
     a.cbase = A.cbase.get();
     a.val = val;
     a.blk = A.blk.get();
+    a.blkk = A.blkk.get();
     a.x = x;
     return a;
 }

@@ -70,6 +70,7 @@ SArgs<T> sargs(const DCsr& M, const T* val, const T* x) {
     a.cbase = M.cbase.get();
     a.val = val;
     a.blk = M.blk.get();
+    a.blkk = M.blkk.get();
     a.x = x;
     return a;
 }

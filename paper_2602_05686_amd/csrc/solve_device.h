@@ -27,6 +27,7 @@ struct SArgs {
     const int* cbase;
     const T* val;
     const int* blk;
+    const int* blkk;   // first entry of each block (rowptr at its first row)
     const T* x;        // gathered operand
     const T* b;        // right-hand side (RESID, SMOOTH, RESNORM)
     const T* yin;      // ADD: base vector; SMOOTH: iterate at the row
@@ -207,8 +208,10 @@ __device__ __forceinline__ void stage_products(const SArgs<T>& a, int bid, int k
 // branch, and no wait, between them.
 template <typename T, int MODE, bool HAS_DOT, int G>
 __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamShared<T>& S) {
+    // rows and entries of the block from the two tables: the loads of the
+    // entries do not wait for the row pointer
     const int r0 = a.blk[bid], r1 = a.blk[bid + 1];
-    const int k0 = a.rowptr[r0], k1 = a.rowptr[r1];
+    const int k0 = a.blkk[bid], k1 = a.blkk[bid + 1];
     const int cnt = k1 - k0;
     double dp = 0.0;
     if (!(r1 - r0 == 1 && cnt > long_row_limit(G))) {
