@@ -615,7 +615,9 @@ void Hierarchy::vcycle_t(const double* r64, double* z64, DotTarget rz, hipStream
         }
         T* x = V::xa(Lv);
         T* y = V::xb(Lv);
-        smooth_first<T>(n, b64, b, V::dinv(Lv), (T)Lv.c2[0], V::d(Lv), x, s);
+        // the first step from zero; below the finest level the restriction
+        // that made b has already taken it
+        if (l == 0) smooth_first<T>(n, b64, b, V::dinv(Lv), (T)Lv.c2[0], V::d(Lv), x, s);
         for (size_t k = 1; k < Lv.c1.size(); ++k) {
             spmv_smooth<T>(Lv.A, V::A(Lv.A), x, b, V::dinv(Lv), V::d(Lv), (T)Lv.c1[k], (T)Lv.c2[k], y, nullptr,
                            nullptr, DotTarget{}, s);
@@ -623,7 +625,12 @@ void Hierarchy::vcycle_t(const double* r64, double* z64, DotTarget rz, hipStream
         }
         cur[l] = x;
         spmv_resid<T>(Lv.A, V::A(Lv.A), x, b, V::r(Lv), s);
-        spmv<T>(Lv.R, V::A(Lv.R), V::r(Lv), V::b(lev[l + 1]), s);
+        Level& Ln = lev[l + 1];
+        if (l + 2 < L)
+            spmv_restrict_first<T>(Lv.R, V::A(Lv.R), V::r(Lv), V::b(Ln), V::dinv(Ln), (T)Ln.c2[0], V::d(Ln),
+                                   V::xa(Ln), s);
+        else
+            spmv<T>(Lv.R, V::A(Lv.R), V::r(Lv), V::b(Ln), s);
     }
     // coarsest level
     Level& Lc = lev[L - 1];
@@ -681,12 +688,13 @@ double Hierarchy::vcycle_alg_bytes() const {
         bytes += n_spmv * matrix(L.A);
         bytes += matrix(L.R);  // R r
         bytes += matrix(L.P);  // x += P e
-        // vectors: first step reads b, dinv, writes d, x (4); each smoother
-        // SpMV reads x, b, dinv, d and writes d, x (6); residual reads x, b,
-        // writes r (3); restriction reads r, writes b_c; prolongation reads
-        // e_c, x, writes x
-        const double vec_n = 4.0 + 6.0 * ((steps - 1.0) + steps) + 3.0 + 1.0 + 2.0;
-        const double vec_c = 1.0 + 1.0;
+        // vectors: the finest level's first step reads b, dinv, writes d, x
+        // (4); each smoother SpMV reads x, b, dinv, d and writes d, x (6);
+        // residual reads x, b, writes r (3); restriction reads r, writes b_c
+        // and, above the coarsest level, takes that level's first step
+        // (reads dinv_c, writes d_c, x_c); prolongation reads e_c, x, writes x
+        const double vec_n = (l == 0 ? 4.0 : 0.0) + 6.0 * ((steps - 1.0) + steps) + 3.0 + 1.0 + 2.0;
+        const double vec_c = 1.0 + 1.0 + (l + 2 < nlev ? 3.0 : 0.0);
         bytes += vec_n * s * n + vec_c * s * nc;
     }
     bytes += 8.0 * (double)nL * nL + 2.0 * s * nL;

@@ -256,6 +256,18 @@ void spmv_smooth(const DCsr& A, const T* val, const T* x, const T* b, const T* d
     else launch_stream<T, M_SMOOTH, false>(A, a, s);
 }
 
+template <typename T>
+void spmv_restrict_first(const DCsr& R, const T* val, const T* r, T* bc, const T* dinv_c, T c2, T* d_c, T* x_c,
+                         hipStream_t s) {
+    auto a = base_args<T>(R, val, r);
+    a.y = bc;
+    a.dinv = dinv_c;
+    a.c2 = c2;
+    a.d = d_c;
+    a.xo = x_c;
+    launch_stream<T, M_RESTRICT, false>(R, a, s);
+}
+
 void spmv_dot(const DCsr& A, const double* p, double* q, DotTarget dt, hipStream_t s) {
     auto a = base_args<double>(A, A.val.get(), p);
     a.y = q;
@@ -285,7 +297,9 @@ void spmv_scale_norm(const DCsr& A, const double* x, const double* dscale, doubl
     template void spmv_resid<T>(const DCsr&, const T*, const T*, const T*, T*, hipStream_t);          \
     template void spmv_add<T>(const DCsr&, const T*, const T*, const T*, T*, hipStream_t);            \
     template void spmv_smooth<T>(const DCsr&, const T*, const T*, const T*, const T*, T*, T, T, T*,   \
-                                 double*, const double*, DotTarget, hipStream_t);
+                                 double*, const double*, DotTarget, hipStream_t);                      \
+    template void spmv_restrict_first<T>(const DCsr&, const T*, const T*, T*, const T*, T, T*, T*,    \
+                                         hipStream_t);
 INST(double)
 INST(float)
 #undef INST

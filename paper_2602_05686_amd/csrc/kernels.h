@@ -29,8 +29,8 @@ int stream_group(const int* rowptr_host, int n);
 // synchronised once
 void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack);
 
-// dot partials of a streaming launch: one per wavefront of each row block
-constexpr int kStreamPartials = kBlock / 64;
+// dot partials of a streaming launch: one per row block
+constexpr int kStreamPartials = 1;  // dot partials per streaming block
 inline int stream_partials(const DCsr& A) { return A.nblk * kStreamPartials; }
 
 // dot-fusion target: per-block partial sums, reduced by finish_sum into *result
@@ -57,6 +57,11 @@ void spmv_add(const DCsr& A, const T* val, const T* x, const T* y_in, T* y, hipS
 template <typename T>
 void spmv_smooth(const DCsr& A, const T* val, const T* x, const T* b, const T* dinv, T* d, T c1, T c2, T* out,
                  double* out64, const double* dotvec, DotTarget dt, hipStream_t s);
+// restriction fused with the next level's first smoother step from zero:
+// bc = R r; d_c = c2 * dinv_c .* bc; x_c = d_c (as smooth_first on bc)
+template <typename T>
+void spmv_restrict_first(const DCsr& R, const T* val, const T* r, T* bc, const T* dinv_c, T c2, T* d_c, T* x_c,
+                         hipStream_t s);
 // q = A p and sum_i p_i q_i (FP64)
 void spmv_dot(const DCsr& A, const double* p, double* q, DotTarget dt, hipStream_t s);
 // y = b - A x and sum_i y_i^2

@@ -17,7 +17,16 @@ __host__ __device__ inline int vec_grid(int64_t n) {
 }
 
 // ----------------------------------------------------------- streaming SpMV
-enum StreamMode { M_PLAIN = 0, M_RESID = 1, M_ADD = 2, M_SMOOTH = 3, M_DOTPQ = 4, M_RESNORM = 5, M_SCALENORM = 6 };
+enum StreamMode {
+    M_PLAIN = 0,
+    M_RESID = 1,
+    M_ADD = 2,
+    M_SMOOTH = 3,
+    M_DOTPQ = 4,
+    M_RESNORM = 5,
+    M_SCALENORM = 6,
+    M_RESTRICT = 7  // y = A x, then the first smoother step on y as right-hand side
+};
 
 template <typename T>
 struct SArgs {
@@ -32,8 +41,9 @@ struct SArgs {
     const T* b;        // right-hand side (RESID, SMOOTH, RESNORM)
     const T* yin;      // ADD: base vector; SMOOTH: iterate at the row
     const T* dinv;     // SMOOTH: inverse diagonal; SCALENORM: row scale
-    T* d;              // SMOOTH: direction (in/out)
+    T* d;              // SMOOTH: direction (in/out); RESTRICT: direction (out)
     T* y;              // output
+    T* xo;             // RESTRICT: first smoother iterate
     double* y64;       // SMOOTH: FP64 output instead of y
     const double* dotvec;  // SMOOTH: fused dot partner
     T c1, c2;
@@ -59,7 +69,7 @@ __device__ __forceinline__ RowOperands<T> row_operands(const SArgs<T>& a, int r)
         o.xin = a.yin[r];
     }
     if constexpr (MODE == M_DOTPQ) o.xin = a.x[r];
-    if constexpr (MODE == M_SCALENORM) o.dinv = a.dinv[r];
+    if constexpr (MODE == M_SCALENORM || MODE == M_RESTRICT) o.dinv = a.dinv[r];
     return o;
 }
 
@@ -91,6 +101,13 @@ __device__ __forceinline__ double epilogue(const SArgs<T>& a, int r, T s, const 
         T v = o.dinv * s;
         a.y[r] = v;
         dp = (double)v * (double)v;
+    } else if constexpr (MODE == M_RESTRICT) {
+        // the coarse right-hand side, and the first smoother step from a
+        // zero iterate (the same operations as smooth_first_body)
+        a.y[r] = s;
+        T di = a.c2 * (o.dinv * s);
+        a.d[r] = di;
+        a.xo[r] = di;
     }
     return dp;
 }
@@ -198,9 +215,8 @@ __device__ __forceinline__ void stage_products(const SArgs<T>& a, int bid, int k
 
 // Row block `bid` of the matrix in `a`: stream its val/col range into LDS
 // products, reduce each row with G threads (or the whole block for a long
-// row), apply the epilogue, and store each wavefront's dot partial at
-// a.dt.partial[bid * kStreamPartials + wave] (no block-wide step at the end,
-// so the waves of a block retire independently).
+// row), apply the epilogue, and store the block's dot partial (its
+// wavefront sums in wavefront order) at a.dt.partial[bid].
 //
 // Every load of the streaming phase is unconditional: indices past the
 // block's end are clamped to its last entry (or row) and the results are
@@ -314,8 +330,15 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
         }
     }
     if constexpr (HAS_DOT) {
+        // the block's partial: wavefront sums added in wavefront order
         const double t = wave_sum(dp);
-        if ((threadIdx.x & 63) == 0) a.dt.partial[bid * kStreamPartials + (threadIdx.x >> 6)] = t;
+        if ((threadIdx.x & 63) == 0) S.sh[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double u = S.sh[0];
+            for (int w = 1; w < kBlock / 64; ++w) u += S.sh[w];
+            a.dt.partial[bid] = u;
+        }
     }
 }
 
