@@ -10,8 +10,12 @@
 // that overflow it are redone with a table in global memory sized from the
 // row's product count.  Numeric phase: the distinct columns are compacted and
 // rank-sorted (ascending output columns), and the products are accumulated
-// strictly in canonical order by one lane, so every entry is the same
-// sequence of IEEE additions as a serial row-by-row product.
+// strictly in canonical order, A entry after A entry (the products of one A
+// entry have distinct columns and are added at once), so every entry is the
+// same sequence of IEEE additions as a serial row-by-row product.  Overflow
+// rows of at most kDBig columns run their numeric phase in a large LDS table
+// of a one-wavefront workgroup, the others in global memory.
+
 #pragma clang fp contract(off)
 
 #include "device_util.h"
@@ -27,6 +31,12 @@ constexpr int kDMax = 512;    // max distinct columns on the LDS path
 constexpr int kHSSmall = 256; // LDS hash slots per wave for rows of at most 128 products
 constexpr int kRankTile = 1024;  // LDS tile of the column list when ranking long rows
 constexpr int kRankKeys = 8;     // keys per lane per ranking pass
+constexpr int kDBig = 2048;      // overflow rows with at most this many columns: numeric phase in LDS
+constexpr int kHSBig = 4096;     // their LDS hash slots (one wavefront per workgroup)
+// numeric phase variants: LDS table per wavefront (rows of at most kDMax
+// columns), global-memory table, or one large LDS table per one-wavefront
+// workgroup (overflow rows of at most kDBig columns)
+enum NumericMode { N_LDS = 0, N_GLOBAL = 1, N_BIG = 2 };
 
 __device__ __forceinline__ unsigned hash_slot(int key, unsigned mask) {
     return ((unsigned)key * 2654435761u) & mask;
@@ -45,10 +55,13 @@ __device__ __forceinline__ int hash_insert(int* keys, unsigned mask, int key) {
 }
 
 // Enumerate the products of row i of A*B in canonical order, 64 per step.
-// f(valid, colB, value, t0, total) is called by every lane for each step of
-// 64 products starting at t0; lanes past the end get valid = false.  All
-// cross-lane traffic uses shuffles, so every lane executes the same steps.
-// f returns whether to go on; its answer must be the same on every lane.
+// f(valid, colB, value, t0, total, seg) is called by every lane for each step
+// of 64 products starting at t0; lanes past the end get valid = false.  seg
+// is the index of the product's A entry within the current chunk of 64 A
+// entries: it does not decrease with the lane, and the products of one A
+// entry (one B row) have distinct columns.  All cross-lane traffic uses
+// shuffles, so every lane executes the same steps.  f returns whether to go
+// on; its answer must be the same on every lane.
 template <bool NEED_VAL, typename F>
 __device__ void for_each_product(const int* arp, const int* acol, const double* aval, const int* brp,
                                  const int* bcol, const double* bval, int i, F&& f) {
@@ -93,7 +106,7 @@ __device__ void for_each_product(const int* arp, const int* acol, const double* 
                 colB = bcol[kb];
                 if (NEED_VAL) pv = sa * bval[kb];
             }
-            if (!f(valid, colB, pv, t0, total)) return;
+            if (!f(valid, colB, pv, t0, total, lo)) return;
         }
     }
 }
@@ -173,7 +186,7 @@ __device__ void symbolic_row(int ridx, const int* rows, const int* arp, const in
     int added = 0;
     bool full = false;
     for_each_product<false>(arp, acol, nullptr, brp, bcol, nullptr, i,
-                            [&](bool valid, int c, double, int, int) {
+                            [&](bool valid, int c, double, int, int, int) {
                                 int r = 0;
                                 if (valid) r = hash_insert(keys, mask, c);
                                 added += __popcll(__ballot(r > 0));
@@ -202,19 +215,24 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int
 }
 
 // one row (list position ridx) of the numeric phase, by one wavefront
-template <bool GLOBAL, int HS>
+template <int MODE, int HS>
 __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int* acol, const double* aval,
                             const int* brp, const int* bcol, const double* bval, const int* crp, int* ccol,
                             double* cval, const int* skip, int* gkeys, int* gvals, double* gacc, const int64_t* goff,
                             const int* pcount, int mlo, int mhi, int* lds_keys, int* lds_vals, double* lds_acc,
                             int* lds_tile) {
+    constexpr bool GLOBAL = MODE == N_GLOBAL;
     const int lane = threadIdx.x & 63;
     const int i = rows ? rows[ridx] : ridx;
     int m = 0;
-    if constexpr (!GLOBAL) {
+    if constexpr (MODE == N_LDS) {
         if (skip && skip[i]) return;
         m = pcount[i];
         if (m <= mlo || m > mhi) return;
+    } else {
+        // overflow rows: up to kDBig columns in LDS, the others in global memory
+        const int dr = crp[i + 1] - crp[i];
+        if ((MODE == N_BIG) != (dr <= kDBig)) return;
     }
     int *keys, *vals;
     double* acc;
@@ -225,6 +243,13 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
         vals = gvals + o;
         acc = gacc + o;
         mask = (unsigned)(goff[ridx + 1] - o) - 1;
+    } else if (MODE == N_BIG) {
+        keys = lds_keys;
+        vals = lds_vals;
+        acc = lds_acc;
+        unsigned t = 64;
+        while (t < 2u * (unsigned)(crp[i + 1] - crp[i])) t <<= 1;
+        mask = t - 1;
     } else {
         keys = lds_keys;
         vals = lds_vals;
@@ -237,7 +262,7 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
     }
     phase_fence<GLOBAL>();
     for_each_product<false>(arp, acol, nullptr, brp, bcol, nullptr, i,
-                            [&](bool valid, int c, double, int, int) {
+                            [&](bool valid, int c, double, int, int, int) {
                                 if (valid) (void)hash_insert(keys, mask, c);
                                 return true;
                             });
@@ -261,12 +286,31 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
     }
     phase_fence<GLOBAL>();
     // rank of each column among the row's columns = its output position
-    if constexpr (!GLOBAL) {
+    if constexpr (MODE == N_LDS) {
         for (int e = lane; e < d; e += 64) {
             const int c = lst[e];
             int r = 0;
             for (int q = 0; q < d; ++q) r += (lst[q] < c);
             vals[hash_find_fresh<GLOBAL>(keys, mask, c)] = r;
+        }
+    } else if constexpr (MODE == N_BIG) {
+        // kRankKeys keys per lane at a time, compared against the list in LDS
+        for (int e0 = 0; e0 < d; e0 += 64 * kRankKeys) {
+            int c[kRankKeys], r[kRankKeys];
+#pragma unroll
+            for (int u = 0; u < kRankKeys; ++u) {
+                const int e = e0 + u * 64 + lane;
+                c[u] = e < d ? lst[e] : -1;
+                r[u] = 0;
+            }
+            for (int q = 0; q < d; ++q) {
+                const int v = lst[q];
+#pragma unroll
+                for (int u = 0; u < kRankKeys; ++u) r[u] += (v < c[u]) ? 1 : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kRankKeys; ++u)
+                if (c[u] >= 0) vals[hash_find_fresh<false>(keys, mask, c[u])] = r[u];
         }
     } else {
         // long rows: kRankKeys keys per lane at a time, compared against the
@@ -304,45 +348,41 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
     }
     for (int e = lane; e < d; e += 64) acc[e] = 0.0;
     phase_fence<GLOBAL>();
-    // Accumulate in canonical product order.  Within each step of 64
-    // products, the first lane holding an output column (its leader) adds
-    // that column's products of the step to the running value in lane order;
-    // steps follow each other in product order.  Every entry therefore
-    // receives exactly the sequence of additions of a serial row product.
+    // Accumulate in canonical product order.  The products of one A entry
+    // (a segment) have distinct columns, so a segment's lanes add their
+    // products to their columns' running values at once; the segments of a
+    // step go one after the other in order, and steps follow each other in
+    // product order.  Every entry therefore receives exactly the sequence of
+    // additions of a serial row product.
     for_each_product<true>(arp, acol, aval, brp, bcol, bval, i,
-                           [&](bool valid, int c, double pv, int t0, int total) {
+                           [&](bool valid, int c, double pv, int t0, int total, int seg) {
                                int r = valid ? vals[hash_find_fresh<GLOBAL>(keys, mask, c)] : 0;
                                r = (r >= 0 && r < d) ? r : 0;
                                const int m = min(64, total - t0);
-                               double run = valid ? acc[r] : 0.0;
-                               bool leader = valid;
-                               for (int q = 0; q < m; ++q) {
-                                   const int rq = __shfl(r, q, 64);
-                                   const double vq = __shfl(pv, q, 64);
-                                   if (valid && rq == r) {
-                                       if (q < lane) leader = false;
-                                       run += vq;
-                                   }
+                               const int s0 = __shfl(seg, 0, 64), s1 = __shfl(seg, m - 1, 64);
+                               for (int sg = s0; sg <= s1; ++sg) {
+                                   if (valid && seg == sg) acc[r] += pv;
+                                   phase_fence<GLOBAL>();
                                }
-                               if (leader) acc[r] = run;
-                               phase_fence<GLOBAL>();
                                return true;
                            });
     phase_fence<GLOBAL>();
     for (int e = lane; e < d; e += 64) cval[base + e] = acc[e];
 }
 
-// LDS path (GLOBAL = false): the rows of the list whose product count m lies
-// in (mlo, mhi] and that did not overflow (skip), with HS hash slots per
-// wave (HS >= 2 * mhi unless HS = kHS); GLOBAL: the listed overflow rows.
-// A wavefront per row, grid-stride; nrows_dev (if set) holds the count.
-template <bool GLOBAL, int HS>
+// LDS path (N_LDS): the rows of the list whose product count m lies in
+// (mlo, mhi] and that did not overflow (skip), with HS hash slots per wave
+// (HS >= 2 * mhi unless HS = kHS); N_GLOBAL: the listed overflow rows with
+// more than kDBig columns.  A wavefront per row, grid-stride; nrows_dev (if
+// set) holds the count.
+template <int MODE, int HS>
 __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int* nrows_dev, const int* rows,
                                                            const int* arp, const int* acol, const double* aval,
                                                            const int* brp, const int* bcol, const double* bval,
                                                            const int* crp, int* ccol, double* cval, const int* skip,
                                                            int* gkeys, int* gvals, double* gacc,
                                                            const int64_t* goff, const int* pcount, int mlo, int mhi) {
+    constexpr bool GLOBAL = MODE == N_GLOBAL;
     __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS];
     __shared__ int svals[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS];
     __shared__ double sacc[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS / 2];
@@ -350,9 +390,23 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
     const int w = threadIdx.x >> 6;
     const int nr = nrows_dev ? *nrows_dev : nrows;
     for (int ridx = blockIdx.x * kWaves + w; ridx < nr; ridx += gridDim.x * kWaves)
-        numeric_row<GLOBAL, HS>(ridx, rows, arp, acol, aval, brp, bcol, bval, crp, ccol, cval, skip, gkeys, gvals,
-                                gacc, goff, pcount, mlo, mhi, skeys[GLOBAL ? 0 : w], svals[GLOBAL ? 0 : w],
-                                sacc[GLOBAL ? 0 : w], stile[GLOBAL ? w : 0]);
+        numeric_row<MODE, HS>(ridx, rows, arp, acol, aval, brp, bcol, bval, crp, ccol, cval, skip, gkeys, gvals,
+                              gacc, goff, pcount, mlo, mhi, skeys[GLOBAL ? 0 : w], svals[GLOBAL ? 0 : w],
+                              sacc[GLOBAL ? 0 : w], stile[GLOBAL ? w : 0]);
+}
+
+// the listed overflow rows with at most kDBig columns: one wavefront per
+// workgroup, with a kHSBig-slot hash table and kDBig accumulators in LDS
+__global__ __launch_bounds__(64) void k_spgemm_numeric_big(int nrows, const int* rows, const int* arp,
+                                                           const int* acol, const double* aval, const int* brp,
+                                                           const int* bcol, const double* bval, const int* crp,
+                                                           int* ccol, double* cval) {
+    __shared__ int skeys[kHSBig];
+    __shared__ int svals[kHSBig];
+    __shared__ double sacc[kDBig];
+    for (int ridx = blockIdx.x; ridx < nrows; ridx += gridDim.x)
+        numeric_row<N_BIG, kHSBig>(ridx, rows, arp, acol, aval, brp, bcol, bval, crp, ccol, cval, nullptr, nullptr,
+                                   nullptr, nullptr, nullptr, nullptr, 0, 0, skeys, svals, sacc, nullptr);
 }
 
 // --------------------------------------------------- one thread per row
@@ -644,12 +698,12 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
                            A.val.get(), B.rowptr.get(), B.col.get(), B.val.get(), (const int*)pcount.get(),
                            C.rowptr.get(), C.col.get(), C.val.get());
         // wide rows with few products: small tables, so more wavefronts fit a CU
-        hipLaunchKernelGGL((k_spgemm_numeric<false, kHSSmall>), dim3(wgrid), dim3(kBlock), 0, s, 0, nwide_dev,
+        hipLaunchKernelGGL((k_spgemm_numeric<N_LDS, kHSSmall>), dim3(wgrid), dim3(kBlock), 0, s, 0, nwide_dev,
                            (const int*)wl.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(),
                            B.val.get(), C.rowptr.get(), C.col.get(), C.val.get(), (const int*)flags.get(),
                            (int*)nullptr, (int*)nullptr, (double*)nullptr, (const int64_t*)nullptr,
                            (const int*)pcount.get(), -1, kHSSmall / 2);
-        hipLaunchKernelGGL((k_spgemm_numeric<false, kHS>), dim3(wgrid), dim3(kBlock), 0, s, 0, nwide_dev,
+        hipLaunchKernelGGL((k_spgemm_numeric<N_LDS, kHS>), dim3(wgrid), dim3(kBlock), 0, s, 0, nwide_dev,
                            (const int*)wl.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(),
                            B.val.get(), C.rowptr.get(), C.col.get(), C.val.get(), (const int*)flags.get(),
                            (int*)nullptr, (int*)nullptr, (double*)nullptr, (const int64_t*)nullptr,
@@ -657,7 +711,10 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
         MATAMG_LAUNCH_CHECK();
     }
     if (novf > 0) {
-        hipLaunchKernelGGL((k_spgemm_numeric<true, 1>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
+        hipLaunchKernelGGL(k_spgemm_numeric_big, dim3(std::min(novf, 4096)), dim3(64), 0, s, novf,
+                           (const int*)list.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(),
+                           B.col.get(), B.val.get(), (const int*)C.rowptr.get(), C.col.get(), C.val.get());
+        hipLaunchKernelGGL((k_spgemm_numeric<N_GLOBAL, 1>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
                            (const int*)nullptr, list.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(),
                            B.col.get(), B.val.get(), C.rowptr.get(), C.col.get(), C.val.get(), (const int*)nullptr,
                            gkeys.get(), gvals.get(), gacc.get(), toff.get(), (const int*)nullptr, 0, 0);
