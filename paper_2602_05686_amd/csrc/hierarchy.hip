@@ -173,9 +173,9 @@ double Hierarchy::time_smoother(int level, int reps, hipStream_t s, double* byte
         using V = Vec<T>;
         T* x = V::xa(L);
         T* y = V::xb(L);
-        MATAMG_HIP(hipMemsetAsync(V::b(L), 0, sizeof(T) * n, s));
-        MATAMG_HIP(hipMemsetAsync(x, 0, sizeof(T) * n, s));
-        MATAMG_HIP(hipMemsetAsync(V::d(L), 0, sizeof(T) * n, s));
+        zero_async(V::b(L), sizeof(T) * n, s);
+        zero_async(x, sizeof(T) * n, s);
+        zero_async(V::d(L), sizeof(T) * n, s);
         spmv_smooth<T>(L.A, V::A(L.A), x, V::b(L), V::dinv(L), V::d(L), (T)c1, (T)c2, y, nullptr, nullptr,
                        DotTarget{}, s);
         MATAMG_HIP(hipEventRecord(e0, s));
@@ -286,7 +286,7 @@ void coarse_inverse(Hierarchy& h, int* flag, hipStream_t s) {
     const int nc = C.A.n;
     h.nL = nc;
     if (h.Ainv.size() != (size_t)nc * nc) h.Ainv.alloc((size_t)nc * nc, &h.mem);
-    MATAMG_HIP(hipMemsetAsync(h.Ainv.get(), 0, sizeof(double) * (size_t)nc * nc, s));
+    zero_async(h.Ainv.get(), sizeof(double) * (size_t)nc * nc, s);
     densify(nc, C.A.rowptr.get(), C.A.col.get(), C.A.val.get(), h.Ainv.get(), s);
     DBuf<double> work((size_t)nc * nc, &h.mem);
     if (!dense_spd_inverse(nc, h.Ainv.get(), work.get(), flag, s))
@@ -345,8 +345,8 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
 
     h.scal.alloc(S_NSCAL, mc);
     h.counter.alloc(1, mc);
-    MATAMG_HIP(hipMemsetAsync(h.counter.get(), 0, sizeof(unsigned), s));
-    MATAMG_HIP(hipMemsetAsync(h.scal.get(), 0, sizeof(double) * S_NSCAL, s));
+    zero_async(h.counter.get(), sizeof(unsigned), s);
+    zero_async(h.scal.get(), sizeof(double) * S_NSCAL, s);
     {
         // MATAMG_NO_GRAPH=1 runs every CG step eagerly (used to check the
         // captured graphs against direct launches)
@@ -354,7 +354,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
         h.use_graphs = !(ng && ng[0] == '1');
     }
     DBuf<int> flag(1, mc);
-    MATAMG_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int), s));
+    zero_async(flag.get(), sizeof(int), s);
 
     // ---- level 1 inputs on the device
     Level& L0 = h.lev[0];
@@ -415,7 +415,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
         // strength of connection and dropping
         L.dir.alloc(nl, mc);
         if (l == 0) detect_dirichlet(nl, L.A.rowptr.get(), L.A.col.get(), L.A.val.get(), L.dir.get(), s);
-        else MATAMG_HIP(hipMemsetAsync(L.dir.get(), 0, nl, s));
+        else zero_async(L.dir.get(), nl, s);
         DBuf<double> minv;
         if (opt.soc == AMG_SOC_MATERIAL) {
             minv.alloc((size_t)nl * ncomp, mc);
@@ -448,6 +448,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
             mis_init(nl, L.dir.get(), state.get(), s);
             int rounds = 0;
             for (bool done = false; !done;) {
+                zero_async(und.get(), sizeof(int) * kMisBatch, s);
                 for (int j = 0; j < kMisBatch; ++j)
                     mis_round(L.A, L.mask.get(), key, state.get(), t1.get(), t2.get(), und.get() + j, s);
                 int left[kMisBatch];
@@ -537,7 +538,7 @@ void update_values(Hierarchy& h, const double* val, bool host_ptrs, hipStream_t 
         if (!h.lev[l].mask || !h.lev[l].agg || !h.lev[l].dir)
             fail(AMG_ERR_INVALID_ARG, "the hierarchy no longer holds the masks and aggregates an update reuses");
     DBuf<int> flag(1, mc);
-    MATAMG_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int), s));
+    zero_async(flag.get(), sizeof(int), s);
     {
         // checked before anything of the hierarchy changes
         const size_t nnz = (size_t)L0.A.nnz;
@@ -764,7 +765,7 @@ amg_status pcg_solve(Hierarchy& h, const double* b_in, double* x_io, double tol,
     read_scal();
     const double bn = std::sqrt(h.hscal[S_BB]);
     if (bn == 0.0) {
-        MATAMG_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, ws));
+        zero_async(x, sizeof(double) * n, ws);
         st = AMG_OK;
     } else if (std::sqrt(h.hscal[S_RR]) / bn <= tol) {
         rel_true = std::sqrt(h.hscal[S_RR]) / bn;

@@ -238,7 +238,7 @@ __global__ void k_zero_upper(double* A, int n) {
 bool dense_spd_inverse(int n, double* A, double* work, int* flag, hipStream_t s) {
     if (n <= 0) return true;
     const int nt = ceil_div(n, NB);
-    MATAMG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    zero_async(flag, sizeof(int), s);
     // Cholesky, lower triangle in place
     for (int kb = 0; kb < nt; ++kb) {
         hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(kPotrfThreads), 0, s, A, n, kb, flag);
@@ -257,7 +257,7 @@ bool dense_spd_inverse(int n, double* A, double* work, int* flag, hipStream_t s)
     // Y = L^{-1}, right-looking: block row I is solved with L_II once every
     // earlier block row has been subtracted from it, then subtracted from all
     // later block rows at once (a critical path of nt steps, not nt^2 / 2)
-    MATAMG_HIP(hipMemsetAsync(work, 0, sizeof(double) * (size_t)n * n, s));
+    zero_async(work, sizeof(double) * (size_t)n * n, s);
     hipLaunchKernelGGL(k_identity, dim3(ceil_div(n, kBlock)), dim3(kBlock), 0, s, work, n);
     for (int I = 0; I < nt; ++I) {
         const int ncols = min(n, (I + 1) * NB);

@@ -110,14 +110,23 @@ __global__ void k_block_next(int n, const int* rp, const int* par, const int* lo
     }
 }
 
-__global__ void k_mark_start(int* mark) { mark[0] = 1; }
-
-__global__ void k_mark_jump(int n, const int* jump, int* mark) {
-    FOR_ROWS(p, (int64_t)n + 1) if (mark[p]) mark[jump[p]] = 1;
+// mark[p] = (p == 0): row 0 starts the first block
+__global__ void k_mark_init(int n, int* mark) {
+    FOR_ROWS(p, (int64_t)n + 1) mark[p] = (p == 0) ? 1 : 0;
 }
 
-__global__ void k_jump_square(int n, const int* jump, int* out) {
-    FOR_ROWS(p, (int64_t)n + 1) out[p] = jump[jump[p]];
+// One doubling round: every marked start marks the start `jump` blocks
+// ahead of it, and (if out is set) out = jump o jump.  A mark set by another
+// thread of the same round may be seen early; that only marks a true start
+// sooner (marks are only ever set on the orbit of row 0), so after the round
+// at least the starts within twice the span are marked, as with the rounds
+// apart.
+__global__ void k_mark_square(int n, const int* jump, int* mark, int* out) {
+    FOR_ROWS(p, (int64_t)n + 1) {
+        const int j = jump[p];
+        if (mark[p]) mark[j] = 1;
+        if (out) out[p] = jump[j];
+    }
 }
 
 // out[0] = number of blocks, out[1] = threads per row
@@ -190,8 +199,8 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack) {
         A.nblk = 0;
         A.blk.alloc(1, mc);
         A.blkk.alloc(1, mc);
-        MATAMG_HIP(hipMemsetAsync(A.blk.get(), 0, sizeof(int), s));
-        MATAMG_HIP(hipMemsetAsync(A.blkk.get(), 0, sizeof(int), s));
+        zero_async(A.blk.get(), sizeof(int), s);
+        zero_async(A.blkk.get(), sizeof(int), s);
         MATAMG_HIP(hipStreamSynchronize(s));
         return;
     }
@@ -199,7 +208,7 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack) {
     // threads per row from the longest row, decided on the device: the
     // only read-back is the block count at the end
     DBuf<int> par(8, mc);
-    MATAMG_HIP(hipMemsetAsync(par.get(), 0, 8 * sizeof(int), s));
+    zero_async(par.get(), 8 * sizeof(int), s);
     hipLaunchKernelGGL(k_max_row_len, dim3(std::min(grid1(n), 256)), dim3(kBlock), 0, s, n, rp, par.get());
     hipLaunchKernelGGL(k_group_params, dim3(1), dim3(1), 0, s, n, rp, par.get());
     MATAMG_LAUNCH_CHECK();
@@ -214,16 +223,14 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack) {
                        pos.get() + n, ja.get());
     MATAMG_LAUNCH_CHECK();
     // pointer doubling from row 0 (flags reused as the start marks)
-    MATAMG_HIP(hipMemsetAsync(flags.get(), 0, sizeof(int) * n1, s));
-    hipLaunchKernelGGL(k_mark_start, dim3(1), dim3(1), 0, s, flags.get());
+    hipLaunchKernelGGL(k_mark_init, dim3(grid1(n1)), dim3(kBlock), 0, s, n, flags.get());
     int* cur = ja.get();
     int* nxt = jb.get();
     for (int64_t span = 1; span <= (int64_t)n; span <<= 1) {
-        hipLaunchKernelGGL(k_mark_jump, dim3(grid1(n1)), dim3(kBlock), 0, s, n, (const int*)cur, flags.get());
-        if ((span << 1) <= (int64_t)n) {
-            hipLaunchKernelGGL(k_jump_square, dim3(grid1(n1)), dim3(kBlock), 0, s, n, (const int*)cur, nxt);
-            std::swap(cur, nxt);
-        }
+        const bool more = (span << 1) <= (int64_t)n;
+        hipLaunchKernelGGL(k_mark_square, dim3(grid1(n1)), dim3(kBlock), 0, s, n, (const int*)cur, flags.get(),
+                           more ? nxt : (int*)nullptr);
+        if (more) std::swap(cur, nxt);
     }
     MATAMG_LAUNCH_CHECK();
     exclusive_scan(flags.get(), pos.get(), n, tmp.get(), s);

@@ -806,14 +806,14 @@ static void finish_incidence(Incidence& out, DBuf<int>& cnt, int nt, MemCounter*
     out.rowptr.alloc((size_t)nt + 1, mc);
     DBuf<int> tmp(scan_tmp_size(nt), mc);
     exclusive_scan(cnt.get(), out.rowptr.get(), nt, tmp.get(), s);
-    MATAMG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (size_t)(nt > 0 ? nt : 1), s));
+    zero_async(cnt.get(), sizeof(int) * (size_t)(nt > 0 ? nt : 1), s);
 }
 
 void build_node_elements(const int* en, int64_t nelem, int npe, int n, Incidence& out, int* flag, MemCounter* mc,
                          hipStream_t s) {
     const int64_t total = nelem * npe;
     DBuf<int> cnt((size_t)n, mc);
-    MATAMG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (size_t)n, s));
+    zero_async(cnt.get(), sizeof(int) * (size_t)n, s);
     LAUNCH(k_count_elem_nodes, total, en, total, n, cnt.get(), flag);
     finish_incidence(out, cnt, n, mc, s);
     out.items.alloc((size_t)(total > 0 ? total : 1), mc);
@@ -824,7 +824,7 @@ void build_node_elements(const int* en, int64_t nelem, int npe, int n, Incidence
 
 void build_aggregate_members(const int* agg, int n, int nagg, Incidence& out, MemCounter* mc, hipStream_t s) {
     DBuf<int> cnt((size_t)(nagg > 0 ? nagg : 1), mc);
-    MATAMG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (size_t)(nagg > 0 ? nagg : 1), s));
+    zero_async(cnt.get(), sizeof(int) * (size_t)(nagg > 0 ? nagg : 1), s);
     LAUNCH(k_count_agg, n, agg, n, cnt.get());
     finish_incidence(out, cnt, nagg, mc, s);
     out.items.alloc((size_t)(n > 0 ? n : 1), mc);
@@ -875,7 +875,6 @@ void mis_init(int n, const uint8_t* dir, uint8_t* state, hipStream_t s) { LAUNCH
 void mis_round(const DCsr& A, const uint8_t* mask, uint64_t key, uint8_t* state, uint64_t* t1, uint64_t* t2,
                int* undecided, hipStream_t s) {
     const int n = A.n;
-    MATAMG_HIP(hipMemsetAsync(undecided, 0, sizeof(int), s));
     if (A.nblk > 0) {
         hipLaunchKernelGGL((k_mis_hop<true>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, A.rowptr.get(),
                            A.col.get(), mask, A.blk.get(), A.nblk, key, (const uint8_t*)state, (const uint64_t*)nullptr,
@@ -896,7 +895,7 @@ void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, c
                 const uint8_t* state, const int* root_rank, int* phase2, int* agg, int* list, int* nlist,
                 hipStream_t s) {
     LAUNCH(k_agg_phase2, n, n, rowptr, col, mask, dir, state, root_rank, phase2);
-    MATAMG_HIP(hipMemsetAsync(nlist, 0, sizeof(int), s));
+    zero_async(nlist, sizeof(int), s);
     LAUNCH(k_agg_phase3_split, n, n, dir, phase2, agg, list, nlist);
     if (n > 0) {
         hipLaunchKernelGGL(k_agg_phase3_rows, dim3(1024), dim3(kBlock), 0, s, rowptr, col, mask, phase2,

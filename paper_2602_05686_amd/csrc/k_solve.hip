@@ -92,11 +92,72 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const int* in, int* out, 
 }
 }  // namespace
 
+// inputs up to this length are scanned by one block of kScanOneThreads threads
+constexpr int kScanOneThreads = 1024;
+constexpr int64_t kScanOneMax = 1 << 16;
+
+namespace {
+// the whole scan in one block: tiles of kScanOneThreads * kScanItems
+// consecutive values, each thread kScanItems of them, with a running carry
+__global__ __launch_bounds__(kScanOneThreads) void k_scan_one(const int* in, int* out, int64_t n) {
+    __shared__ int sh[kScanOneThreads / 64];
+    int carry = 0;
+    for (int64_t t0 = 0; t0 < n; t0 += (int64_t)kScanOneThreads * kScanItems) {
+        const int64_t base = t0 + (int64_t)threadIdx.x * kScanItems;
+        int v[kScanItems];
+        int sum = 0;
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t i = base + k;
+            v[k] = (i < n) ? in[i] : 0;
+            sum += v[k];
+        }
+        int tot;
+        int ex = block_exclusive_scan(sum, sh, &tot) + carry;
+        for (int k = 0; k < kScanItems; ++k) {
+            const int64_t i = base + k;
+            if (i < n) out[i] = ex;
+            ex += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ void k_zero_words(uint32_t* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void k_zero_bytes(uint8_t* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+}  // namespace
+
+void zero_async(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0 || p == nullptr) return;
+    if (((uintptr_t)p & 3u) == 0 && (bytes & 3u) == 0) {
+        const int64_t n = (int64_t)(bytes / 4);
+        hipLaunchKernelGGL(k_zero_words, dim3(std::min<int64_t>(ceil_div(n, kBlock), 2048)), dim3(kBlock), 0, s,
+                           (uint32_t*)p, n);
+    } else {
+        const int64_t n = (int64_t)bytes;
+        hipLaunchKernelGGL(k_zero_bytes, dim3(std::min<int64_t>(ceil_div(n, kBlock), 2048)), dim3(kBlock), 0, s,
+                           (uint8_t*)p, n);
+    }
+    MATAMG_LAUNCH_CHECK();
+}
+
 size_t scan_tmp_size(int64_t n) { return (size_t)ceil_div(n > 0 ? n : 1, kScanTile) + 1; }
 
 void exclusive_scan(const int* in, int* out, int64_t n, int* tmp, hipStream_t s) {
     if (n <= 0) {
-        MATAMG_HIP(hipMemsetAsync(out, 0, sizeof(int), s));
+        zero_async(out, sizeof(int), s);
+        return;
+    }
+    if (n <= kScanOneMax) {
+        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(kScanOneThreads), 0, s, in, out, n);
+        MATAMG_LAUNCH_CHECK();
         return;
     }
     int nb = ceil_div(n, kScanTile);

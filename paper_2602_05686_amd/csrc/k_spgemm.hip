@@ -31,8 +31,10 @@ constexpr int kDMax = 512;    // max distinct columns on the LDS path
 constexpr int kHSSmall = 256; // LDS hash slots per wave for rows of at most 128 products
 constexpr int kRankTile = 1024;  // LDS tile of the column list when ranking long rows
 constexpr int kRankKeys = 8;     // keys per lane per ranking pass
-constexpr int kDBig = 2048;      // overflow rows with at most this many columns: numeric phase in LDS
-constexpr int kHSBig = 4096;     // their LDS hash slots (one wavefront per workgroup)
+constexpr int kDBig = 4096;      // overflow rows with at most this many columns: numeric phase in LDS
+constexpr int kHSBig = 8192;     // their LDS hash slots (one wavefront per workgroup)
+// dynamic LDS of the large-table workgroup: keys and ranks per slot, one accumulator per column
+constexpr size_t kBigLds = sizeof(int) * 2 * kHSBig + sizeof(double) * kDBig;
 // numeric phase variants: LDS table per wavefront (rows of at most kDMax
 // columns), global-memory table, or one large LDS table per one-wavefront
 // workgroup (overflow rows of at most kDBig columns)
@@ -396,14 +398,16 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
 }
 
 // the listed overflow rows with at most kDBig columns: one wavefront per
-// workgroup, with a kHSBig-slot hash table and kDBig accumulators in LDS
+// workgroup, with a kHSBig-slot hash table and kDBig accumulators in (96 KB
+// of dynamic) LDS
 __global__ __launch_bounds__(64) void k_spgemm_numeric_big(int nrows, const int* rows, const int* arp,
                                                            const int* acol, const double* aval, const int* brp,
                                                            const int* bcol, const double* bval, const int* crp,
                                                            int* ccol, double* cval) {
-    __shared__ int skeys[kHSBig];
-    __shared__ int svals[kHSBig];
-    __shared__ double sacc[kDBig];
+    extern __shared__ __align__(16) unsigned char big_lds[];
+    double* sacc = reinterpret_cast<double*>(big_lds);
+    int* skeys = reinterpret_cast<int*>(sacc + kDBig);
+    int* svals = skeys + kHSBig;
     for (int ridx = blockIdx.x; ridx < nrows; ridx += gridDim.x)
         numeric_row<N_BIG, kHSBig>(ridx, rows, arp, acol, aval, brp, bcol, bval, crp, ccol, cval, nullptr, nullptr,
                                    nullptr, nullptr, nullptr, nullptr, 0, 0, skeys, svals, sacc, nullptr);
@@ -711,7 +715,14 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
         MATAMG_LAUNCH_CHECK();
     }
     if (novf > 0) {
-        hipLaunchKernelGGL(k_spgemm_numeric_big, dim3(std::min(novf, 4096)), dim3(64), 0, s, novf,
+        // the dynamic LDS limit, raised once per process (thread-safe static)
+        static const bool big_lds_set = [] {
+            MATAMG_HIP(hipFuncSetAttribute((const void*)k_spgemm_numeric_big,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBigLds));
+            return true;
+        }();
+        (void)big_lds_set;
+        hipLaunchKernelGGL(k_spgemm_numeric_big, dim3(std::min(novf, 4096)), dim3(64), kBigLds, s, novf,
                            (const int*)list.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(),
                            B.col.get(), B.val.get(), (const int*)C.rowptr.get(), C.col.get(), C.val.get());
         hipLaunchKernelGGL((k_spgemm_numeric<N_GLOBAL, 1>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
@@ -729,13 +740,13 @@ void transpose(const DCsr& A, DCsr& T, MemCounter* mc, hipStream_t s) {
     T.m = n;
     T.nnz = A.nnz;
     DBuf<int> cnt((size_t)(m > 0 ? m : 1), mc);
-    MATAMG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (size_t)(m > 0 ? m : 1), s));
+    zero_async(cnt.get(), sizeof(int) * (size_t)(m > 0 ? m : 1), s);
     if (A.nnz > 0)
         hipLaunchKernelGGL(k_col_counts, dim3(g1(A.nnz)), dim3(kBlock), 0, s, A.nnz, A.col.get(), cnt.get());
     T.rowptr.alloc((size_t)m + 1, mc);
     DBuf<int> tmp(scan_tmp_size(m), mc);
     exclusive_scan(cnt.get(), T.rowptr.get(), m, tmp.get(), s);
-    MATAMG_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * (size_t)(m > 0 ? m : 1), s));
+    zero_async(cnt.get(), sizeof(int) * (size_t)(m > 0 ? m : 1), s);
     T.col.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), mc);
     T.val.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), mc);
     if (n > 0)

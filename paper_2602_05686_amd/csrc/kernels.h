@@ -10,6 +10,8 @@ namespace matamg {
 // `tmp` must hold scan_tmp_size(n) ints.  Returns nothing; total stays on device.
 size_t scan_tmp_size(int64_t n);
 void exclusive_scan(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);
+// bytes zero bytes at p, by a kernel on s (cheaper to issue than a runtime memset)
+void zero_async(void* p, size_t bytes, hipStream_t s);
 
 // deterministic dot product sum_i a_i b_i in FP64 (fixed reduction tree for a given n)
 // written to *result (device).  partial: >= kMaxPartials doubles, counter: zeroed uint.
