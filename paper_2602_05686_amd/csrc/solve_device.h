@@ -213,6 +213,23 @@ __device__ __forceinline__ void stage_products(const SArgs<T>& a, int bid, int k
     }
 }
 
+// s + prod[k0] + prod[k0 + step] + ... (k < k1), added one at a time in
+// that order; the LDS reads go out eight at a time so that their latencies
+// overlap (the additions, and so the result, are those of the plain loop)
+template <typename T, int STEP>
+__device__ __forceinline__ T ordered_sum(const T* prod, int k0, int k1, T s) {
+    int k = k0;
+    for (; k + 7 * STEP < k1; k += 8 * STEP) {
+        T p[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p[u] = prod[k + u * STEP];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += p[u];
+    }
+    for (; k < k1; k += STEP) s += prod[k];
+    return s;
+}
+
 // Row block `bid` of the matrix in `a`: stream its val/col range into LDS
 // products, reduce each row with G threads (or the whole block for a long
 // row), apply the epilogue, and store the block's dot partial (its
@@ -275,8 +292,7 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
             // the group's eight lanes
             const bool wide = owner && (e1 - e0) > kWideRow;
             T s = 0;
-            if (owner && !wide)
-                for (int k = e0 - k0; k < e1 - k0; ++k) s += S.prod[k];
+            if (owner && !wide) s = ordered_sum<T, 1>(S.prod, e0 - k0, e1 - k0, s);
             const int lane = (int)threadIdx.x & 63, grp = lane >> 3, gl = lane & 7;
             unsigned long long wm = __ballot(wide);
             // rank of this lane's row among the wide rows of the wavefront
@@ -287,8 +303,7 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
                 const int l = m ? __builtin_ctzll(m) : 0;
                 const int f0 = __shfl(e0, l, 64) - k0, f1 = __shfl(e1, l, 64) - k0;
                 T ps = 0;
-                if (m)
-                    for (int k = f0 + gl; k < f1; k += 8) ps += S.prod[k];
+                if (m) ps = ordered_sum<T, 8>(S.prod, f0 + gl, f1, ps);
                 for (int off = 4; off > 0; off >>= 1) ps += __shfl_xor(ps, off, 64);
                 const int src = (rank >= base && rank < base + 8) ? (rank - base) * 8 : 0;
                 const T got = __shfl(ps, src, 64);
@@ -306,8 +321,7 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
                 const int rqc = own ? rq : r1 - 1;
                 const int f0 = a.rowptr[rqc] - k0, f1 = a.rowptr[rqc + 1] - k0;
                 T s = 0;
-                if (own)
-                    for (int k = f0 + gl; k < f1; k += G) s += S.prod[k];
+                if (own) s = ordered_sum<T, G>(S.prod, f0 + gl, f1, s);
                 for (int off = G / 2; off > 0; off >>= 1) s += __shfl_down(s, off, G);
                 if (gl == 0 && own) dp += epilogue<T, MODE, HAS_DOT>(a, rq, s, row_operands<T, MODE>(a, rq));
             }
