@@ -447,9 +447,29 @@ __global__ __launch_bounds__(kBlock) void k_mis_hop(const int* rowptr, const int
     const RowBlock rb = row_block(rowptr, blk, bid);
     auto tuple_at = [&](int j) -> uint64_t { return FIRST ? tuple_of(state[j], key, j) : tin[j]; };
     if (!rb.longrow) {
-        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) {
-            const int k = rb.k0 + t;
-            tv[t] = mask[k] ? tuple_at(col[k]) : 0ull;   // the diagonal's own tuple is harmless
+        // all column and mask loads first (indices past the block's end
+        // clamped to its last entry), then all neighbour gathers, then the
+        // stores: three memory latencies per block instead of three per
+        // stride; the diagonal's own tuple is harmless
+        constexpr int U = kStreamCap / kBlock;
+        if (rb.cnt > 0) {
+            int c[U];
+            uint8_t m[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = (int)threadIdx.x + u * kBlock;
+                const int k = rb.k0 + (t < rb.cnt ? t : rb.cnt - 1);
+                c[u] = col[k];
+                m[u] = mask[k];
+            }
+            uint64_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = tuple_at(c[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = (int)threadIdx.x + u * kBlock;
+                if (t < rb.cnt) tv[t] = m[u] ? v[u] : 0ull;
+            }
         }
         __syncthreads();
         const int r = rb.r0 + (int)threadIdx.x;
