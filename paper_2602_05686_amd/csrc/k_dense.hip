@@ -56,44 +56,53 @@ __device__ void tile_mac(double acc[4][4], const double* A, int lda, bool ta, in
     }
 }
 
-// factor the diagonal tile kb in LDS; flag <- 1 if not positive definite.
-// One wavefront, left-looking, thread i owning row i: at step j thread j
-// forms the diagonal from its own row, then every row i > j forms L_ij from
-// the dot product of rows i and j over the finished columns k < j.  Each step
-// is a single chain of j multiply-adds per thread, with no index arithmetic.
+// factor the diagonal tile kb; flag <- 1 if not positive definite.  One
+// wavefront, right-looking, thread i holding row i in registers (every index
+// below is a compile-time constant once the loops are unrolled): at step j
+// thread j takes the square root of its fully updated diagonal, every row
+// i > j divides its entry in column j by it and publishes the entry in LDS,
+// then subtracts L_ij L_kj from its entries in columns j < k <= i.  Each
+// entry receives its subtractions in ascending j, the order of the
+// left-looking dot products, and a step's updates are independent of each
+// other.
 constexpr int kPotrfThreads = NB;
 __global__ __launch_bounds__(kPotrfThreads) void k_potrf_diag(double* A, int n, int kb, int* flag) {
-    __shared__ double T[NB][NB + 1];
+    __shared__ double C[NB][NB + 1];  // C[k][j] = L_kj once column j is done
     const int o = kb * NB;
     const int nb = min(NB, n - o);
-    for (int e = threadIdx.x; e < nb * nb; e += kPotrfThreads) {
-        int i = e / nb, j = e % nb;
-        T[i][j] = A[(size_t)(o + i) * n + o + j];
-    }
-    __syncthreads();
     const int i = threadIdx.x;
-    for (int j = 0; j < nb; ++j) {
-        if (i == j) {
-            double d = T[j][j];
-            for (int k = 0; k < j; ++k) d -= T[j][k] * T[j][k];
-            if (!(d > 0.0) || !isfinite(d)) {
-                *flag = 1;
-                d = 1.0;
+    const bool live = i < nb;
+    double row[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) row[k] = (live && k < nb) ? A[(size_t)(o + i) * n + o + k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (j < nb) {
+            if (i == j) {
+                double d = row[j];
+                if (!(d > 0.0) || !isfinite(d)) {
+                    *flag = 1;
+                    d = 1.0;
+                }
+                row[j] = sqrt(d);
+                C[j][j] = row[j];
             }
-            T[j][j] = sqrt(d);
+            __syncthreads();
+            if (live && i > j) {
+                row[j] = row[j] / C[j][j];
+                C[i][j] = row[j];
+            }
+            __syncthreads();
+            const double lij = row[j];
+#pragma unroll
+            for (int k = j + 1; k < NB; ++k)
+                if (live && i >= k) row[k] -= lij * C[k][j];
         }
-        __syncthreads();
-        if (i > j && i < nb) {
-            double v = T[i][j];
-            for (int k = 0; k < j; ++k) v -= T[i][k] * T[j][k];
-            T[i][j] = v / T[j][j];
-        }
-        __syncthreads();
     }
-    for (int e = threadIdx.x; e < nb * nb; e += kPotrfThreads) {
-        int r = e / nb, c = e % nb;
-        A[(size_t)(o + r) * n + o + c] = (c <= r) ? T[r][c] : 0.0;
-    }
+    if (live)
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            if (k < nb) A[(size_t)(o + i) * n + o + k] = (k <= i) ? row[k] : 0.0;
 }
 
 // rows below the diagonal tile: X L_kk^T = B, one thread per row

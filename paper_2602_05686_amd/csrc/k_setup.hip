@@ -535,14 +535,27 @@ __global__ void k_agg_phase2(int n, const int* rowptr, const int* col, const uin
         if (state[i] == MIS_IN) {
             a = rank[i];
         } else if (!(dir && dir[i])) {
-            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-                const int j = col[k];
-                if (j == i || !mask[k]) continue;
-                if (state[j] == MIS_IN) {
-                    a = rank[j];
-                    break;
+            // the first kept neighbour (ascending stored order) that is a
+            // root; the row is read eight entries at a time, each chunk's
+            // columns and masks, then their states, loaded together
+            const int lo = rowptr[i], hi = rowptr[i + 1];
+            int root = -1;
+            for (int k0 = lo; k0 < hi && root < 0; k0 += 8) {
+                int c[8];
+                uint8_t m[8], st[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = min(k0 + u, hi - 1);
+                    c[u] = col[k];
+                    m[u] = mask[k];
                 }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) st[u] = state[c[u]];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (root < 0 && k0 + u < hi && c[u] != i && m[u] && st[u] == MIS_IN) root = c[u];
             }
+            if (root >= 0) a = rank[root];
         }
         phase2[i] = a;
     }

@@ -14,7 +14,7 @@
 // entry have distinct columns and are added at once), so every entry is the
 // same sequence of IEEE additions as a serial row-by-row product.  Overflow
 // rows of at most kDBig columns run their numeric phase in a large LDS table
-// of a one-wavefront workgroup, the others in global memory.
+// shared by a workgroup's wavefronts, the others in global memory.
 
 #pragma clang fp contract(off)
 
@@ -32,13 +32,13 @@ constexpr int kHSSmall = 256; // LDS hash slots per wave for rows of at most 128
 constexpr int kRankTile = 1024;  // LDS tile of the column list when ranking long rows
 constexpr int kRankKeys = 8;     // keys per lane per ranking pass
 constexpr int kDBig = 4096;      // overflow rows with at most this many columns: numeric phase in LDS
-constexpr int kHSBig = 8192;     // their LDS hash slots (one wavefront per workgroup)
+constexpr int kHSBig = 8192;     // their LDS hash slots (one workgroup per row)
 // dynamic LDS of the large-table workgroup: keys and ranks per slot, one accumulator per column
 constexpr size_t kBigLds = sizeof(int) * 2 * kHSBig + sizeof(double) * kDBig;
-// numeric phase variants: LDS table per wavefront (rows of at most kDMax
-// columns), global-memory table, or one large LDS table per one-wavefront
-// workgroup (overflow rows of at most kDBig columns)
-enum NumericMode { N_LDS = 0, N_GLOBAL = 1, N_BIG = 2 };
+// numeric phase of the wavefront path: LDS table per wavefront (rows of at
+// most kDMax columns) or global-memory table (overflow rows of more than
+// kDBig columns); the overflow rows in between take numeric_row_big
+enum NumericMode { N_LDS = 0, N_GLOBAL = 1 };
 
 __device__ __forceinline__ unsigned hash_slot(int key, unsigned mask) {
     return ((unsigned)key * 2654435761u) & mask;
@@ -56,7 +56,8 @@ __device__ __forceinline__ int hash_insert(int* keys, unsigned mask, int key) {
     return -1;
 }
 
-// Enumerate the products of row i of A*B in canonical order, 64 per step.
+// Enumerate the products of row i of A*B in canonical order, 64 per step
+// (with stride > 1, only the steps s with s % stride == offset).
 // f(valid, colB, value, t0, total, seg) is called by every lane for each step
 // of 64 products starting at t0; lanes past the end get valid = false.  seg
 // is the index of the product's A entry within the current chunk of 64 A
@@ -66,9 +67,10 @@ __device__ __forceinline__ int hash_insert(int* keys, unsigned mask, int key) {
 // on; its answer must be the same on every lane.
 template <bool NEED_VAL, typename F>
 __device__ void for_each_product(const int* arp, const int* acol, const double* aval, const int* brp,
-                                 const int* bcol, const double* bval, int i, F&& f) {
+                                 const int* bcol, const double* bval, int i, F&& f, int stride = 1, int offset = 0) {
     const int lane = threadIdx.x & 63;
     const int a0 = arp[i], a1 = arp[i + 1];
+    int step = 0;  // steps of the row so far: only those with step % stride == offset are taken
     for (int c0 = a0; c0 < a1; c0 += 64) {
         const int ka = c0 + lane;
         int blen = 0, bstart = 0;
@@ -86,7 +88,8 @@ __device__ void for_each_product(const int* arp, const int* acol, const double* 
         }
         const int excl = incl - blen;
         const int total = __shfl(incl, 63, 64);
-        for (int t0 = 0; t0 < total; t0 += 64) {
+        for (int t0 = 0; t0 < total; t0 += 64, ++step) {
+            if (stride > 1 && step % stride != offset) continue;
             const int t = t0 + lane;
             const bool valid = t < total;
             // source = last lane whose exclusive offset is <= t (empty B rows
@@ -232,9 +235,8 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
         m = pcount[i];
         if (m <= mlo || m > mhi) return;
     } else {
-        // overflow rows: up to kDBig columns in LDS, the others in global memory
-        const int dr = crp[i + 1] - crp[i];
-        if ((MODE == N_BIG) != (dr <= kDBig)) return;
+        // overflow rows of up to kDBig columns take the large LDS table
+        if (crp[i + 1] - crp[i] <= kDBig) return;
     }
     int *keys, *vals;
     double* acc;
@@ -245,13 +247,6 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
         vals = gvals + o;
         acc = gacc + o;
         mask = (unsigned)(goff[ridx + 1] - o) - 1;
-    } else if (MODE == N_BIG) {
-        keys = lds_keys;
-        vals = lds_vals;
-        acc = lds_acc;
-        unsigned t = 64;
-        while (t < 2u * (unsigned)(crp[i + 1] - crp[i])) t <<= 1;
-        mask = t - 1;
     } else {
         keys = lds_keys;
         vals = lds_vals;
@@ -294,25 +289,6 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
             int r = 0;
             for (int q = 0; q < d; ++q) r += (lst[q] < c);
             vals[hash_find_fresh<GLOBAL>(keys, mask, c)] = r;
-        }
-    } else if constexpr (MODE == N_BIG) {
-        // kRankKeys keys per lane at a time, compared against the list in LDS
-        for (int e0 = 0; e0 < d; e0 += 64 * kRankKeys) {
-            int c[kRankKeys], r[kRankKeys];
-#pragma unroll
-            for (int u = 0; u < kRankKeys; ++u) {
-                const int e = e0 + u * 64 + lane;
-                c[u] = e < d ? lst[e] : -1;
-                r[u] = 0;
-            }
-            for (int q = 0; q < d; ++q) {
-                const int v = lst[q];
-#pragma unroll
-                for (int u = 0; u < kRankKeys; ++u) r[u] += (v < c[u]) ? 1 : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < kRankKeys; ++u)
-                if (c[u] >= 0) vals[hash_find_fresh<false>(keys, mask, c[u])] = r[u];
         }
     } else {
         // long rows: kRankKeys keys per lane at a time, compared against the
@@ -397,20 +373,107 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
                               sacc[GLOBAL ? 0 : w], stile[GLOBAL ? w : 0]);
 }
 
-// the listed overflow rows with at most kDBig columns: one wavefront per
-// workgroup, with a kHSBig-slot hash table and kDBig accumulators in (96 KB
-// of dynamic) LDS
-__global__ __launch_bounds__(64) void k_spgemm_numeric_big(int nrows, const int* rows, const int* arp,
-                                                           const int* acol, const double* aval, const int* brp,
-                                                           const int* bcol, const double* bval, const int* crp,
-                                                           int* ccol, double* cval) {
+// Overflow row i with at most kDBig columns, by a whole workgroup of kWaves
+// wavefronts on one table in LDS: the wavefronts share the symbolic
+// insertion (every kWaves-th step of 64 products each) and the ranking, and
+// wavefront 0 alone accumulates, in canonical order as numeric_row does.
+__device__ void numeric_row_big(int i, const int* arp, const int* acol, const double* aval, const int* brp,
+                                const int* bcol, const double* bval, const int* crp, int* ccol, double* cval,
+                                int* keys, int* vals, double* acc) {
+    const int tid = (int)threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int base = crp[i];
+    const int d = crp[i + 1] - base;
+    unsigned tsz = 64;
+    while (tsz < 2u * (unsigned)d) tsz <<= 1;
+    const unsigned mask = tsz - 1;
+    for (unsigned h = tid; h <= mask; h += kBlock) {
+        keys[h] = -1;
+        vals[h] = 0;
+    }
+    __syncthreads();
+    for_each_product<false>(
+        arp, acol, nullptr, brp, bcol, nullptr, i,
+        [&](bool valid, int c, double, int, int, int) {
+            if (valid) (void)hash_insert(keys, mask, c);
+            return true;
+        },
+        kWaves, w);
+    __syncthreads();
+    // compact the occupied slots (wavefront 0) into the accumulators' space
+    int* lst = reinterpret_cast<int*>(acc);
+    if (w == 0) {
+        int filled = 0;
+        for (unsigned h0 = 0; h0 <= mask; h0 += 64) {
+            const unsigned h = h0 + lane;
+            const int key = (h <= mask) ? keys[h] : -1;
+            const bool occ = key >= 0;
+            const uint64_t bal = __ballot(occ);
+            const int before = __popcll(bal & ((1ull << lane) - 1ull));
+            if (occ && filled + before < d) lst[filled + before] = key;
+            filled += __popcll(bal);
+        }
+    }
+    __syncthreads();
+    // ranks: kRankKeys keys per lane at a time, the wavefronts taking turns
+    for (int e0 = w * 64 * kRankKeys; e0 < d; e0 += kWaves * 64 * kRankKeys) {
+        int c[kRankKeys], r[kRankKeys];
+#pragma unroll
+        for (int u = 0; u < kRankKeys; ++u) {
+            const int e = e0 + u * 64 + lane;
+            c[u] = e < d ? lst[e] : -1;
+            r[u] = 0;
+        }
+        for (int q = 0; q < d; ++q) {
+            const int v = lst[q];
+#pragma unroll
+            for (int u = 0; u < kRankKeys; ++u) r[u] += (v < c[u]) ? 1 : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kRankKeys; ++u)
+            if (c[u] >= 0) vals[hash_find_fresh<false>(keys, mask, c[u])] = r[u];
+    }
+    __syncthreads();
+    for (unsigned h = tid; h <= mask; h += kBlock) {
+        const int key = keys[h];
+        const int r = vals[h];
+        if (key >= 0 && r >= 0 && r < d) ccol[base + r] = key;
+    }
+    for (int e = tid; e < d; e += kBlock) acc[e] = 0.0;
+    __syncthreads();
+    if (w == 0) {
+        for_each_product<true>(arp, acol, aval, brp, bcol, bval, i,
+                               [&](bool valid, int c, double pv, int t0, int total, int seg) {
+                                   int r = valid ? vals[hash_find_fresh<false>(keys, mask, c)] : 0;
+                                   r = (r >= 0 && r < d) ? r : 0;
+                                   const int m = min(64, total - t0);
+                                   const int s0 = __shfl(seg, 0, 64), s1 = __shfl(seg, m - 1, 64);
+                                   for (int sg = s0; sg <= s1; ++sg) {
+                                       if (valid && seg == sg) acc[r] += pv;
+                                       phase_fence<false>();
+                                   }
+                                   return true;
+                               });
+    }
+    __syncthreads();
+    for (int e = tid; e < d; e += kBlock) cval[base + e] = acc[e];
+    __syncthreads();  // the tables are reused by the workgroup's next row
+}
+
+// the listed overflow rows with at most kDBig columns: a workgroup per row,
+// with a kHSBig-slot hash table and kDBig accumulators in 96 KB of dynamic LDS
+__global__ __launch_bounds__(kBlock) void k_spgemm_numeric_big(int nrows, const int* rows, const int* arp,
+                                                               const int* acol, const double* aval, const int* brp,
+                                                               const int* bcol, const double* bval, const int* crp,
+                                                               int* ccol, double* cval) {
     extern __shared__ __align__(16) unsigned char big_lds[];
     double* sacc = reinterpret_cast<double*>(big_lds);
     int* skeys = reinterpret_cast<int*>(sacc + kDBig);
     int* svals = skeys + kHSBig;
-    for (int ridx = blockIdx.x; ridx < nrows; ridx += gridDim.x)
-        numeric_row<N_BIG, kHSBig>(ridx, rows, arp, acol, aval, brp, bcol, bval, crp, ccol, cval, nullptr, nullptr,
-                                   nullptr, nullptr, nullptr, nullptr, 0, 0, skeys, svals, sacc, nullptr);
+    for (int ridx = blockIdx.x; ridx < nrows; ridx += gridDim.x) {
+        const int i = rows[ridx];
+        if (crp[i + 1] - crp[i] > kDBig) continue;  // block-uniform
+        numeric_row_big(i, arp, acol, aval, brp, bcol, bval, crp, ccol, cval, skeys, svals, sacc);
+    }
 }
 
 // --------------------------------------------------- one thread per row
@@ -722,7 +785,7 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
             return true;
         }();
         (void)big_lds_set;
-        hipLaunchKernelGGL(k_spgemm_numeric_big, dim3(std::min(novf, 4096)), dim3(64), kBigLds, s, novf,
+        hipLaunchKernelGGL(k_spgemm_numeric_big, dim3(std::min(novf, 4096)), dim3(kBlock), kBigLds, s, novf,
                            (const int*)list.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(),
                            B.col.get(), B.val.get(), (const int*)C.rowptr.get(), C.col.get(), C.val.get());
         hipLaunchKernelGGL((k_spgemm_numeric<N_GLOBAL, 1>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
