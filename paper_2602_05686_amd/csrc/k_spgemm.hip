@@ -487,22 +487,21 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric_big(int nrows, const 
 constexpr int kThreadCols = 32;
 constexpr int kThreadRow = -3;  // pcount marker of a row on the thread path
 
-// add product (c, v) to the row's column list key/acc[0..d) (v when VAL);
-// returns false when a new column does not fit
-template <bool VAL>
-__device__ __forceinline__ bool thread_row_add(int (&key)[kThreadCols], double (&acc)[kThreadCols], int& d, int c,
-                                               double v) {
+// add product (c, v) to the row's column list key/acc[0..d) of S slots (v
+// when VAL); returns false when a new column does not fit
+template <bool VAL, int S>
+__device__ __forceinline__ bool thread_row_add(int (&key)[S], double (&acc)[S], int& d, int c, double v) {
     bool found = false;
 #pragma unroll
-    for (int j = 0; j < kThreadCols; ++j)
+    for (int j = 0; j < S; ++j)
         if (key[j] == c) {
             found = true;
             if constexpr (VAL) acc[j] += v;
         }
     if (found) return true;
-    if (d == kThreadCols) return false;
+    if (d == S) return false;
 #pragma unroll
-    for (int j = 0; j < kThreadCols; ++j)
+    for (int j = 0; j < S; ++j)
         if (j == d) {
             key[j] = c;
             if constexpr (VAL) acc[j] = 0.0 + v;  // as the wavefront path: a zeroed sum plus the first product
@@ -562,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic_thread(int n, const 
         int d = 0;
         bool fits = true;
         thread_row_products<false, 8>(arp, acol, nullptr, brp, bcol, nullptr, i, [&](int c, double) {
-            if (fits && !thread_row_add<false>(key, acc, d, c, 0.0)) fits = false;
+            if (fits && !thread_row_add<false, kThreadCols>(key, acc, d, c, 0.0)) fits = false;
         });
         wide[i] = fits ? 0 : 1;
         if (fits) {
@@ -572,31 +571,36 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic_thread(int n, const 
     }
 }
 
-// numeric for the rows the thread symbolic pass kept
+// numeric for the rows the thread symbolic pass kept whose column count
+// lies in (dlo, S], with S register slots (fewer slots for narrower rows:
+// fewer registers and compares per product; the additions are the same)
+template <int S>
 __global__ __launch_bounds__(kBlock) void k_spgemm_numeric_thread(int n, const int* arp, const int* acol,
                                                                   const double* aval, const int* brp,
                                                                   const int* bcol, const double* bval,
                                                                   const int* pcount, const int* crp, int* ccol,
-                                                                  double* cval) {
+                                                                  double* cval, int dlo) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         if (pcount[i] != kThreadRow) continue;
-        int key[kThreadCols];
-        double acc[kThreadCols];
+        const int base = crp[i];
+        const int dr = crp[i + 1] - base;
+        if (dr <= dlo || dr > S) continue;
+        int key[S];
+        double acc[S];
 #pragma unroll
-        for (int j = 0; j < kThreadCols; ++j) {
+        for (int j = 0; j < S; ++j) {
             key[j] = -1;
             acc[j] = 0.0;
         }
         int d = 0;
         thread_row_products<true, 4>(arp, acol, aval, brp, bcol, bval, i,
-                                     [&](int c, double v) { (void)thread_row_add<true>(key, acc, d, c, v); });
-        const int base = crp[i];
+                                     [&](int c, double v) { (void)thread_row_add<true, S>(key, acc, d, c, v); });
 #pragma unroll
-        for (int j = 0; j < kThreadCols; ++j) {
+        for (int j = 0; j < S; ++j) {
             if (key[j] < 0) continue;
             int r = 0;
 #pragma unroll
-            for (int q = 0; q < kThreadCols; ++q) r += (key[q] >= 0 && key[q] < key[j]) ? 1 : 0;
+            for (int q = 0; q < S; ++q) r += (key[q] >= 0 && key[q] < key[j]) ? 1 : 0;
             ccol[base + r] = key[j];
             cval[base + r] = acc[j];
         }
@@ -761,9 +765,12 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
     C.col.alloc((size_t)(nnz > 0 ? nnz : 1), mc);
     C.val.alloc((size_t)(nnz > 0 ? nnz : 1), mc);
     if (n > 0) {
-        hipLaunchKernelGGL(k_spgemm_numeric_thread, dim3(g1(n)), dim3(kBlock), 0, s, n, A.rowptr.get(), A.col.get(),
-                           A.val.get(), B.rowptr.get(), B.col.get(), B.val.get(), (const int*)pcount.get(),
-                           C.rowptr.get(), C.col.get(), C.val.get());
+        hipLaunchKernelGGL(k_spgemm_numeric_thread<kThreadCols / 2>, dim3(g1(n)), dim3(kBlock), 0, s, n,
+                           A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(), B.val.get(),
+                           (const int*)pcount.get(), C.rowptr.get(), C.col.get(), C.val.get(), -1);
+        hipLaunchKernelGGL(k_spgemm_numeric_thread<kThreadCols>, dim3(g1(n)), dim3(kBlock), 0, s, n, A.rowptr.get(),
+                           A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(), B.val.get(),
+                           (const int*)pcount.get(), C.rowptr.get(), C.col.get(), C.val.get(), kThreadCols / 2);
         // wide rows with few products: small tables, so more wavefronts fit a CU
         hipLaunchKernelGGL((k_spgemm_numeric<N_LDS, kHSSmall>), dim3(wgrid), dim3(kBlock), 0, s, 0, nwide_dev,
                            (const int*)wl.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(),
