@@ -931,7 +931,8 @@ void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, c
     zero_async(nlist, sizeof(int), s);
     LAUNCH(k_agg_phase3_split, n, n, dir, phase2, agg, list, nlist);
     if (n > 0) {
-        hipLaunchKernelGGL(k_agg_phase3_rows, dim3(1024), dim3(kBlock), 0, s, rowptr, col, mask, phase2,
+        hipLaunchKernelGGL(k_agg_phase3_rows, dim3(std::min(ceil_div(n, kBlock / 64), 8192)), dim3(kBlock), 0, s,
+                           rowptr, col, mask, phase2,
                            (const int*)list, (const int*)nlist, agg);
         MATAMG_LAUNCH_CHECK();
     }

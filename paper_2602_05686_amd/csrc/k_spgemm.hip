@@ -612,17 +612,18 @@ __global__ void k_list_flagged(int n, const int* flags, const int* pos, int* lis
         if (flags[i]) list[pos[i]] = i;
 }
 
-// product-count upper bound of each listed row, as a hash table size (power of two >= 2*m)
-__global__ void k_row_table_size(int nrows, const int* rows, const int* arp, const int* acol, const int* brp,
-                                 int ncols, int64_t* size) {
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += gridDim.x * blockDim.x) {
-        const int i = rows[r];
-        int64_t m = 0;
-        for (int k = arp[i]; k < arp[i + 1]; ++k) m += brp[acol[k] + 1] - brp[acol[k]];
+// product-count upper bound of each listed row, as a hash table size (power
+// of two >= 2*m): a wavefront per row, lane-strided over its A entries
+__global__ __launch_bounds__(kBlock) void k_row_table_size(int nrows, const int* rows, const int* arp,
+                                                           const int* acol, const int* brp, int ncols,
+                                                           int64_t* size) {
+    const int w = (int)threadIdx.x >> 6;
+    for (int r = blockIdx.x * kWaves + w; r < nrows; r += gridDim.x * kWaves) {
+        int64_t m = row_products(arp, acol, brp, rows[r]);
         if (m > ncols) m = ncols;
         int64_t t = 64;
         while (t < 2 * m) t <<= 1;
-        size[r] = t;
+        if ((threadIdx.x & 63) == 0) size[r] = t;
     }
 }
 
@@ -645,16 +646,28 @@ __global__ void k_overflow_list(int n, const int* flags, const int* pos, int* li
         if (flags[i]) list[pos[i]] = i;
 }
 
-__global__ void k_scan64(int n, const int64_t* in, int64_t* out) {
-    // small serial exclusive scan (overflow rows are few)
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        int64_t s = 0;
-        for (int i = 0; i < n; ++i) {
-            out[i] = s;
-            s += in[i];
+// exclusive scan of n 64-bit values by one block, kBlock at a time with a
+// running carry (overflow rows are few)
+__global__ __launch_bounds__(kBlock) void k_scan64(int n, const int64_t* in, int64_t* out) {
+    __shared__ int64_t sh[kBlock];
+    int64_t carry = 0;
+    for (int b = 0; b < n; b += kBlock) {
+        const int i = b + (int)threadIdx.x;
+        const int64_t v = i < n ? in[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        // inclusive Hillis-Steele scan in LDS
+        for (int off = 1; off < kBlock; off <<= 1) {
+            const int64_t y = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += y;
+            __syncthreads();
         }
-        out[n] = s;
+        if (i < n) out[i] = carry + sh[threadIdx.x] - v;
+        carry += sh[kBlock - 1];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[n] = carry;
 }
 
 // ---------------------------------------------------------------- transpose
@@ -746,9 +759,9 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
         hipLaunchKernelGGL(k_overflow_list, dim3(g1(n)), dim3(kBlock), 0, s, n, flags.get(), pos.get(), list.get());
         tsize.alloc((size_t)novf, mc);
         toff.alloc((size_t)novf + 1, mc);
-        hipLaunchKernelGGL(k_row_table_size, dim3(g1(novf)), dim3(kBlock), 0, s, novf, list.get(), A.rowptr.get(),
-                           A.col.get(), B.rowptr.get(), B.m, tsize.get());
-        hipLaunchKernelGGL(k_scan64, dim3(1), dim3(1), 0, s, novf, tsize.get(), toff.get());
+        hipLaunchKernelGGL(k_row_table_size, dim3(std::min(ceil_div(novf, kWaves), 8192)), dim3(kBlock), 0, s, novf,
+                           list.get(), A.rowptr.get(), A.col.get(), B.rowptr.get(), B.m, tsize.get());
+        hipLaunchKernelGGL(k_scan64, dim3(1), dim3(kBlock), 0, s, novf, tsize.get(), toff.get());
         int64_t tot = 0;
         d2h(&tot, toff.get() + novf, 1, s);
         gkeys.alloc((size_t)tot, mc);
