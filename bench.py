@@ -429,15 +429,25 @@ def run_reuse(args, amg, log):
             "op_complexity_fresh": st_f["op_complexity"], "rhs_solves": solves, "amortised": amort}
 
 
+def stats_ms(v):
+    """mean, standard deviation, median, min and max of a list of times (ms)"""
+    v = np.asarray(v, dtype=float)
+    return {"mean": float(v.mean()), "std": float(v.std(ddof=1)) if v.size > 1 else 0.0,
+            "median": float(np.median(v)), "min": float(v.min()), "max": float(v.max()), "n": int(v.size)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128, help="hexes per side")
     ap.add_argument("--repeats", type=int, default=20)
     ap.add_argument("--stretch", type=float, default=10.0)
-    ap.add_argument("--vcycles", type=int, default=50)
+    ap.add_argument("--max-levels", type=int, default=10, help="hierarchy depth cap (the 192^3 stack needs 16)")
+    ap.add_argument("--max-iter", type=int, default=1000, help="PCG iteration cap")
+    ap.add_argument("--vcycles", type=int, default=100)
+    ap.add_argument("--fp32-reps", type=int, default=5, help="timed FP32-form solves on one hierarchy")
     ap.add_argument("--cpu-sample", type=int, default=5, help="oracle PCG iterations in the CPU sample (0: skip)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="one setup, a few V-cycles and a 1 GiB device copy (for counter collection), no JSON")
@@ -508,13 +518,13 @@ def main():
              es=torch.from_numpy(prob.elem_sigma).to(dev), xc=torch.from_numpy(prob.coords).to(dev),
              b=torch.from_numpy(prob.b).to(dev))
     x = torch.zeros(n, dtype=torch.float64, device=dev)
-    opts64 = amg.options(dim=3)
+    opts64 = amg.options(dim=3, max_levels=args.max_levels)
     torch.cuda.synchronize()
 
     def step(opts):
         h = amg.Hierarchy(d["rowptr"], d["col"], d["val"], d["en"], d["es"], d["xc"], opts)
         x.zero_()
-        _, info = h.solve(d["b"], x)
+        _, info = h.solve(d["b"], x, max_iter=args.max_iter)
         return h, info
 
     if args.profile_kernels:
@@ -538,11 +548,14 @@ def main():
         h, info = step(opts64)
         h.close()
     log(f"timing {args.steps} step(s)")
-    infos, setups = [], []
+    infos, setups, step_ms = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
+        ts = time.perf_counter()
         h, info = step(opts64)
+        torch.cuda.synchronize()
+        step_ms.append(1e3 * (time.perf_counter() - ts))
         infos.append(info)
         setups.append(h.stats()["t_setup_s"])
         if k + 1 < args.steps:
@@ -588,19 +601,23 @@ def main():
 
     fp32 = None
     if not args.no_fp32:
-        opts32 = amg.options(dim=3, precision="fp32")
+        opts32 = amg.options(dim=3, precision="fp32", max_levels=args.max_levels)
         h32, _ = step(opts32)
-        x.zero_()
-        _, info32 = h32.solve(d["b"], x)
+        t32 = []
+        for _ in range(max(1, args.fp32_reps)):
+            x.zero_()
+            _, info32 = h32.solve(d["b"], x, max_iter=args.max_iter)
+            t32.append(info32["t_solve_s"])
         x32 = x.cpu().numpy()
         h32.close()
-        fp32 = dict(t_solve_s=info32["t_solve_s"], iterations=info32["iterations"], rel_res=info32["rel_res"],
-                    status=info32["status"], speedup_vs_fp64_solve=t_solve / info32["t_solve_s"],
+        t32m = float(np.mean(t32))
+        fp32 = dict(t_solve_s=t32m, t_solve_ms_stats=stats_ms(np.array(t32) * 1e3), iterations=info32["iterations"],
+                    rel_res=info32["rel_res"], status=info32["status"], speedup_vs_fp64_solve=t_solve / t32m,
                     speedup_per_iteration=(t_solve / infos[-1]["iterations"]) /
-                    (info32["t_solve_s"] / max(1, info32["iterations"])),
+                    (t32m / max(1, info32["iterations"])),
                     rel_err_vs_fp64_form=float(np.linalg.norm(x32 - x64) / np.linalg.norm(x64)),
                     rel_err_vs_closed_form=float(np.linalg.norm(x32 - exact) / np.linalg.norm(exact)))
-        log(f"fp32 form: solve {info32['t_solve_s'] * 1e3:.1f} ms, iters {info32['iterations']}")
+        log(f"fp32 form: solve {t32m * 1e3:.1f} ms (mean of {len(t32)}), iters {info32['iterations']}")
 
     serving = None
     if not args.no_serving:
@@ -633,6 +650,10 @@ def main():
         "solve_only_dof_per_s": n / t_solve,
         "t_setup_ms": 1e3 * float(np.mean(setups)),
         "t_solve_ms": 1e3 * t_solve,
+        "step_ms_stats": stats_ms(step_ms),
+        "t_setup_ms_stats": stats_ms(np.array(setups) * 1e3),
+        "t_solve_ms_stats": stats_ms(np.array([i["t_solve_s"] for i in infos]) * 1e3),
+        "iterations_per_step": sorted(set(int(i["iterations"]) for i in infos)),
         "iterations": infos[-1]["iterations"],
         "rel_res_true": infos[-1]["rel_res"],
         "rel_err_vs_closed_form": err64,

@@ -1,6 +1,9 @@
 // extern "C" boundary: argument checks, error translation, data accessors.
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
 #include <string>
 
 #include "hierarchy.h"
@@ -24,6 +27,78 @@ void* readback_buffer() {
     thread_local void* buf = nullptr;
     if (!buf) MATAMG_HIP(hipHostMalloc(&buf, kReadbackBytes, hipHostMallocDefault));
     return buf;
+}
+
+namespace {
+std::mutex g_idle_mu;
+std::unordered_map<uint64_t, std::vector<void*>> g_idle;  // (device, bytes) -> buffers
+uint64_t g_idle_bytes = 0;
+std::mutex g_stream_mu;
+std::vector<hipStream_t> g_streams[64];  // idle solve streams per device
+
+uint64_t idle_key(size_t bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    return ((uint64_t)(dev & 0xff) << 56) | (uint64_t)bytes;
+}
+}  // namespace
+
+void* idle_take(size_t bytes) {
+    const uint64_t key = idle_key(bytes);
+    std::lock_guard<std::mutex> lock(g_idle_mu);
+    auto it = g_idle.find(key);
+    if (it == g_idle.end() || it->second.empty()) return nullptr;
+    void* p = it->second.back();
+    it->second.pop_back();
+    g_idle_bytes -= bytes;
+    return p;
+}
+
+bool idle_put(void* p, size_t bytes) {
+    const uint64_t key = idle_key(bytes);
+    std::lock_guard<std::mutex> lock(g_idle_mu);
+    if (g_idle_bytes + bytes > kIdleCacheBytes) return false;
+    g_idle[key].push_back(p);
+    g_idle_bytes += bytes;
+    return true;
+}
+
+hipStream_t take_stream() {
+    int dev = 0;
+    MATAMG_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lock(g_stream_mu);
+        if (dev >= 0 && dev < 64 && !g_streams[dev].empty()) {
+            hipStream_t st = g_streams[dev].back();
+            g_streams[dev].pop_back();
+            return st;
+        }
+    }
+    hipStream_t st = nullptr;
+    MATAMG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    return st;
+}
+
+void give_stream(hipStream_t st) {
+    if (!st) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipStreamDestroy(st);
+        return;
+    }
+    std::lock_guard<std::mutex> lock(g_stream_mu);
+    g_streams[dev].push_back(st);
+}
+
+hipStream_t release_stream() {
+    static hipStream_t streams[64] = {nullptr};
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        streams[dev] = nullptr;
+    return streams[dev];
 }
 
 bool pool_enabled() {
@@ -292,11 +367,19 @@ amg_status amg_time_smoother(amg_hierarchy* hh, int32_t level, int32_t reps, voi
 
 void amg_free(amg_hierarchy* h) {
     if (!h) return;
-    // pooled buffers are released on the null stream: let every stream of
-    // the device finish with them first
+    // let every stream of the device finish with the buffers; the pooled ones
+    // are then idle and kept for reuse (those beyond the cache's limit go back
+    // to the pool on a stream of the library's own)
     (void)hipDeviceSynchronize();
     try {
-        delete h;
+        hipStream_t fs = release_stream();
+        {
+            // the device is idle: its buffers are kept for the next hierarchy
+            AllocStreamScope scope(fs, true);
+            alloc_mode().idle = true;
+            delete h;
+        }
+        if (fs) (void)hipStreamSynchronize(fs);
     } catch (...) {
     }
 }

@@ -55,6 +55,7 @@ struct MemCounter {
 struct AllocMode {
     bool pooled = false;
     hipStream_t stream = nullptr;
+    bool idle = false;  // released buffers are idle (the device is synchronised): keep them for reuse
 };
 AllocMode& alloc_mode();
 struct AllocStreamScope {
@@ -66,10 +67,26 @@ struct AllocStreamScope {
     AllocStreamScope(const AllocStreamScope&) = delete;
     AllocStreamScope& operator=(const AllocStreamScope&) = delete;
 };
+// Idle device buffers kept for reuse.  A stream-ordered allocation or free
+// costs 0.1-0.25 ms of host time each in this runtime (a hierarchy holds
+// a few hundred buffers), so the buffers of a freed hierarchy, released once
+// the device is idle, are kept here by device and exact byte size and handed
+// to the next pooled allocation of that size on the device, whatever its
+// stream.  At most kIdleCacheBytes per process are kept.
+constexpr uint64_t kIdleCacheBytes = 32ull << 30;
+void* idle_take(size_t bytes);            // nullptr if none is kept
+bool idle_put(void* p, size_t bytes);     // false when the cache is full
+// a per-device solve stream from the library's free list (created when the
+// list is empty; default priority), and its return
+hipStream_t take_stream();
+void give_stream(hipStream_t s);
 // keep memory freed to the device's default pool for reuse (idempotent)
 void keep_pool_memory(int device);
 // false when MATAMG_NO_POOL=1 asks for plain hipMalloc / hipFree everywhere
 bool pool_enabled();
+// a per-device stream of the library (default priority, created once) on which
+// the pooled buffers of a freed hierarchy are handed back
+hipStream_t release_stream();
 
 template <typename T>
 class DBuf {
@@ -94,7 +111,13 @@ class DBuf {
         if (n == 0) return;
         const AllocMode m = alloc_mode();
         pooled_ = m.pooled;
-        hipError_t e = pooled_ ? hipMallocAsync((void**)&p_, n * sizeof(T), m.stream) : hipMalloc(&p_, n * sizeof(T));
+        hipError_t e = hipSuccess;
+        if (pooled_) {
+            p_ = static_cast<T*>(idle_take(n * sizeof(T)));
+            if (!p_) e = hipMallocAsync((void**)&p_, n * sizeof(T), m.stream);
+        } else {
+            e = hipMalloc(&p_, n * sizeof(T));
+        }
         if (e != hipSuccess) {
             p_ = nullptr;
             n_ = 0;
@@ -107,8 +130,11 @@ class DBuf {
             // a pooled buffer goes back to the pool in the order of the current
             // thread's stream (the null stream outside a scope: callers free
             // hierarchies only once the device is idle)
-            if (pooled_) (void)hipFreeAsync(p_, alloc_mode().stream);
-            else (void)hipFree(p_);
+            if (pooled_) {
+                if (!(alloc_mode().idle && idle_put(p_, n_ * sizeof(T)))) (void)hipFreeAsync(p_, alloc_mode().stream);
+            } else {
+                (void)hipFree(p_);
+            }
             if (mc_) mc_->add(-(int64_t)(n_ * sizeof(T)));
         }
         p_ = nullptr;

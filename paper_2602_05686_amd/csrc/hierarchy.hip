@@ -154,7 +154,7 @@ Hierarchy::~Hierarchy() {
     for (auto& g : graph)
         if (g) (void)hipGraphExecDestroy(g);
     if (ev_in) (void)hipEventDestroy(ev_in);
-    if (ws) (void)hipStreamDestroy(ws);
+    give_stream(ws);  // back to the library's free list (its work stays ordered before later use)
 }
 
 // Steady-state duration of one smoother step on `level` (the fused
@@ -208,7 +208,7 @@ double Hierarchy::time_smoother(int level, int reps, hipStream_t s, double* byte
 // on the first solve (hierarchies driven by the solve server never need them)
 void Hierarchy::ensure_solve_resources() {
     if (!hscal) MATAMG_HIP(hipHostMalloc((void**)&hscal, sizeof(double) * S_NSCAL, hipHostMallocDefault));
-    if (!ws) MATAMG_HIP(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
+    if (!ws) ws = take_stream();
     if (!ev_in) MATAMG_HIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
 }
 
