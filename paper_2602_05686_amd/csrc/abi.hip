@@ -63,6 +63,47 @@ bool idle_put(void* p, size_t bytes) {
     return true;
 }
 
+namespace {
+std::mutex g_temp_mu;
+std::unordered_map<hipStream_t, std::unordered_map<size_t, std::vector<void*>>> g_temps;
+uint64_t g_temp_bytes = 0;
+}  // namespace
+
+void* stream_take(hipStream_t st, size_t bytes) {
+    std::lock_guard<std::mutex> lock(g_temp_mu);
+    auto it = g_temps.find(st);
+    if (it == g_temps.end()) return nullptr;
+    auto jt = it->second.find(bytes);
+    if (jt == it->second.end() || jt->second.empty()) return nullptr;
+    void* p = jt->second.back();
+    jt->second.pop_back();
+    g_temp_bytes -= bytes;
+    return p;
+}
+
+bool stream_put(hipStream_t st, void* p, size_t bytes) {
+    std::lock_guard<std::mutex> lock(g_temp_mu);
+    if (g_temp_bytes + bytes > kIdleCacheBytes) return false;
+    g_temps[st][bytes].push_back(p);
+    g_temp_bytes += bytes;
+    return true;
+}
+
+void stream_cache_flush(hipStream_t st, bool to_idle) {
+    std::unordered_map<size_t, std::vector<void*>> mine;
+    {
+        std::lock_guard<std::mutex> lock(g_temp_mu);
+        auto it = g_temps.find(st);
+        if (it == g_temps.end()) return;
+        mine.swap(it->second);
+        g_temps.erase(it);
+        for (auto& kv : mine) g_temp_bytes -= kv.first * kv.second.size();
+    }
+    for (auto& kv : mine)
+        for (void* p : kv.second)
+            if (!(to_idle && idle_put(p, kv.first))) (void)hipFreeAsync(p, st);
+}
+
 hipStream_t take_stream() {
     int dev = 0;
     MATAMG_HIP(hipGetDevice(&dev));

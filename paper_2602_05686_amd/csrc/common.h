@@ -55,7 +55,8 @@ struct MemCounter {
 struct AllocMode {
     bool pooled = false;
     hipStream_t stream = nullptr;
-    bool idle = false;  // released buffers are idle (the device is synchronised): keep them for reuse
+    bool idle = false;   // released buffers are idle (the device is synchronised): keep them for reuse
+    bool temps = false;  // released buffers are kept for later allocations on the same stream
 };
 AllocMode& alloc_mode();
 struct AllocStreamScope {
@@ -76,6 +77,13 @@ struct AllocStreamScope {
 constexpr uint64_t kIdleCacheBytes = 32ull << 30;
 void* idle_take(size_t bytes);            // nullptr if none is kept
 bool idle_put(void* p, size_t bytes);     // false when the cache is full
+// Buffers released in stream order during a setup, kept (by stream and exact
+// size) for the setup's later allocations on the same stream, which are
+// ordered after every use of the buffer; at the setup's end they become idle
+// buffers (the stream synchronised) or, after a failure, go back to the pool.
+void* stream_take(hipStream_t s, size_t bytes);
+bool stream_put(hipStream_t s, void* p, size_t bytes);
+void stream_cache_flush(hipStream_t s, bool to_idle);
 // a per-device solve stream from the library's free list (created when the
 // list is empty; default priority), and its return
 hipStream_t take_stream();
@@ -113,7 +121,8 @@ class DBuf {
         pooled_ = m.pooled;
         hipError_t e = hipSuccess;
         if (pooled_) {
-            p_ = static_cast<T*>(idle_take(n * sizeof(T)));
+            p_ = m.temps ? static_cast<T*>(stream_take(m.stream, n * sizeof(T))) : nullptr;
+            if (!p_) p_ = static_cast<T*>(idle_take(n * sizeof(T)));
             if (!p_) e = hipMallocAsync((void**)&p_, n * sizeof(T), m.stream);
         } else {
             e = hipMalloc(&p_, n * sizeof(T));
@@ -131,7 +140,10 @@ class DBuf {
             // thread's stream (the null stream outside a scope: callers free
             // hierarchies only once the device is idle)
             if (pooled_) {
-                if (!(alloc_mode().idle && idle_put(p_, n_ * sizeof(T)))) (void)hipFreeAsync(p_, alloc_mode().stream);
+                const AllocMode& m = alloc_mode();
+                const size_t b = n_ * sizeof(T);
+                const bool kept = (m.idle && idle_put(p_, b)) || (m.temps && stream_put(m.stream, p_, b));
+                if (!kept) (void)hipFreeAsync(p_, m.stream);
             } else {
                 (void)hipFree(p_);
             }

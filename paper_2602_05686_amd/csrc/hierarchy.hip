@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdlib>
 
+#include <exception>
+
 #include "hierarchy.h"
 #include "setup_kernels.h"
 
@@ -313,7 +315,13 @@ void cast_fp32(Hierarchy& h, hipStream_t s) {
 // a setup's or update's temporaries come from the pool in the order of its
 // stream, unless the caller's thread already set a scope (the solve
 // server's workers do)
+//
+// A scope opened here (not a server thread's) also keeps the temporaries it
+// releases for its own later allocations on the stream; when it closes, the
+// stream is synchronised and they become idle buffers, or, when it closes
+// because of an error, they go back to the pool in stream order.
 struct SetupAllocScope {
+    bool own;  // declared first: initialised before the scope is opened
     AllocStreamScope scope;
     static hipStream_t pick(hipStream_t s) {
         if (!alloc_mode().pooled && pool_enabled()) {
@@ -323,7 +331,18 @@ struct SetupAllocScope {
         }
         return alloc_mode().pooled ? alloc_mode().stream : s;
     }
-    explicit SetupAllocScope(hipStream_t s) : scope(pick(s), alloc_mode().pooled || pool_enabled()) {}
+    explicit SetupAllocScope(hipStream_t s)
+        : own(!alloc_mode().pooled && pool_enabled()), scope(pick(s), alloc_mode().pooled || pool_enabled()) {
+        if (own) alloc_mode().temps = true;
+    }
+    ~SetupAllocScope() {
+        if (!own) return;
+        const hipStream_t st = alloc_mode().stream;
+        const bool clean = std::uncaught_exceptions() == 0 && hipStreamSynchronize(st) == hipSuccess;
+        stream_cache_flush(st, clean);
+    }
+    SetupAllocScope(const SetupAllocScope&) = delete;
+    SetupAllocScope& operator=(const SetupAllocScope&) = delete;
 };
 
 }  // namespace
