@@ -8,8 +8,8 @@
 // row next(r) that depends on r alone, so every next(r) is computed in
 // parallel (binary searches over the row pointer and the list of long rows)
 // and the block starts -- the orbit of row 0 under next -- are marked by
-// pointer doubling: after round k every start within 2^(k+1) blocks of row 0
-// is marked.  The result equals the host walk exactly.
+// radix-8 pointer jumping: after round k every start within 8^(k+1) blocks
+// of row 0 is marked.  The result equals the host walk exactly.
 #include <algorithm>
 
 #include "device_util.h"
@@ -115,17 +115,21 @@ __global__ void k_mark_init(int n, int* mark) {
     FOR_ROWS(p, (int64_t)n + 1) mark[p] = (p == 0) ? 1 : 0;
 }
 
-// One doubling round: every marked start marks the start `jump` blocks
-// ahead of it, and (if out is set) out = jump o jump.  A mark set by another
-// thread of the same round may be seen early; that only marks a true start
-// sooner (marks are only ever set on the orbit of row 0), so after the round
-// at least the starts within twice the span are marked, as with the rounds
-// apart.
-__global__ void k_mark_square(int n, const int* jump, int* mark, int* out) {
+// One round of radix-8 doubling with jump = J: every marked start p marks
+// J(p), J^2(p), ..., J^7(p), and (if out is set) out = J^8.  A mark set by
+// another thread of the same round may be seen early; that only marks a
+// true start sooner (marks are only ever set on the orbit of row 0), so
+// after the round at least the starts within eight times the span are
+// marked, as with the rounds apart.
+__global__ void k_mark_pow8(int n, const int* jump, int* mark, int* out) {
     FOR_ROWS(p, (int64_t)n + 1) {
-        const int j = jump[p];
-        if (mark[p]) mark[j] = 1;
-        if (out) out[p] = jump[j];
+        const bool mk = mark[p] != 0;
+        int q = (int)p;
+        for (int t = 1; t < 8; ++t) {
+            q = jump[q];
+            if (mk) mark[q] = 1;
+        }
+        if (out) out[p] = jump[q];
     }
 }
 
@@ -226,9 +230,9 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack) {
     hipLaunchKernelGGL(k_mark_init, dim3(grid1(n1)), dim3(kBlock), 0, s, n, flags.get());
     int* cur = ja.get();
     int* nxt = jb.get();
-    for (int64_t span = 1; span <= (int64_t)n; span <<= 1) {
-        const bool more = (span << 1) <= (int64_t)n;
-        hipLaunchKernelGGL(k_mark_square, dim3(grid1(n1)), dim3(kBlock), 0, s, n, (const int*)cur, flags.get(),
+    for (int64_t span = 1; span <= (int64_t)n; span <<= 3) {
+        const bool more = (span << 3) <= (int64_t)n;
+        hipLaunchKernelGGL(k_mark_pow8, dim3(grid1(n1)), dim3(kBlock), 0, s, n, (const int*)cur, flags.get(),
                            more ? nxt : (int*)nullptr);
         if (more) std::swap(cur, nxt);
     }
