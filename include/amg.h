@@ -207,6 +207,11 @@ amg_status amg_get_level_aux(const amg_hierarchy* h, int32_t level, int32_t whic
 amg_status amg_time_smoother(amg_hierarchy* h, int32_t level, int32_t reps, void* hip_stream, double* avg_ms,
                              double* bytes_per_launch);
 
+/* Frees a hierarchy (null: no-op).  Waits for every stream of the device,
+ * then keeps the hierarchy's device buffers in the library (up to 32 GiB per
+ * process) for later setups of the same sizes, which skip the runtime's
+ * allocation cost; the memory stays reserved to the process.  The hierarchy
+ * must not be in use on any stream. */
 void amg_free(amg_hierarchy* h);
 
 /* ------------------------------------------------------------------------
