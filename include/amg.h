@@ -214,6 +214,12 @@ amg_status amg_time_smoother(amg_hierarchy* h, int32_t level, int32_t reps, void
  * must not be in use on any stream. */
 void amg_free(amg_hierarchy* h);
 
+/* Hands the device buffers kept by amg_free on the current device back to the
+ * device's memory pool (for callers that need the memory elsewhere).  Waits
+ * for every stream of the device.  bytes (optional, host): the number of
+ * bytes handed back.  Errors: HIP. */
+amg_status amg_trim_cache(int64_t* bytes);
+
 /* ------------------------------------------------------------------------
  * Serving: a solve server that keeps many hierarchies on the device and
  * advances all their solves together (continuous batching).

@@ -13,4 +13,5 @@ from ._lib import (  # noqa: F401
     Server,
     load,
     options,
+    trim_cache,
 )

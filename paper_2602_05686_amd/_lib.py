@@ -30,7 +30,7 @@ EXPORTED = [
     "amg_options_default", "amg_setup", "amg_pcg_solve", "amg_update_values", "amg_vcycle", "amg_level_spmv",
     "amg_hierarchy_info",
     "amg_get_aggregates", "amg_get_soc_mask", "amg_get_level_csr", "amg_get_level_aux", "amg_time_smoother",
-    "amg_free", "amg_status_string", "amg_last_error",
+    "amg_free", "amg_trim_cache", "amg_status_string", "amg_last_error",
     "amg_server_create", "amg_server_submit", "amg_server_poll", "amg_server_result", "amg_server_info",
     "amg_server_set_batch_wait", "amg_server_destroy",
 ]
@@ -134,6 +134,7 @@ def load():
     L.amg_time_smoother.argtypes = [P, i32, i32, P, ctypes.POINTER(f64), ctypes.POINTER(f64)]
     L.amg_free.argtypes = [P]
     L.amg_free.restype = None
+    L.amg_trim_cache.argtypes = [ctypes.POINTER(ctypes.c_int64)]
     L.amg_server_create.argtypes = [ctypes.POINTER(Options), i64, i32, i32, ctypes.POINTER(P)]
     L.amg_server_submit.argtypes = [P, i64, P, P, P, i64, i32, P, P, P, P, P, f64, i32,
                                     ctypes.POINTER(ctypes.c_uint64)]
@@ -175,6 +176,13 @@ def options(dim=3, **kw) -> Options:
             v = DROP[v]
         setattr(o, k, v)
     return o
+
+
+def trim_cache() -> int:
+    """Hand the device buffers kept by freed hierarchies back to the pool; returns their bytes."""
+    n = ctypes.c_int64(0)
+    check(load().amg_trim_cache(ctypes.byref(n)), "amg_trim_cache")
+    return int(n.value)
 
 
 def _hp(a: np.ndarray):

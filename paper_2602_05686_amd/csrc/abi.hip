@@ -104,6 +104,32 @@ void stream_cache_flush(hipStream_t st, bool to_idle) {
             if (!(to_idle && idle_put(p, kv.first))) (void)hipFreeAsync(p, st);
 }
 
+uint64_t idle_trim(hipStream_t st) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    const uint64_t mine = (uint64_t)(dev & 0xff) << 56;
+    std::vector<std::pair<void*, size_t>> out;
+    {
+        std::lock_guard<std::mutex> lock(g_idle_mu);
+        for (auto it = g_idle.begin(); it != g_idle.end();) {
+            if ((it->first & (0xffull << 56)) == mine) {
+                const size_t bytes = (size_t)(it->first & ((1ull << 56) - 1));
+                for (void* p : it->second) out.emplace_back(p, bytes);
+                g_idle_bytes -= bytes * it->second.size();
+                it = g_idle.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    uint64_t total = 0;
+    for (auto& pb : out) {
+        (void)hipFreeAsync(pb.first, st);
+        total += pb.second;
+    }
+    return total;
+}
+
 hipStream_t take_stream() {
     int dev = 0;
     MATAMG_HIP(hipGetDevice(&dev));
@@ -423,6 +449,17 @@ void amg_free(amg_hierarchy* h) {
         if (fs) (void)hipStreamSynchronize(fs);
     } catch (...) {
     }
+}
+
+amg_status amg_trim_cache(int64_t* bytes) {
+    return guarded([&]() -> amg_status {
+        MATAMG_HIP(hipDeviceSynchronize());
+        hipStream_t fs = release_stream();
+        const uint64_t b = idle_trim(fs);
+        if (fs) MATAMG_HIP(hipStreamSynchronize(fs));
+        if (bytes) *bytes = (int64_t)b;
+        return AMG_OK;
+    });
 }
 
 // ------------------------------------------------------------------ serving

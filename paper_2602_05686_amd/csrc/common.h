@@ -77,6 +77,8 @@ struct AllocStreamScope {
 constexpr uint64_t kIdleCacheBytes = 32ull << 30;
 void* idle_take(size_t bytes);            // nullptr if none is kept
 bool idle_put(void* p, size_t bytes);     // false when the cache is full
+// frees the idle buffers of the current device on stream s; returns their bytes
+uint64_t idle_trim(hipStream_t s);
 // Buffers released in stream order during a setup, kept (by stream and exact
 // size) for the setup's later allocations on the same stream, which are
 // ordered after every use of the buffer; at the setup's end they become idle

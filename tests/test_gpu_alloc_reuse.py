@@ -62,6 +62,12 @@ def test_reused_buffers_give_bitwise_the_same_setup_and_solve(amg):
     assert np.array_equal(x4, x1) and i4["iterations"] == i1["iterations"]
     g.close()
     h.close()
+    # the kept buffers go back to the pool; a setup after that still agrees
+    assert amg.trim_cache() > 0
+    assert amg.trim_cache() == 0
+    h, x5, i5, m5 = run(amg, p1, max_coarse=100)
+    assert np.array_equal(x5, x1) and all(same(a, b) for a, b in zip(m1, m5))
+    h.close()
 
 
 def test_fp32_form_after_fp64_frees(amg):
