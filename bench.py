@@ -179,6 +179,14 @@ def run_serving(args, amg, log):
                           iterations_mix=results[i][1]["iterations"], iterations_alone=ia["iterations"],
                           shared_rounds_with=results[i][2]["max_batch"] - 1))
     makespan = t_last - t_first
+    # where the latency goes: waiting for admission, setup, solve (rounds)
+    tl = [results[i][2] for i in range(len(reqs))]
+    phases = {}
+    for name, a, b in (("admission_wait", "t_arrival", "t_admit"), ("setup", "t_admit", "t_setup_done"),
+                       ("solve", "t_setup_done", "t_done")):
+        v = np.array([t[b] - t[a] for t in tl])
+        phases[name] = {"mean_s": float(v.mean()), "p50_s": float(np.percentile(v, 50)),
+                        "p99_s": float(np.percentile(v, 99))}
     out = {
         "requests": len(reqs), "rate_per_s": args.serve_rate, "budget_GiB": args.serve_budget_gib,
         "max_active": args.serve_active, "precision": "fp32-hierarchy", "tol": 1e-8, "max_iter": args.serve_max_iter,
@@ -192,6 +200,7 @@ def run_serving(args, amg, log):
         "launches": st["launches"], "peak_reserved_GiB": st["peak_reserved_bytes"] / 2**30,
         "estimate_exceeded": st["estimate_exceeded"], "failed": st["failed"],
         "submit_lateness_max_s": float(max(lateness)), "generation_s": t_gen, "replay_wall_s": t_wall,
+        "latency_phases": phases,
         "alone_vs_mix": alone,
     }
     log(f"serving: p50 {out['p50_latency_s']:.2f}s p99 {out['p99_latency_s']:.2f}s, "
