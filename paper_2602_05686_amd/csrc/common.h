@@ -190,12 +190,23 @@ struct DCsr {
     // span fewer than 2^16 values): col = cbase[b] + col16 within block b
     DBuf<uint16_t> col16;
     DBuf<int> cbase;
+    int cap = 2048;  // most stored entries in one streaming block (kStreamCap or kStreamCapWide)
+    // the setup kernels' row blocks (at most kStreamCap entries) when the
+    // streaming blocks above were widened; otherwise they share blk
+    DBuf<int> sblk;
+    int snblk = 0;
+    const int* setup_blk() const { return sblk ? sblk.get() : blk.get(); }
+    int setup_nblk() const { return sblk ? snblk : nblk; }
     // column bytes per stored entry the streaming kernels read
     double col_bytes() const { return col16 ? 2.0 : 4.0; }
 };
 
 constexpr int kBlock = 256;          // threads per block in streaming kernels
 constexpr int kStreamCap = 2048;     // nnz staged in LDS per streaming block
+// wider streaming blocks for large one-thread-per-row packed matrices: twice
+// the bytes per workgroup (the setup kernels keep kStreamCap blocks)
+constexpr int kStreamCapWide = 4096;
+constexpr int kWideBlockMin = 12000;  // widen a matrix with at least this many kStreamCap blocks
 constexpr int kMaxRowsPerBlock = kBlock;
 constexpr int kLongRow = 96;         // setup kernels: longer single-row blocks take the whole-block path
 constexpr int kWideRow = 32;         // streaming, one thread per row: wider rows are summed by 8 lanes of its wavefront

@@ -62,10 +62,13 @@ struct Hierarchy {
 // device scalar slots
 enum Scalar { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_RR = 3, S_BB = 4, S_TMP = 5, S_NSCAL = 8 };
 
+// wide_blocks: give large finest-level operators the wider streaming blocks
+// (the batched launches of the server take only kStreamCap blocks)
 std::unique_ptr<Hierarchy> build_hierarchy(int64_t n, const int* rowptr, const int* col, const double* val,
                                            int64_t nelem, int npe, const int* elem_nodes,
                                            const double* elem_sigma, const double* coords,
-                                           const amg_options& opt, bool host_ptrs, hipStream_t s);
+                                           const amg_options& opt, bool host_ptrs, hipStream_t s,
+                                           bool wide_blocks = true);
 
 // new values of A on the setup's pattern; masks, aggregates, coordinates and
 // tensors are kept, every value-dependent quantity is recomputed

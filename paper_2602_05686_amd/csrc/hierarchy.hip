@@ -35,19 +35,44 @@ double now_s() {
 // Row blocks of A for the streaming kernels, computed on the device, and
 // (if `pack`) the 16-bit packed columns.  MATAMG_CHECK_PARTITION=1 also runs
 // the host walk and fails on any difference (used by the tests).
-void make_blocks(DCsr& A, MemCounter* mc, hipStream_t s, bool pack = true) {
-    stream_partition(A, mc, s, pack);
+void make_blocks(DCsr& A, MemCounter* mc, hipStream_t s, bool pack = true, int cap = kStreamCap) {
+    stream_partition(A, mc, s, pack, cap);
     const char* chk = std::getenv("MATAMG_CHECK_PARTITION");
     if (chk && chk[0] == '1') {
         std::vector<int> rp((size_t)A.n + 1);
         d2h(rp.data(), A.rowptr.get(), rp.size(), s);
         const int group = stream_group(rp.data(), A.n);
-        std::vector<int> blk = stream_blocks(rp.data(), A.n, group);
+        std::vector<int> blk = stream_blocks(rp.data(), A.n, group, cap);
         std::vector<int> dev((size_t)A.nblk + 1);
         d2h(dev.data(), A.blk.get(), dev.size(), s);
         if (group != A.group || blk != dev)
             fail(AMG_ERR_HIP, "device row-block partition differs from the host walk (n=" + std::to_string(A.n) + ")");
     }
+}
+
+// Streaming blocks of up to kStreamCapWide entries for a large packed
+// one-thread-per-row matrix: twice the bytes per workgroup, which the finest
+// levels stream faster, while the setup kernels keep the kStreamCap blocks
+// (sblk).  Kept only if the wider blocks pack too.
+void widen_stream_blocks(DCsr& A, MemCounter* mc, hipStream_t s) {
+    if (A.group != 1 || !A.col16 || A.cap != kStreamCap || A.nblk < kWideBlockMin) return;
+    DBuf<int> blk = std::move(A.blk), blkk = std::move(A.blkk), cbase = std::move(A.cbase);
+    DBuf<uint16_t> col16 = std::move(A.col16);
+    const int nblk = A.nblk;
+    make_blocks(A, mc, s, true, kStreamCapWide);
+    if (A.col16 && A.group == 1) {
+        A.sblk = std::move(blk);
+        A.snblk = nblk;
+        return;
+    }
+    // not packable with wider blocks: back to the setup's partition
+    A.blk = std::move(blk);
+    A.blkk = std::move(blkk);
+    A.cbase = std::move(cbase);
+    A.col16 = std::move(col16);
+    A.nblk = nblk;
+    A.group = 1;
+    A.cap = kStreamCap;
 }
 
 // reduction partials: one slot per block of the widest fused-reduction launch
@@ -350,7 +375,8 @@ struct SetupAllocScope {
 std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const int* col, const double* val,
                                            int64_t nelem, int npe, const int* elem_nodes,
                                            const double* elem_sigma, const double* coords,
-                                           const amg_options& opt, bool host_ptrs, hipStream_t s) {
+                                           const amg_options& opt, bool host_ptrs, hipStream_t s,
+                                           bool wide_blocks) {
     const double t0 = now_s();
     SetupAllocScope scope(s);
     auto hp = std::make_unique<Hierarchy>();
@@ -520,6 +546,8 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
     }
     h.nlev = l + 1;
     ensure_partial(h, stream_partials(h.lev[0].A));
+    if (wide_blocks)
+        for (int k = 0; k < h.nlev; ++k) widen_stream_blocks(h.lev[k].A, mc, s);
 
     smoother_bounds(h, s);
     coarse_inverse(h, flag.get(), s);

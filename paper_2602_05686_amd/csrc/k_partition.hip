@@ -3,7 +3,8 @@
 //
 // The partition is the greedy one: walking the rows in order, a block takes
 // rows while it holds fewer than max_block_rows(G) rows and its stored
-// entries stay within kStreamCap; a row longer than long_row_limit(G) forms a
+// entries stay within the cap (kStreamCap, or kStreamCapWide); a row longer
+// than long_row_limit(G) forms a
 // block of its own.  The walk is sequential, but the block that starts at row r ends at a
 // row next(r) that depends on r alone, so every next(r) is computed in
 // parallel (binary searches over the row pointer and the list of long rows)
@@ -75,7 +76,8 @@ __global__ void k_long_list(int n, const int* flags, const int* pos, int* list) 
 }
 
 // end (exclusive) of the block that starts at row r; next[n] = n
-__global__ void k_block_next(int n, const int* rp, const int* par, const int* longs, const int* nlong, int* next) {
+__global__ void k_block_next(int n, const int* rp, const int* par, const int* longs, const int* nlong, int bcap,
+                             int* next) {
     const int nl = *nlong;
     const int limit = par[2], max_rows = par[3];
     FOR_ROWS(r64, (int64_t)n + 1) {
@@ -89,8 +91,8 @@ __global__ void k_block_next(int n, const int* rp, const int* par, const int* lo
             continue;
         }
         int e = min(n, r + max_rows);
-        // largest j in (r, e] with rp[j] - rp[r] <= kStreamCap (j = r + 1 always qualifies)
-        const int cap = rp[r] + kStreamCap;
+        // largest j in (r, e] with rp[j] - rp[r] <= bcap (j = r + 1 always qualifies)
+        const int cap = rp[r] + bcap;
         int lo = r + 1, hi = e;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -194,10 +196,13 @@ __global__ void k_block_entries(int nblk, const int* rp, const int* blk, int* bl
 
 }  // namespace
 
-void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack) {
+void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack, int cap) {
     const int n = A.n;
     A.col16.release();
     A.cbase.release();
+    A.sblk.release();
+    A.snblk = 0;
+    A.cap = cap;
     if (n <= 0) {
         A.group = 1;
         A.nblk = 0;
@@ -224,7 +229,7 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack) {
     hipLaunchKernelGGL(k_long_list, dim3(grid1(n)), dim3(kBlock), 0, s, n, flags.get(), pos.get(), longs.get());
     DBuf<int> ja(n1, mc), jb(n1, mc);
     hipLaunchKernelGGL(k_block_next, dim3(grid1(n1)), dim3(kBlock), 0, s, n, rp, (const int*)par.get(), longs.get(),
-                       pos.get() + n, ja.get());
+                       pos.get() + n, cap, ja.get());
     MATAMG_LAUNCH_CHECK();
     // pointer doubling from row 0 (flags reused as the start marks)
     hipLaunchKernelGGL(k_mark_init, dim3(grid1(n1)), dim3(kBlock), 0, s, n, flags.get());

@@ -880,17 +880,17 @@ void tensor_inverse(int n, int dim, const double* sig, double* minv, int* flag, 
 
 void soc_values(const DCsr& A, int dim, const double* x, const double* minv, const uint8_t* dir, int soc,
                 double* lval, double* ldiag, hipStream_t s) {
-    if (A.nblk <= 0) return;
-    SocArgs a{A.rowptr.get(), A.col.get(), A.val.get(), A.blk.get(), A.nblk, dim, soc, x, minv, dir, lval, ldiag};
-    hipLaunchKernelGGL(k_soc_values, dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a);
+    if (A.setup_nblk() <= 0) return;
+    SocArgs a{A.rowptr.get(), A.col.get(), A.val.get(), A.setup_blk(), A.setup_nblk(), dim, soc, x, minv, dir, lval, ldiag};
+    hipLaunchKernelGGL(k_soc_values, dim3(xcd_grid(A.setup_nblk())), dim3(kBlock), 0, s, a);
     MATAMG_LAUNCH_CHECK();
 }
 
 void soc_mask(const DCsr& A, const uint8_t* dir, const double* lval, const double* ldiag, double theta, double* S,
               uint8_t* mask, hipStream_t s) {
-    if (A.nblk <= 0) return;
-    MaskArgs a{A.rowptr.get(), A.col.get(), A.blk.get(), A.nblk, dir, lval, ldiag, theta * theta, S, mask};
-    hipLaunchKernelGGL(k_soc_mask, dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a);
+    if (A.setup_nblk() <= 0) return;
+    MaskArgs a{A.rowptr.get(), A.col.get(), A.setup_blk(), A.setup_nblk(), dir, lval, ldiag, theta * theta, S, mask};
+    hipLaunchKernelGGL(k_soc_mask, dim3(xcd_grid(A.setup_nblk())), dim3(kBlock), 0, s, a);
     MATAMG_LAUNCH_CHECK();
 }
 
@@ -908,12 +908,12 @@ void mis_init(int n, const uint8_t* dir, uint8_t* state, hipStream_t s) { LAUNCH
 void mis_round(const DCsr& A, const uint8_t* mask, uint64_t key, uint8_t* state, uint64_t* t1, uint64_t* t2,
                int* undecided, hipStream_t s) {
     const int n = A.n;
-    if (A.nblk > 0) {
-        hipLaunchKernelGGL((k_mis_hop<true>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, A.rowptr.get(),
-                           A.col.get(), mask, A.blk.get(), A.nblk, key, (const uint8_t*)state, (const uint64_t*)nullptr,
+    if (A.setup_nblk() > 0) {
+        hipLaunchKernelGGL((k_mis_hop<true>), dim3(xcd_grid(A.setup_nblk())), dim3(kBlock), 0, s, A.rowptr.get(),
+                           A.col.get(), mask, A.setup_blk(), A.setup_nblk(), key, (const uint8_t*)state, (const uint64_t*)nullptr,
                            t1);
-        hipLaunchKernelGGL((k_mis_hop<false>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, A.rowptr.get(),
-                           A.col.get(), mask, A.blk.get(), A.nblk, key, (const uint8_t*)state, (const uint64_t*)t1,
+        hipLaunchKernelGGL((k_mis_hop<false>), dim3(xcd_grid(A.setup_nblk())), dim3(kBlock), 0, s, A.rowptr.get(),
+                           A.col.get(), mask, A.setup_blk(), A.setup_nblk(), key, (const uint8_t*)state, (const uint64_t*)t1,
                            t2);
         MATAMG_LAUNCH_CHECK();
     }
@@ -939,17 +939,17 @@ void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, c
 }
 
 void filter_count(const DCsr& A, const uint8_t* mask, int* cnt, hipStream_t s) {
-    if (A.nblk <= 0) return;
-    hipLaunchKernelGGL(k_filter_count, dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, A.rowptr.get(), A.col.get(), mask,
-                       A.blk.get(), A.nblk, cnt);
+    if (A.setup_nblk() <= 0) return;
+    hipLaunchKernelGGL(k_filter_count, dim3(xcd_grid(A.setup_nblk())), dim3(kBlock), 0, s, A.rowptr.get(), A.col.get(), mask,
+                       A.setup_blk(), A.setup_nblk(), cnt);
     MATAMG_LAUNCH_CHECK();
 }
 
 void filter_fill(const DCsr& A, const uint8_t* mask, const int* frowptr, int* fcol, double* fval, double* dt,
                  double* dtinv, hipStream_t s) {
-    if (A.nblk <= 0) return;
-    hipLaunchKernelGGL(k_filter_fill, dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, A.rowptr.get(), A.col.get(),
-                       A.val.get(), mask, A.blk.get(), A.nblk, frowptr, fcol, fval, dt, dtinv);
+    if (A.setup_nblk() <= 0) return;
+    hipLaunchKernelGGL(k_filter_fill, dim3(xcd_grid(A.setup_nblk())), dim3(kBlock), 0, s, A.rowptr.get(), A.col.get(),
+                       A.val.get(), mask, A.setup_blk(), A.setup_nblk(), frowptr, fcol, fval, dt, dtinv);
     MATAMG_LAUNCH_CHECK();
 }
 
@@ -970,9 +970,9 @@ void coarse_aux(int nc, int dim, const Incidence& m, const double* x, const doub
 }
 
 void diag_inverse_blocks(const DCsr& A, double* dinv, hipStream_t s) {
-    if (A.nblk <= 0) return;
-    hipLaunchKernelGGL(k_diag_inverse_blocks, dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, A.rowptr.get(),
-                       A.col.get(), A.val.get(), A.blk.get(), A.nblk, dinv);
+    if (A.setup_nblk() <= 0) return;
+    hipLaunchKernelGGL(k_diag_inverse_blocks, dim3(xcd_grid(A.setup_nblk())), dim3(kBlock), 0, s, A.rowptr.get(),
+                       A.col.get(), A.val.get(), A.setup_blk(), A.setup_nblk(), dinv);
     MATAMG_LAUNCH_CHECK();
 }
 

@@ -213,7 +213,7 @@ int stream_group(const int* rp, int n) {
     return stream_group_rule(max_len, wide, n > 0 ? rp[n] : 0);
 }
 
-std::vector<int> stream_blocks(const int* rp, int n, int group) {
+std::vector<int> stream_blocks(const int* rp, int n, int group, int cap) {
     const int max_rows = max_block_rows(group);
     const int long_len = long_row_limit(group);
     std::vector<int> blk;
@@ -229,7 +229,7 @@ std::vector<int> stream_blocks(const int* rp, int n, int group) {
             rows = 0;
             continue;
         }
-        if (rows > 0 && (cur + len > kStreamCap || rows == max_rows)) {
+        if (rows > 0 && (cur + len > cap || rows == max_rows)) {
             blk.push_back(r);
             cur = 0;
             rows = 0;
@@ -242,18 +242,21 @@ std::vector<int> stream_blocks(const int* rp, int n, int group) {
 }
 
 namespace {
-template <typename T, int MODE, bool HAS_DOT, int G>
+template <typename T, int MODE, bool HAS_DOT, int G, int CAP = kStreamCap>
 __global__ __launch_bounds__(kBlock) void k_stream(SArgs<T> a, int nblk) {
-    __shared__ StreamShared<T> S;
+    __shared__ StreamShared<T, CAP> S;
     const int bid = xcd_block(nblk);
     if (bid >= nblk) return;
-    stream_block<T, MODE, HAS_DOT, G>(a, bid, S);
+    stream_block<T, MODE, HAS_DOT, G, CAP>(a, bid, S);
 }
 
 template <typename T, int MODE, bool HAS_DOT>
 void launch_stream(const DCsr& A, const SArgs<T>& a, hipStream_t s) {
     if (A.nblk <= 0) return;
-    if (A.group == 1)
+    if (A.group == 1 && A.cap == kStreamCapWide)
+        hipLaunchKernelGGL((k_stream<T, MODE, HAS_DOT, 1, kStreamCapWide>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s,
+                           a, A.nblk);
+    else if (A.group == 1)
         hipLaunchKernelGGL((k_stream<T, MODE, HAS_DOT, 1>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a, A.nblk);
     else
         hipLaunchKernelGGL((k_stream<T, MODE, HAS_DOT, 8>), dim3(xcd_grid(A.nblk)), dim3(kBlock), 0, s, a, A.nblk);

@@ -21,7 +21,7 @@ void dot(const T* a, const T* b, int64_t n, double* partial, unsigned* counter, 
 
 // --------------------------------------------------------------- streaming ---
 // row blocks for the streaming CSR kernels, computed from a host row pointer
-std::vector<int> stream_blocks(const int* rowptr_host, int n, int group);
+std::vector<int> stream_blocks(const int* rowptr_host, int n, int group, int cap = kStreamCap);
 // threads per row for a matrix (host row pointer): stream_group_rule
 int stream_group(const int* rowptr_host, int n);
 // A.group, A.nblk and A.blk from A's device row pointer (the same greedy
@@ -29,7 +29,8 @@ int stream_group(const int* rowptr_host, int n);
 // A.col16 and A.cbase when every block's columns span fewer than 2^16
 // values (otherwise both stay empty); reads back the block count, so s is
 // synchronised once
-void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack);
+// (blocks of at most `cap` stored entries; A.cap records it)
+void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack, int cap = kStreamCap);
 
 // dot partials of a streaming launch: one per row block
 constexpr int kStreamPartials = 1;  // dot partials per streaming block

@@ -63,6 +63,9 @@ struct LV<float> {
 
 template <typename T>
 SArgs<T> sargs(const DCsr& M, const T* val, const T* x) {
+    // the batched streaming kernels stage kStreamCap entries per block; the
+    // server's hierarchies keep that partition
+    if (M.cap != kStreamCap) fail(AMG_ERR_HIP, "served matrix has widened streaming blocks");
     SArgs<T> a{};
     a.rowptr = M.rowptr.get();
     a.col = M.col.get();
@@ -431,7 +434,7 @@ void Server::worker_main() {
             std::string msg;
             try {
                 h = build_hierarchy(R->n, R->rowptr.data(), R->col.data(), R->val.data(), R->nelem, R->npe,
-                                    R->elem_nodes.data(), R->elem_sigma.data(), R->coords.data(), opt_, true, s);
+                                    R->elem_nodes.data(), R->elem_sigma.data(), R->coords.data(), opt_, true, s, false);
                 h->release_setup_data();
                 MATAMG_HIP(hipStreamSynchronize(s));
             } catch (const Error& e) {

@@ -114,10 +114,10 @@ __device__ __forceinline__ double epilogue(const SArgs<T>& a, int r, T s, const 
 
 constexpr int kPerThread = kStreamCap / kBlock;
 
-// LDS of one streaming block
-template <typename T>
+// LDS of one streaming block of at most CAP stored entries
+template <typename T, int CAP = kStreamCap>
 struct StreamShared {
-    T prod[kStreamCap];
+    T prod[CAP];
     double sh[kBlock / 64];
     T shr[kBlock / 64];
 };
@@ -239,8 +239,8 @@ __device__ __forceinline__ T ordered_sum(const T* prod, int k0, int k1, T s) {
 // block's end are clamped to its last entry (or row) and the results are
 // discarded, so the compiler issues all of them back to back with no
 // branch, and no wait, between them.
-template <typename T, int MODE, bool HAS_DOT, int G>
-__device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamShared<T>& S) {
+template <typename T, int MODE, bool HAS_DOT, int G, int CAP = kStreamCap>
+__device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamShared<T, CAP>& S) {
     // rows and entries of the block from the two tables: the loads of the
     // entries do not wait for the row pointer
     const int r0 = a.blk[bid], r1 = a.blk[bid + 1];
@@ -268,9 +268,20 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
                 case 2: stage_pairs<T, 2>(a, bid, k0, cnt, S.prod); break;
                 case 3: stage_pairs<T, 3>(a, bid, k0, cnt, S.prod); break;
                 case 4: stage_pairs<T, 4>(a, bid, k0, cnt, S.prod); break;
-                default: break;
+                default:
+                    if constexpr (CAP > kStreamCap) {
+                        switch (((cnt - stage_head(k0, cnt)) / 2 + kBlock - 1) / kBlock) {
+                            case 5: stage_pairs<T, 5>(a, bid, k0, cnt, S.prod); break;
+                            case 6: stage_pairs<T, 6>(a, bid, k0, cnt, S.prod); break;
+                            case 7: stage_pairs<T, 7>(a, bid, k0, cnt, S.prod); break;
+                            case 8: stage_pairs<T, 8>(a, bid, k0, cnt, S.prod); break;
+                            default: break;
+                        }
+                    }
+                    break;
             }
-        } else {
+        } else if constexpr (CAP == kStreamCap) {
+            // (wide blocks are only made for packed matrices)
             switch (nu) {
                 case 1: stage_products<T, 1, false>(a, bid, k0, cnt, S.prod); break;
                 case 2: stage_products<T, 2, false>(a, bid, k0, cnt, S.prod); break;
