@@ -181,3 +181,31 @@ def test_layered192_finest_level_and_fp32_solve(amg):
           f"{i64['rel_res']:.2e} error vs exact {err64:.2e} solve {i64['t_solve_s'] * 1e3:.0f} ms; "
           f"fp32-hierarchy vs fp64 form {d:.2e}")
     assert i64["status"] in ("OK", "NOT_CONVERGED") and i64["rel_res"] <= 1e-6
+
+
+def test_layered128_wide_blocks_update_and_partition(amg, layered128, monkeypatch):
+    """At the bench size the two finest operators stream 4096-entry blocks
+    while the setup kernels keep 2048-entry ones: the device partitions
+    agree with the host walk, and a value update (setup kernels on the kept
+    blocks) still gives bit for bit a fresh setup of the scaled problem."""
+    import dataclasses
+
+    monkeypatch.setenv("MATAMG_CHECK_PARTITION", "1")
+    prob = layered128
+    p4 = dataclasses.replace(prob, val=prob.val * 4.0, b=prob.b * 4.0, elem_sigma=prob.elem_sigma * 4.0)
+    banner("layered128: wide blocks, update vs fresh")
+    h = amg.Hierarchy.from_problem(prob)
+    h.update_values(p4.val)
+    f = amg.Hierarchy.from_problem(p4)
+    sh, sf = h.stats(), f.stats()
+    assert sh["levels"] == sf["levels"]
+    assert sh["omega"] == sf["omega"] and sh["lam_cheb"] == sf["lam_cheb"]
+    for l in range(sh["levels"]):
+        a, b = h.level_csr(l, "A"), f.level_csr(l, "A")
+        assert all(np.array_equal(u, v) for u, v in zip(a, b)), l
+    xh, ih = h.solve(p4.b)
+    xf, if_ = f.solve(p4.b)
+    assert ih["iterations"] == if_["iterations"] and np.array_equal(xh, xf)
+    assert ih["rel_res"] <= 1e-8
+    h.close()
+    f.close()
