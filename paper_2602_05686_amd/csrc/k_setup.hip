@@ -561,14 +561,12 @@ __global__ void k_agg_phase2(int n, const int* rowptr, const int* col, const uin
     }
 }
 
-// remaining nodes join the phase-2 aggregate with the most kept neighbours,
-// ties to the smallest aggregate id
 // Phase 3: a node left unassigned by phase 2 joins the phase-2 aggregate
 // that holds most of its kept neighbours (ties: smallest aggregate id).
 // The first kernel settles every other node and lists the unassigned ones;
-// the second gives each listed node a wavefront: lanes take the row's
-// candidates, count each candidate's occurrences over the whole row, and a
-// lane reduction picks (largest count, smallest id).  The outcome of a node
+// the second gives each listed node a wavefront, which visits the distinct
+// aggregates among the row's kept neighbours, counts each with ballots and
+// keeps (largest count, smallest id).  The outcome of a node
 // depends only on phase 2, so the list order does not matter.
 __global__ void k_agg_phase3_split(int n, const uint8_t* dir, const int* phase2, int* agg, int* list, int* nlist) {
     ROW_LOOP(i, n) {
@@ -592,38 +590,40 @@ __global__ __launch_bounds__(kBlock) void k_agg_phase3_rows(const int* rowptr, c
     const int lane = threadIdx.x & 63;
     const int waves = (int)(gridDim.x * blockDim.x) >> 6;
     const int nl = *nlist;
-    for (int w = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); w < nl; w += waves) {
-        const int i = list[w];
-        const int lo = rowptr[i], hi = rowptr[i + 1];
+    // the row and its bounds are the same in every lane; reading them through
+    // the first lane keeps every loop below wave-uniform
+    for (int w = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6)); w < nl;
+         w += waves) {
+        const int i = __builtin_amdgcn_readfirstlane(list[w]);
+        const int lo = __builtin_amdgcn_readfirstlane(rowptr[i]), hi = __builtin_amdgcn_readfirstlane(rowptr[i + 1]);
+        const bool one_chunk = hi - lo <= 64;
         int bestc = -1, bestn = 0;
         for (int k0 = lo; k0 < hi; k0 += 64) {
             const int c = phase3_candidate(col, mask, phase2, i, k0 + lane, hi);
-            int cnt = 0;
-            for (int k1 = lo; k1 < hi; k1 += 64) {
-                const int c2 = phase3_candidate(col, mask, phase2, i, k1 + lane, hi);
-                for (int q = 0; q < 64; ++q) {
-                    const int cq = __shfl(c2, q, 64);  // every lane takes part in the shuffle
-                    cnt += (c >= 0 && cq == c) ? 1 : 0;
+            // visit each distinct candidate of this chunk once: take the lowest
+            // lane still pending, count its aggregate over the whole row with
+            // ballots, then retire every lane that holds the same aggregate
+            uint64_t pending = __ballot(c >= 0);
+            while (pending) {
+                const int v = __builtin_amdgcn_readlane(c, __builtin_ctzll(pending));
+                const uint64_t same = __ballot(c == v);
+                int cnt = __popcll(same);
+                if (!one_chunk) {
+                    cnt = 0;
+                    for (int k1 = lo; k1 < hi; k1 += 64)
+                        cnt += __popcll(__ballot(phase3_candidate(col, mask, phase2, i, k1 + lane, hi) == v));
                 }
-            }
-            if (c >= 0 && (cnt > bestn || (cnt == bestn && c < bestc))) {
-                bestn = cnt;
-                bestc = c;
-            }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const int on = __shfl_xor(bestn, off, 64);
-            const int oc = __shfl_xor(bestc, off, 64);
-            if (on > bestn || (on == bestn && on > 0 && oc < bestc)) {
-                bestn = on;
-                bestc = oc;
+                pending &= ~same;
+                if (cnt > bestn || (cnt == bestn && v < bestc)) {
+                    bestn = cnt;
+                    bestc = v;
+                }
             }
         }
         if (lane == 0) agg[i] = bestc;
     }
 }
 
-// ------------------------------------------------------------- prolongator
 // ------------------------------------------------------------- prolongator
 __global__ __launch_bounds__(kBlock) void k_filter_count(const int* rowptr, const int* col, const uint8_t* mask,
                                                          const int* blk, int nblk, int* cnt) {
@@ -803,14 +803,17 @@ __global__ void k_densify(int n, const int* rowptr, const int* col, const double
     }
 }
 
+// eight lanes per row, so neighbouring lanes read neighbouring entries
 __global__ void k_validate_csr(int n, const int* rowptr, const int* col, int64_t nnz, int* flag) {
-    ROW_LOOP(i, n) {
+    const int sub = threadIdx.x & 7;
+    const int64_t groups = (int64_t)gridDim.x * (kBlock / 8);
+    for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 3; i < n; i += groups) {
         const int lo = rowptr[i], hi = rowptr[i + 1];
         if (lo < 0 || hi < lo || hi > nnz) {
             *flag = 1;
             continue;
         }
-        for (int k = lo; k < hi; ++k) {
+        for (int k = lo + sub; k < hi; k += 8) {
             const int c = col[k];
             if (c < 0 || c >= n || (k > lo && c <= col[k - 1])) {
                 *flag = 1;
@@ -989,7 +992,7 @@ void densify(int n, const int* rowptr, const int* col, const double* val, double
 }
 
 void validate_csr(int n, const int* rowptr, const int* col, int64_t nnz, int* flag, hipStream_t s) {
-    LAUNCH(k_validate_csr, n, n, rowptr, col, nnz, flag);
+    LAUNCH(k_validate_csr, (int64_t)n * 8, n, rowptr, col, nnz, flag);
 }
 
 }  // namespace matamg
