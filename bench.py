@@ -10,7 +10,8 @@ One step = the whole hot path on inputs already resident in HBM:
 amg_setup (Clement tensors, strength, aggregation, prolongators, Galerkin
 products, coarse factorisation) followed by amg_pcg_solve to a true relative
 residual of 1e-8.  value = DOF * steps / time.  The JSON line also carries
-solve-only throughput, the FP32-hierarchy form against the FP64 form, the
+solve-only throughput, the FP32-hierarchy form against the FP64 form (on
+this stack and on the 96^3 rotated-anisotropy cube, `fp32_form.aniso`), the
 V-cycle's algorithmic HBM bandwidth, the roofline of the dominant kernel
 (the finest level's fused Chebyshev SpMV: back-to-back launches between
 HIP events on its stream), the serving stream (256 requests at 20/s,
@@ -438,6 +439,47 @@ def run_reuse(args, amg, log):
             "op_complexity_fresh": st_f["op_complexity"], "rhs_solves": solves, "amortised": amort}
 
 
+def run_fp32_aniso(args, amg, dev, log):
+    """FP32-hierarchy form against the FP64 form on the rotated-anisotropy
+    cube (n^3 hexes, 8^3-element blocks, f ~ U(-1, 1)): the same right-hand
+    side from x0 = 0, several timed solves per form on one hierarchy each."""
+    import torch
+
+    from workloads import rotated_anisotropic_3d
+
+    log(f"generating rotated-anisotropy cube {args.aniso_n}^3")
+    prob = rotated_anisotropic_3d(n=args.aniso_n, block=8)
+    d = [torch.from_numpy(a).to(dev) for a in (prob.rowptr, prob.col, prob.val, prob.elem_nodes, prob.elem_sigma,
+                                                prob.coords)]
+    b = torch.from_numpy(prob.b).to(dev)
+    x = torch.zeros(prob.n, dtype=torch.float64, device=dev)
+    out = dict(workload=f"rotated anisotropy {args.aniso_n}^3, 8^3 blocks, eps 1e-3, isotropic fill 1e-4",
+               n=prob.n, nnz=prob.nnz)
+    sol = {}
+    for name, prec in (("fp64", "fp64"), ("fp32", "fp32")):
+        opts = amg.options(dim=3, precision=prec, max_levels=args.max_levels)
+        torch.cuda.synchronize()
+        h = amg.Hierarchy(*d, opts)
+        t_setup = h.stats()["t_setup_s"]
+        ts = []
+        for _ in range(max(1, args.fp32_reps)):
+            x.zero_()
+            _, info = h.solve(b, x, max_iter=args.max_iter)
+            ts.append(1e3 * info["t_solve_s"])
+        sol[name] = x.cpu().numpy()
+        h.close()
+        out[name] = dict(t_setup_ms=1e3 * t_setup, t_solve_ms_stats=stats_ms(np.array(ts)),
+                         iterations=info["iterations"], rel_res=info["rel_res"], status=info["status"])
+    m64, m32 = out["fp64"]["t_solve_ms_stats"]["median"], out["fp32"]["t_solve_ms_stats"]["median"]
+    out["speedup_vs_fp64_solve"] = m64 / m32
+    out["speedup_per_iteration"] = (m64 / max(1, out["fp64"]["iterations"])) / (m32 / max(1, out["fp32"]["iterations"]))
+    out["rel_err_vs_fp64_form"] = float(np.linalg.norm(sol["fp32"] - sol["fp64"]) / np.linalg.norm(sol["fp64"]))
+    log(f"aniso {args.aniso_n}^3: fp32 {m32:.1f} ms ({out['fp32']['iterations']} it) vs fp64 {m64:.1f} ms "
+        f"({out['fp64']['iterations']} it): {out['speedup_vs_fp64_solve']:.2f}x, "
+        f"rel err {out['rel_err_vs_fp64_form']:.1e}")
+    return out
+
+
 def stats_ms(v):
     """mean, standard deviation, median, min and max of a list of times (ms)"""
     v = np.asarray(v, dtype=float)
@@ -462,6 +504,8 @@ def main():
     ap.add_argument("--profile-kernels", action="store_true",
                     help="one setup, a few V-cycles and a 1 GiB device copy (for counter collection), no JSON")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--aniso-n", type=int, default=96,
+                    help="hexes per side of the rotated-anisotropy FP32/FP64 comparison (0: skip)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream (its JSON object)")
     ap.add_argument("--compare", action="store_true",
@@ -649,6 +693,8 @@ def main():
                 f"iterations {fp32['x0_seeds']['fp32_iterations']} vs {fp32['x0_seeds']['fp64_iterations']}")
         log(f"fp32 form: solve {t32m * 1e3:.1f} ms (mean of {len(t32)}), iters {info32['iterations']}")
     h.close()
+    if fp32 is not None and args.aniso_n > 0:
+        fp32["aniso"] = run_fp32_aniso(args, amg, dev, log)
 
     serving = None
     if not args.no_serving:
