@@ -61,7 +61,23 @@ typedef enum {
  * with theta * s_k >= s_{k+1}; kept where both rows keep the entry) */
 typedef enum { AMG_DROP_POINTWISE = 0, AMG_DROP_CUT = 1 } amg_drop;
 typedef enum { AMG_PREC_FP64 = 0, AMG_PREC_FP32_HIER = 1 } amg_precision;
-typedef enum { AMG_SMOOTH_CHEBYSHEV = 0, AMG_SMOOTH_JACOBI = 1 } amg_smoother;
+/* smoother (solver settings of the numerical section; Chebyshev is the
+ * paper's):
+ *   CHEBYSHEV      Jacobi-preconditioned Chebyshev of degree cheb_degree on
+ *                  [beta/cheb_ratio, beta], beta = cheb_boost * lambda, with
+ *                  lambda the level's power-method estimate of rho(D^{-1}A)
+ *   JACOBI         jacobi_sweeps sweeps of x <- x + w D^{-1}(b - A x) with
+ *                  the fixed weight w = jacobi_omega.  The V-cycle is
+ *                  symmetric positive definite only if w rho(D^{-1}A) < 2 on
+ *                  every level; 3D Q1 operators (stretched, layered or
+ *                  rotated) reach rho(D^{-1}A) of 3-4.5, where w = 2/3 breaks
+ *                  this and CG may stall or fail
+ *   JACOBI_SCALED  the same sweeps with w_l = jacobi_omega * 2 / beta_l per
+ *                  level (beta_l as for Chebyshev): w_l = jacobi_omega where
+ *                  beta_l = 2 (the five-point Laplacian, for which 2/3 is the
+ *                  classical weight), and w_l beta_l = 2 jacobi_omega < 2
+ *                  keeps the V-cycle positive definite for jacobi_omega < 1 */
+typedef enum { AMG_SMOOTH_CHEBYSHEV = 0, AMG_SMOOTH_JACOBI = 1, AMG_SMOOTH_JACOBI_SCALED = 2 } amg_smoother;
 
 /* Setup and solve options.  Defaults (amg_options_default) follow the
  * numerical section: pointwise dropping, 2nd-order Chebyshev smoothing,
@@ -79,7 +95,7 @@ typedef struct {
     double cheb_boost;      /* lambda = boost * power-method estimate (1.1) */
     int32_t power_iters;    /* power-method steps for omega and Chebyshev (10) */
     double omega_sym;       /* prolongator damping numerator (4/3) */
-    double jacobi_omega;    /* damped-Jacobi weight (2/3) */
+    double jacobi_omega;    /* damped-Jacobi weight, > 0 (2/3) */
     int32_t jacobi_sweeps;  /* damped-Jacobi sweeps per smoothing (2) */
     int32_t precision;      /* amg_precision */
     uint64_t seed;          /* aggregation priorities and power-method starts */

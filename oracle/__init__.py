@@ -22,7 +22,7 @@ _lib = None
 OK, INVALID_ARG, OUT_OF_MEMORY, NOT_SPD, STAGNATED, NOT_CONVERGED, BREAKDOWN = 0, 1, 2, 4, 5, 6, 7
 SOC = {"material": 0, "distance": 1, "sa": 2}
 DROP = {"pointwise": 0, "cut": 1}
-SMOOTHER = {"chebyshev": 0, "jacobi": 1}
+SMOOTHER = {"chebyshev": 0, "jacobi": 1, "jacobi_scaled": 2}
 
 
 class OracleError(RuntimeError):

@@ -34,7 +34,7 @@ enum {
 
 enum { SOC_MATERIAL = 0, SOC_DISTANCE = 1, SOC_SA = 2 };
 enum { DROP_POINTWISE = 0, DROP_CUT = 1 };
-enum { SMOOTH_CHEBYSHEV = 0, SMOOTH_JACOBI = 1 };
+enum { SMOOTH_CHEBYSHEV = 0, SMOOTH_JACOBI = 1, SMOOTH_JACOBI_SCALED = 2 };
 
 typedef struct {
     int32_t dim;
@@ -1121,24 +1121,32 @@ static void chebyshev(const Level *L, const OrcOptions *opt, const double *b, do
     }
 }
 
-/* damped Jacobi sweeps x += omega D^{-1} (b - A x) */
+/*
+ * Damped Jacobi sweeps x += w D^{-1} (b - A x), D the diagonal of A.  The
+ * weight is jacobi_omega, or (scaled option) jacobi_omega * 2 / beta with
+ * beta = cheb_boost * lambda the upper end of the Chebyshev interval, so that
+ * w * beta = 2 * jacobi_omega whatever the level's spectrum.
+ */
 static void jacobi(const Level *L, const OrcOptions *opt, const double *b, double *x, int zero_init, double *r)
 {
     int n = L->A.n;
+    double beta = opt->cheb_boost * L->lam_cheb;
+    double w = opt->jacobi_omega;
+    if (opt->smoother == SMOOTH_JACOBI_SCALED && beta > 0.0) w = opt->jacobi_omega * 2.0 / beta;
     for (int s = 0; s < opt->jacobi_sweeps; ++s) {
         if (zero_init && s == 0) {
-            for (int i = 0; i < n; ++i) x[i] = opt->jacobi_omega * (L->dinv[i] * b[i]);
+            for (int i = 0; i < n; ++i) x[i] = w * (L->dinv[i] * b[i]);
             continue;
         }
         spmv(&L->A, x, r);
-        for (int i = 0; i < n; ++i) x[i] = x[i] + opt->jacobi_omega * (L->dinv[i] * (b[i] - r[i]));
+        for (int i = 0; i < n; ++i) x[i] = x[i] + w * (L->dinv[i] * (b[i] - r[i]));
     }
 }
 
 static void smooth(const Level *L, const OrcOptions *opt, const double *b, double *x, int zero_init, double *r,
                    double *d)
 {
-    if (opt->smoother == SMOOTH_JACOBI) jacobi(L, opt, b, x, zero_init, r);
+    if (opt->smoother == SMOOTH_JACOBI || opt->smoother == SMOOTH_JACOBI_SCALED) jacobi(L, opt, b, x, zero_init, r);
     else chebyshev(L, opt, b, x, zero_init, r, d);
 }
 

@@ -22,7 +22,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP", 4: "NOT_SPD",
           6: "NOT_CONVERGED", 7: "BREAKDOWN", 8: "BUDGET"}
 PTR_HOST, PTR_DEVICE = 0, 1
 SOC = {"material": 0, "distance": 1, "sa": 2}
-SMOOTHER = {"chebyshev": 0, "jacobi": 1}
+SMOOTHER = {"chebyshev": 0, "jacobi": 1, "jacobi_scaled": 2}
 PRECISION = {"fp64": 0, "fp32": 1}
 DROP = {"pointwise": 0, "cut": 1}
 

@@ -1,4 +1,5 @@
 // extern "C" boundary: argument checks, error translation, data accessors.
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -213,8 +214,10 @@ amg_status check_options(const amg_options& o) {
     if (!(o.theta >= 0.0 && o.theta <= 1.0)) fail(AMG_ERR_INVALID_ARG, "theta must lie in [0, 1]");
     if (o.soc < AMG_SOC_MATERIAL || o.soc > AMG_SOC_SA) fail(AMG_ERR_INVALID_ARG, "unknown strength measure");
     if (o.drop != AMG_DROP_POINTWISE && o.drop != AMG_DROP_CUT) fail(AMG_ERR_INVALID_ARG, "unknown dropping criterion");
-    if (o.smoother != AMG_SMOOTH_CHEBYSHEV && o.smoother != AMG_SMOOTH_JACOBI)
+    if (o.smoother != AMG_SMOOTH_CHEBYSHEV && o.smoother != AMG_SMOOTH_JACOBI && o.smoother != AMG_SMOOTH_JACOBI_SCALED)
         fail(AMG_ERR_INVALID_ARG, "unknown smoother");
+    if (!(o.jacobi_omega > 0.0) || !std::isfinite(o.jacobi_omega))
+        fail(AMG_ERR_INVALID_ARG, "jacobi_omega must be positive and finite");
     if (o.max_coarse < 1) fail(AMG_ERR_INVALID_ARG, "max_coarse must be positive");
     if (o.max_coarse > 20000) fail(AMG_ERR_INVALID_ARG, "max_coarse above 20000 (dense coarse solve)");
     if (o.max_levels < 1 || o.max_levels > 16) fail(AMG_ERR_INVALID_ARG, "max_levels must lie in [1, 16]");

@@ -106,10 +106,15 @@ double power_method(const DCsr& A, const double* dscale, int iters, uint64_t key
 void smoother_coefficients(Level& L, const amg_options& o) {
     L.c1.clear();
     L.c2.clear();
-    if (o.smoother == AMG_SMOOTH_JACOBI) {
+    if (o.smoother == AMG_SMOOTH_JACOBI || o.smoother == AMG_SMOOTH_JACOBI_SCALED) {
+        // fixed weight, or jacobi_omega * 2 / beta with beta the Chebyshev
+        // upper bound of the level's spectrum
+        const double beta = o.cheb_boost * L.lam_cheb;
+        const double w = (o.smoother == AMG_SMOOTH_JACOBI_SCALED && beta > 0.0) ? o.jacobi_omega * 2.0 / beta
+                                                                                 : o.jacobi_omega;
         for (int k = 0; k < o.jacobi_sweeps; ++k) {
             L.c1.push_back(0.0);
-            L.c2.push_back(o.jacobi_omega);
+            L.c2.push_back(w);
         }
         return;
     }

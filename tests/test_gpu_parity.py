@@ -294,3 +294,68 @@ def test_strength_modes_match_oracle(amg, name, soc, drop):
     assert info["status"] == "OK"
     assert abs(info["iterations"] - io["iterations"]) <= 1
     assert err <= 1e-6
+
+
+# damped-Jacobi smoothing: the fixed weight 2/3 on the cases where
+# w * rho(D^{-1}A) < 2 on every level (elsewhere the V-cycle is indefinite),
+# the spectrum-scaled weight on the 3D cases whose spectra reach 3.4-4.3
+JACOBI_CASES = [("checker64", "jacobi"), ("twodomain64", "jacobi"), ("layered24_tall", "jacobi"),
+                ("layered16", "jacobi_scaled"), ("aniso16", "jacobi_scaled"), ("annulus_h2", "jacobi_scaled")]
+
+
+@pytest.mark.parametrize("name,smoother", JACOBI_CASES)
+def test_jacobi_smoother_matches_oracle(amg, name, smoother):
+    """The Jacobi options against the oracle: the same hierarchy (the setup
+    does not depend on the smoother: masks, aggregates and patterns bitwise,
+    values and spectral estimates to round-off), the V-cycle within the
+    coarse solve's forward-error bound, the FP64 solve within 1e-6 of the
+    oracle's with iterations +-1, and the FP32-hierarchy form to a true
+    relative residual of 1e-8 with its error against the FP64 oracle
+    reported."""
+    import torch
+
+    prob_fn, kw = CASES[name]
+    prob = prob_fn()
+    banner(f"{name}: smoother={smoother}")
+    orc = oracle.Hierarchy(prob, smoother=smoother, **kw)
+    h = amg.Hierarchy.from_problem(prob, smoother=smoother, **kw)
+    st = h.stats()
+    assert st["levels"] == orc.nlev
+    for l in range(orc.nlev - 1):
+        assert np.array_equal(h.soc_mask(l), orc.get(l, "mask")), f"mask level {l}"
+        assert np.array_equal(h.aggregates(l), orc.get(l, "agg")), f"aggregates level {l}"
+        assert st["lam_cheb"][l] == pytest.approx(orc.info(l)["lam_cheb"], rel=1e-10)
+        if smoother == "jacobi":
+            assert 2.0 / 3.0 * st["lam_cheb"][l] < 2.0
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal(prob.n)
+    zo = orc.vcycle(r)
+    rt = torch.from_numpy(r).cuda()
+    zt = torch.zeros_like(rt)
+    h.vcycle(rt, zt)
+    torch.cuda.synchronize()
+    z = zt.cpu().numpy()
+    bound = max(1e-9, 10 * np.finfo(float).eps * coarse_condition(orc))
+    vrel = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    assert vrel <= bound, (vrel, bound)
+    xo, io = orc.pcg(prob.b)
+    assert io["status"] == oracle.OK
+    x, info = h.solve(prob.b)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    h32 = amg.Hierarchy.from_problem(prob, smoother=smoother, precision="fp32", **kw)
+    x32, i32 = h32.solve(prob.b)
+    err32 = np.linalg.norm(x32 - xo) / np.linalg.norm(xo)
+    r32 = prob.b - oracle.spmv(prob.rowptr, prob.col, prob.val, x32)
+    rel32 = np.linalg.norm(r32) / np.linalg.norm(prob.b)
+    print(f"{name} {smoother}: V-cycle rel diff {vrel:.1e}; iters gpu={info['iterations']} oracle={io['iterations']} "
+          f"fp32={i32['iterations']}; rel_err fp64={err:.1e} fp32 vs fp64 oracle={err32:.1e}")
+    assert info["status"] == "OK" and info["rel_res"] <= 1e-8
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    if name in FLOOR_LIMITED:
+        ex = layered_exact(prob)
+        eg = np.linalg.norm(x - ex) / np.linalg.norm(ex)
+        eo = np.linalg.norm(xo - ex) / np.linalg.norm(ex)
+        assert eg <= 2 * eo + 1e-6
+    else:
+        assert err <= 1e-6
+    assert i32["status"] == "OK" and rel32 <= 1e-8

@@ -281,3 +281,63 @@ def test_jacobi_smoother_option_converges(checker):
     h = oracle.Hierarchy(prob, max_coarse=40, smoother="jacobi")
     _, info = h.pcg(prob.b)
     assert info["status"] == 0
+
+
+@pytest.mark.parametrize("smoother,sweeps,omega", [("jacobi", 1, 2.0 / 3.0), ("jacobi", 2, 2.0 / 3.0),
+                                                    ("jacobi", 3, 0.5), ("jacobi_scaled", 2, 2.0 / 3.0),
+                                                    ("jacobi_scaled", 3, 0.9)])
+def test_jacobi_error_propagator_is_a_power_of_the_damped_jacobi_matrix(smoother, sweeps, omega):
+    """The Jacobi options (solver settings of the numerical section: damped
+    Jacobi as the alternative to Chebyshev): `sweeps` sweeps of
+    x <- x + w D^{-1}(b - A x) with D the plain diagonal of A and w = omega,
+    or w = omega * 2 / (1.1 lambda) for the scaled option (lambda the level's
+    spectral estimate).  From a zero start the smoother S satisfies
+    I - S A = J^sweeps, J = I - w D^{-1} A; from any x0 the error is
+    multiplied by the same J^sweeps.  A dropped weight on the zero-start
+    sweep, a wrong sweep count or a wrong diagonal changes the power or the
+    matrix."""
+    prob = poisson_box((6, 6), dirichlet="all")
+    h = oracle.Hierarchy(prob, max_coarse=5, smoother=smoother, jacobi_sweeps=sweeps, jacobi_omega=omega)
+    A = prob.dense()
+    n = prob.n
+    w = omega if smoother == "jacobi" else omega * 2.0 / (1.1 * h.info(0)["lam_cheb"])
+    if smoother == "jacobi_scaled":
+        # the weight times the true spectral radius stays below 2
+        rho = np.abs(np.linalg.eigvals(A / A.diagonal()[:, None])).max()
+        assert w * rho < 2.0 and w != omega
+    J = np.eye(n) - w * A / A.diagonal()[:, None]
+    Js = np.linalg.matrix_power(J, sweeps)
+    S = np.stack([h.smooth(0, e) for e in np.eye(n)], axis=1)
+    assert np.allclose(np.eye(n) - S @ A, Js, rtol=0, atol=1e-13)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(n)
+    x0 = rng.standard_normal(n)
+    xs = np.linalg.solve(A, b)
+    x1 = h.smooth(0, b, x0)
+    assert np.allclose(x1 - xs, Js @ (x0 - xs), rtol=0, atol=1e-12 * np.abs(xs).max())
+
+
+@pytest.mark.parametrize("smoother", ["jacobi", "jacobi_scaled", "chebyshev"])
+def test_two_level_vcycle_equals_the_dense_two_grid_operator(smoother):
+    """Algorithm Vcycle on two levels with a zero start: pre-smoothing,
+    residual, restriction P^T r, exact coarse solve of P^T A P, prolongation
+    and post-smoothing give z = (I - E) A^{-1} r with
+    E = X (I - P (P^T A P)^{-1} P^T A) X, X = I - S A the smoother's error
+    propagator (pre- and post-smoothing apply the same polynomial)."""
+    prob = poisson_box((4, 4, 4), dirichlet="x0")
+    h = oracle.Hierarchy(prob, max_coarse=30, smoother=smoother)
+    assert h.nlev == 2
+    A = prob.dense()
+    n = prob.n
+    nc = h.info(0)["nc"]
+    P = dense(*h.level_csr(0, "P"), nc)
+    S = np.stack([h.smooth(0, e) for e in np.eye(n)], axis=1)
+    X = np.eye(n) - S @ A
+    Ac = P.T @ A @ P
+    E = X @ (np.eye(n) - P @ np.linalg.solve(Ac, P.T @ A)) @ X
+    M = (np.eye(n) - E) @ np.linalg.inv(A)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        r = rng.standard_normal(n)
+        z = h.vcycle(r)
+        assert np.allclose(z, M @ r, rtol=0, atol=1e-11 * np.abs(M @ r).max())
