@@ -8,16 +8,19 @@ three isotropic layers with log-uniform conductivities in [1e-5,1e-2],
 
 One step = the whole hot path on inputs already resident in HBM:
 amg_setup (Clement tensors, strength, aggregation, prolongators, Galerkin
-products, coarse factorisation) followed by amg_pcg_solve to a true relative
-residual of 1e-8.  value = DOF * steps / time.  The JSON line also carries
-solve-only throughput, the FP32-hierarchy form against the FP64 form (on
-this stack and on the 96^3 rotated-anisotropy cube, `fp32_form.aniso`), the
-V-cycle's algorithmic HBM bandwidth, the roofline of the dominant kernel
-(the finest level's fused Chebyshev SpMV: back-to-back launches between
-HIP events on its stream), the serving stream (256 requests at 20/s,
-n log-uniform in [32, 128], layered or anisotropic, FP32-hierarchy form,
-8 GiB budget: p50 / p99 latency and solves/s) and the CPU oracle timed on a
-bounded sample of the same recipe.
+products, coarse factorisation) followed by amg_pcg_solve from x0 = 0 to a
+true relative residual of 1e-8.  value = DOF * steps / time.  The JSON line
+also carries solve-only throughput, the same solve from five seeded starts
+(`seeded_x0`), the FP32-hierarchy form against the FP64 form (on this stack,
+and on the 96^3 rotated-anisotropy cube, `fp32_form.aniso`), the V-cycle's
+algorithmic HBM bandwidth per form, the roofline of the dominant kernel
+(the finest level's fused Chebyshev SpMV: back-to-back launches between HIP
+events on its stream), the 192^3 stack with 50 repeats (`layered192`: both
+forms, 16 levels), the serving stream (256 requests at 20/s, n log-uniform
+in [32, 128], layered or anisotropic, FP32-hierarchy form, 8 GiB budget:
+p50 / p99 latency and solves/s, over all requests and over the converged
+ones) and the CPU oracle's full setup and solve of the same workload,
+measured on one host core, whose solution the GPU results are compared with.
 """
 
 import argparse
@@ -74,24 +77,118 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(prob, iterations, sample_iters):
-    """The oracle as it stands, single-threaded, on a bounded sample of the
-    same workload: its full setup plus `sample_iters` PCG iterations; the
-    solve is scaled to the GPU run's iteration count."""
+def cpu_baseline(prob):
+    """The oracle as it stands, single-threaded, on the same workload: its full
+    setup and its PCG solve from x0 = 0 to a relative residual of 1e-8, both
+    measured.  Returns the baseline record and the oracle's solution."""
     import oracle
 
     t0 = time.perf_counter()
     h = oracle.Hierarchy(prob)
     t1 = time.perf_counter()
-    _, info = h.pcg(prob.b, maxit=sample_iters)
+    x, info = h.pcg(prob.b)
     t2 = time.perf_counter()
-    t_iter = (t2 - t1) / max(info["iterations"], 1)
-    t_est = (t1 - t0) + t_iter * iterations
-    return dict(value=prob.n / t_est, unit="DOF/s", cores=1, kind="oracle",
-                sample=(f"same workload ({prob.n} DOF): full oracle setup ({t1 - t0:.1f}s) + "
-                        f"{info['iterations']} PCG iterations ({t2 - t1:.1f}s, {t_iter * 1e3:.0f} ms/iteration); "
-                        f"solve scaled to the GPU run's {iterations} iterations"),
-                host_cpu=cpu_model(), host_threads=os.cpu_count())
+    rec = dict(value=prob.n / (t2 - t0), unit="DOF/s", cores=1, kind="oracle",
+               sample=(f"the whole workload ({prob.n} DOF), measured: oracle setup {t1 - t0:.1f} s + PCG from x0 = 0, "
+                       f"{info['iterations']} iterations to rel-res 1e-8 ({t2 - t1:.1f} s)"),
+               t_setup_s=t1 - t0, t_solve_s=t2 - t1, iterations=info["iterations"], status=info["status"],
+               rel_res=info["rel_res"], solve_only_dof_per_s=prob.n / (t2 - t1),
+               host_cpu=cpu_model(), host_threads=os.cpu_count())
+    return rec, x
+
+
+def time_vcycles(h, n, reps, dev):
+    """Mean duration (ms) of `reps` back-to-back V-cycles between HIP events on
+    torch's current stream (the stream the V-cycle launches on)."""
+    import torch
+
+    r = torch.randn(n, dtype=torch.float64, device=dev)
+    z = torch.zeros_like(r)
+    for _ in range(3):
+        h.vcycle(r, z)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        h.vcycle(r, z)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def vcycle_record(h, n, reps, dev):
+    st = h.stats()
+    ms = time_vcycles(h, n, reps, dev)
+    gbs = st["vcycle_alg_bytes"] / (ms * 1e-3) / 1e9
+    kt = h.time_smoother(level=0, reps=reps)
+    return {"ms": ms, "alg_bytes": st["vcycle_alg_bytes"], "alg_GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS,
+            "fine_smoother_us": kt["avg_ms"] * 1e3,
+            "fine_smoother_GBps": kt["bytes_per_launch"] / (kt["avg_ms"] * 1e-3) / 1e9}
+
+
+def layered_exact(prob):
+    """Exact discrete solution of a layered stack (f = 0, z-only series resistor)."""
+    kz = prob.meta["layer_k"]
+    res = 1.0 / kz
+    cf = np.concatenate([[0.0], np.cumsum(res)]) / res.sum()
+    return cf[np.rint(prob.coords[:, 2] * prob.shape[2]).astype(int)]
+
+
+def run_layered192(args, amg, dev, log):
+    """The 192^3 layered stack (7,189,057 DOF, 50 repeats of three layers over
+    192 elements, 20:1 flat), which needs 16 levels: per precision form, setup
+    and PCG from x0 = 0 to 1e-8 timed `c4_reps` times, the V-cycle and the
+    finest smoother step timed, errors against the exact discrete solution
+    and between the forms."""
+    import torch
+
+    from workloads import layered_stack_3d
+
+    log("generating layered stack 192^3, 50 repeats, 20:1")
+    prob = layered_stack_3d(n=192, repeats=50, stretch=20.0, config_id=4)
+    n = prob.n
+    d = [torch.from_numpy(a).to(dev) for a in (prob.rowptr, prob.col, prob.val, prob.elem_nodes, prob.elem_sigma,
+                                                prob.coords)]
+    b = torch.from_numpy(prob.b).to(dev)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    exact = layered_exact(prob)
+    out = dict(workload="layered stack 192^3 hex Q1 (7189057 DOF), 50 repeats x 3 layers, 20:1 flat, 16 levels",
+               n=n, nnz=prob.nnz)
+    sol = {}
+    for name in ("fp64", "fp32"):
+        opts = amg.options(dim=3, precision=name, max_levels=16)
+        steps, setups, solves = [], [], []
+        for k in range(max(1, args.c4_reps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = amg.Hierarchy(*d, opts)
+            x.zero_()
+            _, info = h.solve(b, x, max_iter=args.c4_max_iter, raise_on_error=False)
+            torch.cuda.synchronize()
+            steps.append(1e3 * (time.perf_counter() - t0))
+            setups.append(1e3 * h.stats()["t_setup_s"])
+            solves.append(1e3 * info["t_solve_s"])
+            if k + 1 < max(1, args.c4_reps):
+                h.close()
+        sol[name] = x.cpu().numpy()
+        st = h.stats()
+        vc = vcycle_record(h, n, args.vcycles // 5 or 1, dev)
+        h.close()
+        step_ms = float(np.median(steps))
+        out[name] = dict(status=info["status"], iterations=info["iterations"], rel_res=info["rel_res"],
+                         levels=st["n"], op_complexity=st["op_complexity"],
+                         t_setup_ms_stats=stats_ms(setups), t_solve_ms_stats=stats_ms(solves),
+                         step_ms_stats=stats_ms(steps), dof_per_s=n / (step_ms * 1e-3),
+                         solve_only_dof_per_s=n / (float(np.median(solves)) * 1e-3), vcycle=vc,
+                         rel_err_vs_closed_form=float(np.linalg.norm(sol[name] - exact) / np.linalg.norm(exact)))
+        log(f"192^3 {name}: {info['iterations']} it ({info['status']}), setup {np.median(setups):.0f} ms, solve "
+            f"{np.median(solves):.0f} ms, V-cycle {vc['ms']:.3f} ms = {vc['frac_of_peak']:.1%} of peak")
+    out["speedup_fp32_vs_fp64_solve"] = (out["fp64"]["t_solve_ms_stats"]["median"] /
+                                         out["fp32"]["t_solve_ms_stats"]["median"])
+    out["speedup_fp32_vs_fp64_vcycle"] = out["fp64"]["vcycle"]["ms"] / out["fp32"]["vcycle"]["ms"]
+    out["rel_err_fp32_vs_fp64_form"] = float(np.linalg.norm(sol["fp32"] - sol["fp64"]) / np.linalg.norm(sol["fp64"]))
+    return out
 
 
 def run_serving(args, amg, log):
@@ -180,6 +277,13 @@ def run_serving(args, amg, log):
                           iterations_mix=results[i][1]["iterations"], iterations_alone=ia["iterations"],
                           shared_rounds_with=results[i][2]["max_batch"] - 1))
     makespan = t_last - t_first
+    converged_only = None
+    if conv:
+        lc = lat[conv]
+        converged_only = {"requests": len(conv), "solves_per_s": len(conv) / makespan,
+                          "served_dof_per_s": sum(dofs[i] for i in conv) / makespan,
+                          "p50_latency_s": float(np.percentile(lc, 50)), "p99_latency_s": float(np.percentile(lc, 99)),
+                          "mean_latency_s": float(lc.mean())}
     # where the latency goes: waiting for admission, setup, solve (rounds)
     tl = [results[i][2] for i in range(len(reqs))]
     phases = {}
@@ -195,6 +299,8 @@ def run_serving(args, amg, log):
         "mean_latency_s": float(lat.mean()), "max_latency_s": float(lat.max()),
         "solves_per_s": len(reqs) / makespan, "makespan_s": makespan, "served_dof_per_s": sum(dofs) / makespan,
         "status_counts": status, "converged": len(conv),
+        # the same figures over the requests that reached the tolerance only
+        "converged_only": converged_only,
         "iterations": {"median": float(np.median(iters)), "p90": float(np.percentile(iters, 90)),
                        "max": int(iters.max())},
         "mean_batch": st["mean_batch"], "max_batch": st["max_batch"], "rounds": st["steps"],
@@ -206,6 +312,9 @@ def run_serving(args, amg, log):
     }
     log(f"serving: p50 {out['p50_latency_s']:.2f}s p99 {out['p99_latency_s']:.2f}s, "
         f"{out['solves_per_s']:.2f} solves/s, statuses {status}, mean batch {st['mean_batch']:.1f}")
+    if converged_only:
+        log(f"serving, converged only: {converged_only['solves_per_s']:.2f} solves/s, p50 "
+            f"{converged_only['p50_latency_s']:.2f}s p99 {converged_only['p99_latency_s']:.2f}s")
     return out
 
 
@@ -467,13 +576,17 @@ def run_fp32_aniso(args, amg, dev, log):
             _, info = h.solve(b, x, max_iter=args.max_iter)
             ts.append(1e3 * info["t_solve_s"])
         sol[name] = x.cpu().numpy()
+        vc = vcycle_record(h, prob.n, args.vcycles, dev)
         h.close()
         out[name] = dict(t_setup_ms=1e3 * t_setup, t_solve_ms_stats=stats_ms(np.array(ts)),
-                         iterations=info["iterations"], rel_res=info["rel_res"], status=info["status"])
+                         iterations=info["iterations"], rel_res=info["rel_res"], status=info["status"], vcycle=vc)
     m64, m32 = out["fp64"]["t_solve_ms_stats"]["median"], out["fp32"]["t_solve_ms_stats"]["median"]
     out["speedup_vs_fp64_solve"] = m64 / m32
     out["speedup_per_iteration"] = (m64 / max(1, out["fp64"]["iterations"])) / (m32 / max(1, out["fp32"]["iterations"]))
+    out["speedup_vs_fp64_vcycle"] = out["fp64"]["vcycle"]["ms"] / out["fp32"]["vcycle"]["ms"]
     out["rel_err_vs_fp64_form"] = float(np.linalg.norm(sol["fp32"] - sol["fp64"]) / np.linalg.norm(sol["fp64"]))
+    log(f"aniso {args.aniso_n}^3: V-cycle fp32 {out['fp32']['vcycle']['ms']:.3f} ms vs fp64 "
+        f"{out['fp64']['vcycle']['ms']:.3f} ms ({out['speedup_vs_fp64_vcycle']:.2f}x)")
     log(f"aniso {args.aniso_n}^3: fp32 {m32:.1f} ms ({out['fp32']['iterations']} it) vs fp64 {m64:.1f} ms "
         f"({out['fp64']['iterations']} it): {out['speedup_vs_fp64_solve']:.2f}x, "
         f"rel err {out['rel_err_vs_fp64_form']:.1e}")
@@ -500,7 +613,10 @@ def main():
     ap.add_argument("--vcycles", type=int, default=100)
     ap.add_argument("--fp32-reps", type=int, default=5, help="timed FP32-form solves on one hierarchy")
     ap.add_argument("--x0-seeds", type=int, default=5, help="seeded initial guesses for the FP32/FP64 comparison")
-    ap.add_argument("--cpu-sample", type=int, default=5, help="oracle PCG iterations in the CPU sample (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle's full setup and solve")
+    ap.add_argument("--c4-reps", type=int, default=1,
+                    help="timed setup + solve runs per precision form on the 192^3 stack (0: skip)")
+    ap.add_argument("--c4-max-iter", type=int, default=4000, help="PCG iteration cap on the 192^3 stack")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="one setup, a few V-cycles and a 1 GiB device copy (for counter collection), no JSON")
     ap.add_argument("--no-fp32", action="store_true")
@@ -539,7 +655,7 @@ def main():
     import torch
 
     import paper_2602_05686_amd as amg
-    from workloads.q1 import layered_stack_3d
+    from workloads.q1 import layered_stack_3d, seeded_start
 
     amg.load()
     torch.cuda.set_device(0)
@@ -622,35 +738,25 @@ def main():
     x64 = x.cpu().numpy()
     log(f"step {ms_per_step:.1f} ms, setup {np.mean(setups) * 1e3:.1f} ms, solve {t_solve * 1e3:.1f} ms, "
         f"iters {infos[-1]['iterations']}, levels {st['n']}")
-
-    # closed-form discrete solution of the layered stack (f = 0, z-only)
-    kz = prob.meta["layer_k"]
-    res = 1.0 / kz
-    cf = np.concatenate([[0.0], np.cumsum(res)]) / res.sum()
-    zi = np.rint(prob.coords[:, 2] * args.n).astype(int)
-    exact = cf[zi]
+    exact = layered_exact(prob)
     err64 = float(np.linalg.norm(x64 - exact) / np.linalg.norm(exact))
 
     # V-cycle bandwidth and the dominant kernel's roofline
-    r = torch.randn(n, dtype=torch.float64, device=dev)
-    z = torch.zeros_like(r)
-    for _ in range(3):
-        h.vcycle(r, z)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.vcycles):
-        h.vcycle(r, z)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_vc_ms = e0.elapsed_time(e1) / args.vcycles
+    t_vc_ms = time_vcycles(h, n, args.vcycles, dev)
     vc_gbs = st["vcycle_alg_bytes"] / (t_vc_ms * 1e-3) / 1e9
     kt = h.time_smoother(level=0, reps=args.vcycles)
     avg_ms = kt["avg_ms"]
     achieved = kt["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
     log(f"V-cycle {t_vc_ms:.3f} ms = {vc_gbs:.0f} GB/s algorithmic; fine smoother SpMV {avg_ms * 1e3:.1f} us "
         f"= {achieved:.0f} GB/s")
+
+    # the same solve from seeded initial guesses x0 ~ U(0, 1): how the exit
+    # count and the throughput move with the starting point
+    seeds = []
+    for k in range(args.x0_seeds):
+        x.copy_(torch.from_numpy(seeded_start(n, k)).to(dev))
+        _, ik = h.solve(d["b"], x, max_iter=args.max_iter)
+        seeds.append((ik["iterations"], 1e3 * ik["t_solve_s"]))
 
     fp32 = None
     if not args.no_fp32:
@@ -662,52 +768,62 @@ def main():
             _, info32 = h32.solve(d["b"], x, max_iter=args.max_iter)
             t32.append(info32["t_solve_s"])
         x32 = x.cpu().numpy()
-        # The exit iteration sits on an oscillating residual plateau (see
-        # DESIGN), so one exit compares two draws; the two forms are also
-        # compared from seeded initial guesses x0 ~ U(0, 1), by median.
-        seeds = []
+        vc32 = vcycle_record(h32, n, args.vcycles, dev)
+        seeds32 = []
         for k in range(args.x0_seeds):
-            x0 = torch.from_numpy(np.random.default_rng(1000 + k).uniform(0.0, 1.0, n)).to(dev)
-            row = {}
-            for name, hh in (("fp64", h), ("fp32", h32)):
-                x.copy_(x0)
-                _, ik = hh.solve(d["b"], x, max_iter=args.max_iter)
-                row[name] = (ik["iterations"], 1e3 * ik["t_solve_s"])
-            seeds.append(row)
+            x.copy_(torch.from_numpy(seeded_start(n, k)).to(dev))
+            _, ik = h32.solve(d["b"], x, max_iter=args.max_iter)
+            seeds32.append((ik["iterations"], 1e3 * ik["t_solve_s"]))
         h32.close()
         t32m = float(np.mean(t32))
         fp32 = dict(t_solve_s=t32m, t_solve_ms_stats=stats_ms(np.array(t32) * 1e3), iterations=info32["iterations"],
                     rel_res=info32["rel_res"], status=info32["status"], speedup_vs_fp64_solve=t_solve / t32m,
                     speedup_per_iteration=(t_solve / infos[-1]["iterations"]) /
                     (t32m / max(1, info32["iterations"])),
+                    vcycle=vc32, speedup_vs_fp64_vcycle=t_vc_ms / vc32["ms"],
                     rel_err_vs_fp64_form=float(np.linalg.norm(x32 - x64) / np.linalg.norm(x64)),
                     rel_err_vs_closed_form=float(np.linalg.norm(x32 - exact) / np.linalg.norm(exact)))
-        if seeds:
-            med = {f: float(np.median([r[f][1] for r in seeds])) for f in ("fp64", "fp32")}
-            fp32["x0_seeds"] = {
-                "seeds": len(seeds),
-                "fp64_iterations": [r["fp64"][0] for r in seeds], "fp32_iterations": [r["fp32"][0] for r in seeds],
-                "fp64_t_solve_ms_median": med["fp64"], "fp32_t_solve_ms_median": med["fp32"],
-                "speedup_of_medians": med["fp64"] / med["fp32"]}
-            log(f"fp32 vs fp64 from {len(seeds)} seeded x0: median solve {med['fp32']:.1f} vs {med['fp64']:.1f} ms, "
-                f"iterations {fp32['x0_seeds']['fp32_iterations']} vs {fp32['x0_seeds']['fp64_iterations']}")
-        log(f"fp32 form: solve {t32m * 1e3:.1f} ms (mean of {len(t32)}), iters {info32['iterations']}")
+        if seeds32:
+            m64, m32 = float(np.median([v[1] for v in seeds])), float(np.median([v[1] for v in seeds32]))
+            fp32["x0_seeds"] = {"seeds": len(seeds32), "fp64_iterations": [v[0] for v in seeds],
+                                "fp32_iterations": [v[0] for v in seeds32], "fp64_t_solve_ms_median": m64,
+                                "fp32_t_solve_ms_median": m32, "speedup_of_medians": m64 / m32}
+        log(f"fp32 form: solve {t32m * 1e3:.1f} ms (mean of {len(t32)}), iters {info32['iterations']}, V-cycle "
+            f"{vc32['ms']:.3f} ms ({t_vc_ms / vc32['ms']:.2f}x the FP64 one)")
     h.close()
     if fp32 is not None and args.aniso_n > 0:
         fp32["aniso"] = run_fp32_aniso(args, amg, dev, log)
 
+    c4 = None
+    if args.c4_reps > 0:
+        del d
+        torch.cuda.empty_cache()
+        c4 = run_layered192(args, amg, dev, log)
+
     serving = None
     if not args.no_serving:
-        del d
         torch.cuda.empty_cache()
         serving = run_serving(args, amg, log)
 
     cpu = None
-    if args.cpu_sample > 0:
-        log(f"oracle sample: setup + {args.cpu_sample} PCG iterations")
-        cpu = cpu_baseline(prob, infos[-1]["iterations"], args.cpu_sample)
+    if not args.no_cpu_baseline:
+        log("oracle: full setup and PCG solve on the same workload (single-threaded)")
+        cpu, xo = cpu_baseline(prob)
+        cpu["gpu_fp64_rel_err_vs_oracle"] = float(np.linalg.norm(x64 - xo) / np.linalg.norm(xo))
+        cpu["oracle_rel_err_vs_closed_form"] = float(np.linalg.norm(xo - exact) / np.linalg.norm(exact))
+        if fp32 is not None:
+            fp32["rel_err_vs_fp64_oracle"] = float(np.linalg.norm(x32 - xo) / np.linalg.norm(xo))
+        log(f"oracle: {cpu['iterations']} iterations, {cpu['t_setup_s']:.1f} s setup + {cpu['t_solve_s']:.1f} s "
+            f"solve; GPU FP64 solution {cpu['gpu_fp64_rel_err_vs_oracle']:.1e} from the oracle's")
 
     traffic = measured_traffic() if args.n == 128 and args.repeats == 20 and args.stretch == 10.0 else None
+    seeded = None
+    if seeds:
+        med = float(np.median([v[1] for v in seeds]))
+        t_setup_ms = 1e3 * float(np.mean(setups))
+        seeded = {"seeds": len(seeds), "iterations": [v[0] for v in seeds], "t_solve_ms_median": med,
+                  "dof_per_s_setup_plus_median_solve": n / ((t_setup_ms + med) * 1e-3),
+                  "solve_only_dof_per_s_median": n / (med * 1e-3)}
     out = {
         "metric": "DOF/s to rel-res 1e-8 (setup + AMG-PCG solve)",
         "value": n * args.steps / t_total,
@@ -722,7 +838,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"layered stack {args.n}^3 hex Q1 ({n} DOF), {args.repeats} repeats x 3 layers, "
-                               f"{args.stretch:g}:1 flat, FP64 plain form",
+                               f"{args.stretch:g}:1 flat, FP64 plain form, PCG from x0 = 0",
                    "dof": n, "nnz": prob.nnz, "theta": 0.08, "tol": 1e-8},
         "solve_only_dof_per_s": n / t_solve,
         "t_setup_ms": 1e3 * float(np.mean(setups)),
@@ -734,6 +850,7 @@ def main():
         "iterations": infos[-1]["iterations"],
         "rel_res_true": infos[-1]["rel_res"],
         "rel_err_vs_closed_form": err64,
+        "seeded_x0": seeded,
         "levels": st["n"],
         "op_complexity": st["op_complexity"],
         "vcycle": {"ms": t_vc_ms, "alg_bytes": st["vcycle_alg_bytes"], "alg_GBps": vc_gbs,
@@ -743,6 +860,7 @@ def main():
                      "traffic": traffic, "avg_launch_us": avg_ms * 1e3, "launches": args.vcycles,
                      "alg_bytes_per_launch": kt["bytes_per_launch"]},
         "fp32_form": fp32,
+        "layered192": c4,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -751,13 +751,25 @@ static int build_prolongator(Level *L, const OrcOptions *opt, int level)
     for (int i = 0; i < n; ++i) {
         double s = 0.0;
         for (int k = F.rowptr[i]; k < F.rowptr[i + 1]; ++k) s += fabs(F.val[k]);
-        /* A filtered row that keeps only its diagonal has (A_F)_ii = sum_k A_ik,
-         * which is exactly zero on rows with zero row sum and round-off noise
-         * in floating point.  Such a row is empty: its 1-norm is taken as zero
-         * (no smoothing) when it is below 2^-46 times the row's 1-norm in A. */
-        double rowabs = 0.0;
-        for (int k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) rowabs += fabs(A->val[k]);
-        dt[i] = (s > ROW_NOISE * rowabs) ? s : 0.0;
+        /* Isolated rows.  A row that keeps no off-diagonal connection has
+         * (A_F)_ii = sum_k A_ik, its 1-norm diagonal is |sum_k A_ik| and the
+         * formula moves its prolongator row to (1 -+ omega) P^ by the sign of
+         * that sum.  The sum is zero in exact arithmetic on interior rows and
+         * rounding noise in floating point, which on coarse levels (long
+         * Galerkin rows) reaches any size the genuine row sums near a
+         * boundary also take, so no threshold on it separates the two.  The
+         * reading: a non-Dirichlet row whose kept off-diagonals weigh at most
+         * 2^-46 of its 1-norm in A (none kept, or only stored zeros and
+         * noise) is isolated and not smoothed -- Dt_ii = 0, its row of P is
+         * its row of P^ -- which the drop mask decides, not the rounding.  A
+         * Dirichlet row keeps its diagonal (its row of P^ is empty anyway). */
+        double rowabs = 0.0, keptabs = 0.0;
+        for (int k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+            rowabs += fabs(A->val[k]);
+            if (A->col[k] != i && L->mask[k]) keptabs += fabs(A->val[k]);
+        }
+        int isolated = !(L->dir && L->dir[i]) && !(keptabs > ROW_NOISE * rowabs);
+        dt[i] = (!isolated && s > ROW_NOISE * rowabs) ? s : 0.0;
     }
     {
         double *dtinv = (double *)malloc(sizeof(double) * (size_t)n);

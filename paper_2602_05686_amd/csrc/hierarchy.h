@@ -77,4 +77,25 @@ void update_values(Hierarchy& h, const double* val, bool host_ptrs, hipStream_t 
 amg_status pcg_solve(Hierarchy& h, const double* b, double* x, double tol, int max_iter, bool host_ptrs,
                      hipStream_t s, amg_solve_info* info);
 
+// Workspace of one PCG solve: the iterate x (in/out) and r, z, p, q
+// (device vectors of the finest size), the device scalars (S_NSCAL), the
+// reduction partials and counter, a host mirror of the scalars, the stream,
+// and whether the captured step graphs may run (only with the hierarchy's
+// own buffers, which they hold).
+struct PcgWork {
+    double *x, *r, *z, *p, *q;
+    double* scal;
+    double* partial;
+    unsigned* counter;
+    double* hscal;
+    hipStream_t stream;
+    bool graphs;
+};
+// the PCG iteration of pcg_solve on a given workspace; allocates nothing
+amg_status pcg_run(Hierarchy& h, const PcgWork& w, const double* b, double tol, int max_iter, int* iters,
+                   double* rel_true);
+// doubles of reduction partials a solve on h needs
+size_t pcg_partials(const Hierarchy& h);
+
+
 }  // namespace matamg

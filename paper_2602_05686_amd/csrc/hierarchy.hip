@@ -54,8 +54,19 @@ void make_blocks(DCsr& A, MemCounter* mc, hipStream_t s, bool pack = true, int c
 // one-thread-per-row matrix: twice the bytes per workgroup, which the finest
 // levels stream faster, while the setup kernels keep the kStreamCap blocks
 // (sblk).  Kept only if the wider blocks pack too.
+// MATAMG_WIDE_MIN_BLOCKS=<k> lowers the block-count threshold (used by the
+// tests to run the wide kernels on small operators)
+int wide_block_min() {
+    const char* e = std::getenv("MATAMG_WIDE_MIN_BLOCKS");
+    if (e && e[0]) {
+        const int v = std::atoi(e);
+        if (v > 0) return v;
+    }
+    return kWideBlockMin;
+}
+
 void widen_stream_blocks(DCsr& A, MemCounter* mc, hipStream_t s) {
-    if (A.group != 1 || !A.col16 || A.cap != kStreamCap || A.nblk < kWideBlockMin) return;
+    if (A.group != 1 || !A.col16 || A.cap != kStreamCap || A.nblk < wide_block_min()) return;
     DBuf<int> blk = std::move(A.blk), blkk = std::move(A.blkk), cbase = std::move(A.cbase);
     DBuf<uint16_t> col16 = std::move(A.col16);
     const int nblk = A.nblk;
@@ -281,7 +292,7 @@ void smoothed_prolongator(Hierarchy& h, int l, DCsr& P, hipStream_t s) {
     F.col.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
     F.val.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
     DBuf<double> dt(nl, mc), dtinv(nl, mc);
-    filter_fill(L.A, L.mask.get(), F.rowptr.get(), F.col.get(), F.val.get(), dt.get(), dtinv.get(), s);
+    filter_fill(L.A, L.mask.get(), L.dir.get(), F.rowptr.get(), F.col.get(), F.val.get(), dt.get(), dtinv.get(), s);
     make_blocks(F, mc, s, false);  // ten power steps: not worth packing
     ensure_partial(h, std::max(stream_partials(F), stream_partials(L.A)));
     L.lam_pf = power_method(F, dtinv.get(), opt.power_iters, stream_key(opt.seed, kPurposePf, l), h, s);
@@ -781,11 +792,93 @@ hipGraphExec_t Hierarchy::step_graph(int cur) {
     return ex;
 }
 
+// the widest fused reduction of a solve: the finest operator's streaming
+// launches (q = A p, residual norms, the last smoothing step's r.z) and the
+// vector kernels' grids
+size_t pcg_partials(const Hierarchy& h) {
+    return (size_t)std::max(kMaxPartials, stream_partials(h.lev[0].A)) + 1;
+}
+
+// The PCG iteration on an explicit workspace (see PcgWork): the convergence
+// test reads the device scalars after every step through w.hscal.
+amg_status pcg_run(Hierarchy& h, const PcgWork& w, const double* b, double tol, int max_iter, int* iters_out,
+                   double* rel_out) {
+    const DCsr& A = h.lev[0].A;
+    const int n = A.n;
+    hipStream_t ws = w.stream;
+    double* x = w.x;
+    double* r = w.r;
+    double* z = w.z;
+    double* p = w.p;
+    double* q = w.q;
+    auto dt = [&](int slot) { return DotTarget{w.partial, w.counter, w.scal + slot}; };
+    auto read_scal = [&]() {
+        MATAMG_HIP(hipMemcpyAsync(w.hscal, w.scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, ws));
+        MATAMG_HIP(hipStreamSynchronize(ws));
+    };
+    amg_status st = AMG_ERR_NOT_CONVERGED;
+    int iters = 0;
+    double rel_true = 0.0;
+    dot<double>(b, b, n, w.partial, w.counter, w.scal + S_BB, ws);
+    spmv_resid_norm(A, x, b, r, dt(S_RR), ws);
+    read_scal();
+    const double bn = std::sqrt(w.hscal[S_BB]);
+    if (bn == 0.0) {
+        zero_async(x, sizeof(double) * n, ws);
+        st = AMG_OK;
+    } else if (std::sqrt(w.hscal[S_RR]) / bn <= tol) {
+        rel_true = std::sqrt(w.hscal[S_RR]) / bn;
+        st = AMG_OK;
+    } else if (max_iter > 0) {
+        // first step eagerly: z = M r, p = z, q = A p, x and r updated
+        int cur = S_RZ0;
+        h.vcycle(r, z, dt(cur), ws);
+        cg_direction(n, p, z, w.scal + cur, nullptr, ws);
+        spmv_dot(A, p, q, dt(S_PQ), ws);
+        cg_update(n, x, r, p, q, w.scal + cur, w.scal + S_PQ, dt(S_RR), ws);
+        for (int it = 1;; ++it) {
+            read_scal();
+            iters = it;
+            const double pq = w.hscal[S_PQ], rzv = w.hscal[cur];
+            if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(rzv)) {
+                st = AMG_ERR_BREAKDOWN;
+                break;
+            }
+            const double rel = std::sqrt(w.hscal[S_RR]) / bn;
+            rel_true = rel;
+            if (rel <= tol) {
+                spmv_resid_norm(A, x, b, q, dt(S_TMP), ws);
+                read_scal();
+                rel_true = std::sqrt(w.hscal[S_TMP]) / bn;
+                if (rel_true <= tol) {
+                    st = AMG_OK;
+                    break;
+                }
+                // residual replacement
+                MATAMG_HIP(hipMemcpyAsync(r, q, sizeof(double) * n, hipMemcpyDeviceToDevice, ws));
+            }
+            if (it >= max_iter) break;
+            const int nxt = (cur == S_RZ0) ? S_RZ1 : S_RZ0;
+            if (w.graphs) {
+                MATAMG_HIP(hipGraphLaunch(h.step_graph(cur), ws));
+            } else {
+                h.vcycle(r, z, dt(nxt), ws);
+                cg_direction(n, p, z, w.scal + nxt, w.scal + cur, ws);
+                spmv_dot(A, p, q, dt(S_PQ), ws);
+                cg_update(n, x, r, p, q, w.scal + nxt, w.scal + S_PQ, dt(S_RR), ws);
+            }
+            cur = nxt;
+        }
+    }
+    *iters_out = iters;
+    *rel_out = rel_true;
+    return st;
+}
+
 amg_status pcg_solve(Hierarchy& h, const double* b_in, double* x_io, double tol, int max_iter, bool host_ptrs,
                      hipStream_t s, amg_solve_info* info) {
     const double t0 = now_s();
-    const DCsr& A = h.lev[0].A;
-    const int n = A.n;
+    const int n = h.lev[0].A.n;
     h.ensure_solve_resources();
     hipStream_t ws = h.ws;
     // order after the caller's earlier work on its stream
@@ -801,68 +894,12 @@ amg_status pcg_solve(Hierarchy& h, const double* b_in, double* x_io, double tol,
     } else {
         MATAMG_HIP(hipMemcpyAsync(x, x_io, sizeof(double) * n, hipMemcpyDeviceToDevice, ws));
     }
-    double* r = h.cr.get();
-    double* z = h.cz.get();
-    double* p = h.cp.get();
-    double* q = h.cq.get();
-    auto read_scal = [&]() {
-        MATAMG_HIP(hipMemcpyAsync(h.hscal, h.scal.get(), sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, ws));
-        MATAMG_HIP(hipStreamSynchronize(ws));
-    };
-    amg_status st = AMG_ERR_NOT_CONVERGED;
+    // the captured step graphs hold these buffers
+    PcgWork w{x, h.cr.get(), h.cz.get(), h.cp.get(), h.cq.get(), h.scal.get(), h.partial.get(), h.counter.get(),
+              h.hscal, ws, h.use_graphs};
     int iters = 0;
     double rel_true = 0.0;
-    dot<double>(b, b, n, h.partial.get(), h.counter.get(), h.scal.get() + S_BB, ws);
-    spmv_resid_norm(A, x, b, r, h.dt(S_RR), ws);
-    read_scal();
-    const double bn = std::sqrt(h.hscal[S_BB]);
-    if (bn == 0.0) {
-        zero_async(x, sizeof(double) * n, ws);
-        st = AMG_OK;
-    } else if (std::sqrt(h.hscal[S_RR]) / bn <= tol) {
-        rel_true = std::sqrt(h.hscal[S_RR]) / bn;
-        st = AMG_OK;
-    } else if (max_iter > 0) {
-        // first step eagerly: z = M r, p = z, q = A p, x and r updated
-        int cur = S_RZ0;
-        h.vcycle(r, z, h.dt(cur), ws);
-        cg_direction(n, p, z, h.scal.get() + cur, nullptr, ws);
-        spmv_dot(A, p, q, h.dt(S_PQ), ws);
-        cg_update(n, x, r, p, q, h.scal.get() + cur, h.scal.get() + S_PQ, h.dt(S_RR), ws);
-        for (int it = 1;; ++it) {
-            read_scal();
-            iters = it;
-            const double pq = h.hscal[S_PQ], rzv = h.hscal[cur];
-            if (!(pq > 0.0) || !std::isfinite(pq) || !std::isfinite(rzv)) {
-                st = AMG_ERR_BREAKDOWN;
-                break;
-            }
-            const double rel = std::sqrt(h.hscal[S_RR]) / bn;
-            rel_true = rel;
-            if (rel <= tol) {
-                spmv_resid_norm(A, x, b, q, h.dt(S_TMP), ws);
-                read_scal();
-                rel_true = std::sqrt(h.hscal[S_TMP]) / bn;
-                if (rel_true <= tol) {
-                    st = AMG_OK;
-                    break;
-                }
-                // residual replacement
-                MATAMG_HIP(hipMemcpyAsync(r, q, sizeof(double) * n, hipMemcpyDeviceToDevice, ws));
-            }
-            if (it >= max_iter) break;
-            const int nxt = (cur == S_RZ0) ? S_RZ1 : S_RZ0;
-            if (h.use_graphs) {
-                MATAMG_HIP(hipGraphLaunch(h.step_graph(cur), ws));
-            } else {
-                h.vcycle(r, z, h.dt(nxt), ws);
-                cg_direction(n, p, z, h.scal.get() + nxt, h.scal.get() + cur, ws);
-                spmv_dot(A, p, q, h.dt(S_PQ), ws);
-                cg_update(n, x, r, p, q, h.scal.get() + nxt, h.scal.get() + S_PQ, h.dt(S_RR), ws);
-            }
-            cur = nxt;
-        }
-    }
+    const amg_status st = pcg_run(h, w, b, tol, max_iter, &iters, &rel_true);
     if (host_ptrs) d2h(x_io, x, n, ws);
     else MATAMG_HIP(hipMemcpyAsync(x_io, x, sizeof(double) * n, hipMemcpyDeviceToDevice, ws));
     MATAMG_HIP(hipStreamSynchronize(ws));

@@ -659,20 +659,27 @@ __global__ __launch_bounds__(kBlock) void k_filter_count(const int* rowptr, cons
 }
 
 // filtered row (kept entries in order, lumped diagonal), its 1-norm, and the
-// empty-row rule: a row reduced to its lumped diagonal holds the row sum of
-// A, which is round-off noise on zero-sum rows; below 2^-46 of the row's
-// 1-norm the filtered row is empty and is not smoothed
+// rows that are not smoothed (1-norm diagonal zero, prolongator row = the
+// tentative one):
+//  - isolated rows: a non-Dirichlet row whose kept off-diagonals weigh at
+//    most 2^-46 of its 1-norm in A.  Its lumped diagonal is the row sum of
+//    A, zero in exact arithmetic on interior rows and rounding noise of any
+//    size on coarse levels, and the 1-norm scaling would turn its sign into a
+//    (1 -+ omega) factor; the drop mask decides instead, reproducibly;
+//  - empty rows: a filtered row whose 1-norm is at most 2^-46 of that.
+// Both sums run in ascending stored order, one IEEE operation at a time.
 __device__ __forceinline__ void filter_row(int i, const int* cs, const double* vs, const uint8_t* ms, int lo, int hi,
-                                           int p, int* fcol, double* fval, double* dt, double* dtinv) {
+                                           int p, bool dirichlet, int* fcol, double* fval, double* dt, double* dtinv) {
     const int p0 = p;
     int diagpos = -1;
-    double lump = 0.0, rowabs = 0.0;
+    double lump = 0.0, rowabs = 0.0, keptabs = 0.0;
     for (int k = lo; k < hi; ++k) {
         const int j = cs[k];
         const double v = vs[k];
         rowabs += fabs(v);
         if (j == i || ms[k]) {
             if (j == i) diagpos = p;
+            else keptabs += fabs(v);
             fcol[p] = j;
             fval[p] = v;
             p++;
@@ -683,15 +690,16 @@ __device__ __forceinline__ void filter_row(int i, const int* cs, const double* v
     if (diagpos >= 0) fval[diagpos] = fval[diagpos] + lump;
     double s = 0.0;
     for (int q = p0; q < p; ++q) s += fabs(fval[q]);
-    if (!(s > kRowNoise * rowabs)) s = 0.0;
+    const bool isolated = !dirichlet && !(keptabs > kRowNoise * rowabs);
+    if (isolated || !(s > kRowNoise * rowabs)) s = 0.0;
     dt[i] = s;
     dtinv[i] = s > 0.0 ? 1.0 / s : 0.0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_filter_fill(const int* rowptr, const int* col, const double* val,
-                                                        const uint8_t* mask, const int* blk, int nblk,
-                                                        const int* frowptr, int* fcol, double* fval, double* dt,
-                                                        double* dtinv) {
+                                                        const uint8_t* mask, const uint8_t* dir, const int* blk,
+                                                        int nblk, const int* frowptr, int* fcol, double* fval,
+                                                        double* dt, double* dtinv) {
     __shared__ int cs[kStreamCap];
     __shared__ double vs[kStreamCap];
     __shared__ uint8_t ms[kStreamCap];
@@ -707,9 +715,11 @@ __global__ __launch_bounds__(kBlock) void k_filter_fill(const int* rowptr, const
         __syncthreads();
         const int r = rb.r0 + (int)threadIdx.x;
         if (r < rb.r1)
-            filter_row(r, cs, vs, ms, rowptr[r] - rb.k0, rowptr[r + 1] - rb.k0, frowptr[r], fcol, fval, dt, dtinv);
+            filter_row(r, cs, vs, ms, rowptr[r] - rb.k0, rowptr[r + 1] - rb.k0, frowptr[r], dir[r] != 0, fcol, fval,
+                       dt, dtinv);
     } else if (threadIdx.x == 0) {
-        filter_row(rb.r0, col + rb.k0, val + rb.k0, mask + rb.k0, 0, rb.cnt, frowptr[rb.r0], fcol, fval, dt, dtinv);
+        filter_row(rb.r0, col + rb.k0, val + rb.k0, mask + rb.k0, 0, rb.cnt, frowptr[rb.r0], dir[rb.r0] != 0, fcol,
+                   fval, dt, dtinv);
     }
 }
 
@@ -948,11 +958,11 @@ void filter_count(const DCsr& A, const uint8_t* mask, int* cnt, hipStream_t s) {
     MATAMG_LAUNCH_CHECK();
 }
 
-void filter_fill(const DCsr& A, const uint8_t* mask, const int* frowptr, int* fcol, double* fval, double* dt,
-                 double* dtinv, hipStream_t s) {
+void filter_fill(const DCsr& A, const uint8_t* mask, const uint8_t* dir, const int* frowptr, int* fcol, double* fval,
+                 double* dt, double* dtinv, hipStream_t s) {
     if (A.setup_nblk() <= 0) return;
     hipLaunchKernelGGL(k_filter_fill, dim3(xcd_grid(A.setup_nblk())), dim3(kBlock), 0, s, A.rowptr.get(), A.col.get(),
-                       A.val.get(), mask, A.setup_blk(), A.setup_nblk(), frowptr, fcol, fval, dt, dtinv);
+                       A.val.get(), mask, dir, A.setup_blk(), A.setup_nblk(), frowptr, fcol, fval, dt, dtinv);
     MATAMG_LAUNCH_CHECK();
 }
 

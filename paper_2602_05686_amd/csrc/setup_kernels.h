@@ -47,10 +47,11 @@ void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, c
                 const uint8_t* state, const int* root_rank, int* phase2, int* agg, int* list, int* nlist,
                 hipStream_t s);
 
-// filtered matrix A_F (diagonal + kept entries, lumped diagonal) and its 1-norm diagonal
+// filtered matrix A_F (diagonal + kept entries, lumped diagonal) and its 1-norm
+// diagonal (zero on isolated and empty rows); dir: Dirichlet flags of the level
 void filter_count(const DCsr& A, const uint8_t* mask, int* cnt, hipStream_t s);
-void filter_fill(const DCsr& A, const uint8_t* mask, const int* frowptr, int* fcol, double* fval, double* dt,
-                 double* dtinv, hipStream_t s);
+void filter_fill(const DCsr& A, const uint8_t* mask, const uint8_t* dir, const int* frowptr, int* fcol, double* fval,
+                 double* dt, double* dtinv, hipStream_t s);
 void phat_counts(int n, const int* agg, int* cnt, hipStream_t s);
 void phat_fill(int n, const int* agg, const int* prowptr, int* pcol, double* pval, hipStream_t s);
 void prolongator_finalize(int n, const int* prowptr, const int* pcol, double* pval, const int* agg,

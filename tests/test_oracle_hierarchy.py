@@ -48,7 +48,11 @@ def test_prolongator_formula(checker):
     AF[np.arange(n), np.arange(n)] = A.diagonal() + (A - np.diag(A.diagonal())).sum(1) - AF.sum(1)
     assert np.allclose(AF.sum(1), A.sum(1), rtol=0, atol=1e-12 * np.abs(A).max())
     Dt = np.abs(AF).sum(1)
-    Dt[Dt <= 2.0**-46 * np.abs(A).sum(1)] = 0.0   # empty filtered rows are not smoothed
+    rowabs = np.abs(A).sum(1)
+    kept_off = np.abs(np.where(keep & ~np.eye(n, dtype=bool), A, 0.0)).sum(1)
+    # empty filtered rows, and rows whose kept off-diagonals weigh nothing
+    # (isolated, Dirichlet rows aside), are not smoothed
+    Dt[(Dt <= 2.0**-46 * rowabs) | ((kept_off <= 2.0**-46 * rowabs) & ~prob.dirichlet)] = 0.0
     Dtinv = np.where(Dt > 0, 1.0 / np.where(Dt > 0, Dt, 1.0), 0.0)
     Phat = np.zeros((n, nc))
     Phat[agg >= 0, agg[agg >= 0]] = 1.0
@@ -85,8 +89,6 @@ def test_empty_filtered_rows_keep_the_tentative_prolongator():
             lo, hi = rp[i], rp[i + 1]
             off = ci[lo:hi] != i
             if mask[lo:hi][off].any() or agg[i] < 0:
-                continue
-            if abs(va[lo:hi].sum()) > 2.0**-46 * np.abs(va[lo:hi]).sum():
                 continue
             seen += 1
             assert list(pci[prp[i]:prp[i + 1]]) == [agg[i]]

@@ -99,7 +99,9 @@ def test_new_material_on_the_kept_coarsening():
     np.fill_diagonal(AF, 0.0)
     AF[np.arange(n), np.arange(n)] = A.sum(1) - AF.sum(1)
     Dt = np.abs(AF).sum(1)
-    Dt[Dt <= 2.0**-46 * np.abs(A).sum(1)] = 0.0
+    rowabs = np.abs(A).sum(1)
+    kept_off = np.abs(np.where(keep & ~np.eye(n, dtype=bool), A, 0.0)).sum(1)
+    Dt[(Dt <= 2.0**-46 * rowabs) | ((kept_off <= 2.0**-46 * rowabs) & ~prob1.dirichlet)] = 0.0
     Dtinv = np.where(Dt > 0, 1.0 / np.where(Dt > 0, Dt, 1.0), 0.0)
     Phat = np.zeros((n, nc))
     Phat[agg >= 0, agg[agg >= 0]] = 1.0

@@ -20,4 +20,7 @@ from .q1 import (  # noqa: F401
     annulus_3d,
     serving_stream,
     problem_from_request,
+    ulp_perturbed,
+    seeded_start,
+    problem_digest,
 )

@@ -687,3 +687,30 @@ def problem_from_request(req):
     if req["kind"] == "layered":
         return layered_stack_3d(n=req["n"], repeats=20, stretch=10.0, seed=req["seed"], config_id=5)
     return rotated_anisotropic_3d(n=req["n"], seed=req["seed"], config_id=5)
+
+
+def ulp_perturbed(b, seed):
+    """b with every nonzero entry moved by one unit in the last place, up or
+    down by a fair coin from default_rng(1000 + seed); zeros stay zero.  Used
+    to probe how a solver's exit depends on rounding-level changes of the data."""
+    b = np.array(b, dtype=np.float64, copy=True)
+    nz = np.nonzero(b)[0]
+    sgn = np.random.default_rng(1000 + seed).choice([-1.0, 1.0], size=nz.size)
+    b[nz] = np.nextafter(b[nz], np.where(sgn > 0, np.inf, -np.inf))
+    return b
+
+
+def seeded_start(n, seed):
+    """Initial guess x0 ~ U(0, 1)^n from default_rng(1000 + seed)."""
+    return np.random.default_rng(1000 + seed).uniform(0.0, 1.0, n)
+
+
+def problem_digest(prob):
+    """SHA-256 of a problem's arrays (CSR, load vector, element tensors,
+    coordinates): equal digests mean bitwise equal inputs, e.g. on two hosts."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for a in (prob.rowptr, prob.col, prob.val, prob.b, prob.elem_sigma, prob.coords):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
