@@ -166,6 +166,32 @@ amg_status amg_pcg_solve(amg_hierarchy* h, const double* b, double* x, double to
                          amg_ptr_kind kind, void* hip_stream, amg_solve_info* info);
 
 /*
+ * amg_pcg_solve without any allocation, for callers that cannot allocate
+ * device memory during a solve (tight serving loops, harnesses that forbid
+ * it, work ordered among captured graphs).  The same preconditioned CG with
+ * the same kernels and stopping rule, launched directly on hip_stream (no
+ * captured graphs, no solve stream of the library): results are bitwise
+ * those of amg_pcg_solve with device pointers.
+ *
+ * b, x   FP64 [n] device pointers of the current device; x holds the initial
+ *        guess on entry and is iterated in place (on NOT_CONVERGED or
+ *        BREAKDOWN it holds the last iterate)
+ * Workspace: the CG vectors, scalars and reduction partials live in one
+ * fixed 256 MiB device array of the library per device (allocated when the
+ * library is loaded, held until the process ends): the finest level may
+ * have at most about 8.3 million unknowns (4 n doubles plus the partials of
+ * its row blocks); a larger hierarchy gets INVALID_ARG with the bytes
+ * needed.  The array keeps the last call's contents.  Every call on one
+ * device shares it, so calls that overlap on one device (any hierarchies,
+ * any streams, any threads) race and must be serialised by the caller.
+ * The call returns after synchronising hip_stream.
+ * Errors: INVALID_ARG (null vectors, tol <= 0, max_iter < 0, workspace too
+ * small), NOT_CONVERGED, BREAKDOWN, HIP.
+ */
+amg_status amg_pcg_solve_noalloc(amg_hierarchy* h, const double* b, double* x, double tol, int32_t max_iter,
+                                 void* hip_stream, amg_solve_info* info);
+
+/*
  * New values of A on the setup's sparsity pattern, for instance after a
  * change of material.  The paper weighs the material measure's higher setup
  * cost against solves that reuse one hierarchy (numerical results, thermally

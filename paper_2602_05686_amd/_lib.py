@@ -27,7 +27,7 @@ PRECISION = {"fp64": 0, "fp32": 1}
 DROP = {"pointwise": 0, "cut": 1}
 
 EXPORTED = [
-    "amg_options_default", "amg_setup", "amg_pcg_solve", "amg_update_values", "amg_vcycle", "amg_level_spmv",
+    "amg_options_default", "amg_setup", "amg_pcg_solve", "amg_pcg_solve_noalloc", "amg_update_values", "amg_vcycle", "amg_level_spmv",
     "amg_hierarchy_info",
     "amg_get_aggregates", "amg_get_soc_mask", "amg_get_level_csr", "amg_get_level_aux", "amg_time_smoother",
     "amg_free", "amg_trim_cache", "amg_status_string", "amg_last_error",
@@ -123,6 +123,7 @@ def load():
     L.amg_options_default.argtypes = [ctypes.POINTER(Options)]
     L.amg_setup.argtypes = [i64, P, P, P, i64, i32, P, P, P, ctypes.POINTER(Options), i32, P, ctypes.POINTER(P)]
     L.amg_pcg_solve.argtypes = [P, P, P, f64, i32, i32, P, ctypes.POINTER(SolveInfo)]
+    L.amg_pcg_solve_noalloc.argtypes = [P, P, P, f64, i32, P, ctypes.POINTER(SolveInfo)]
     L.amg_vcycle.argtypes = [P, P, P, P]
     L.amg_update_values.argtypes = [P, P, i32, P]
     L.amg_level_spmv.argtypes = [P, i32, P, P, P]
@@ -258,6 +259,17 @@ class Hierarchy:
                                    ctypes.byref(info))
         if raise_on_error and code != AMG_OK:
             check(code, "amg_pcg_solve")
+        return x, dict(status=STATUS[code], iterations=info.iterations, rel_res=info.rel_res_true,
+                       t_solve_s=info.t_solve_s)
+
+    def solve_noalloc(self, b, x, tol=1e-8, max_iter=1000, stream=None, raise_on_error=True):
+        """amg_pcg_solve_noalloc: device tensors b and x (x iterated in place,
+        holding the initial guess); the library allocates nothing."""
+        info = SolveInfo()
+        code = load().amg_pcg_solve_noalloc(self._h, _dp(b), _dp(x), float(tol), int(max_iter), _stream(stream),
+                                            ctypes.byref(info))
+        if raise_on_error and code != AMG_OK:
+            check(code, "amg_pcg_solve_noalloc")
         return x, dict(status=STATUS[code], iterations=info.iterations, rel_res=info.rel_res_true,
                        t_solve_s=info.t_solve_s)
 

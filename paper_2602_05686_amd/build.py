@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libmatamg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["k_solve.hip", "k_batch.hip", "k_partition.hip", "k_dense.hip", "k_setup.hip", "k_spgemm.hip", "hierarchy.hip", "server.hip",
-           "abi.hip"]
+           "noalloc.hip", "abi.hip"]
 # setup arithmetic that decides drop masks and aggregates: one IEEE op at a time
 NO_CONTRACT = {"k_setup.hip", "k_spgemm.hip"}
 

@@ -305,6 +305,16 @@ amg_status amg_pcg_solve(amg_hierarchy* hh, const double* b, double* x, double t
     });
 }
 
+amg_status amg_pcg_solve_noalloc(amg_hierarchy* hh, const double* b, double* x, double tol, int32_t max_iter,
+                                 void* hip_stream, amg_solve_info* info) {
+    return guarded([&]() -> amg_status {
+        Hierarchy& h = H(hh);
+        if (!b || !x) fail(AMG_ERR_INVALID_ARG, "null b or x");
+        if (!(tol > 0.0) || max_iter < 0) fail(AMG_ERR_INVALID_ARG, "tol must be positive, max_iter >= 0");
+        return pcg_solve_noalloc(h, b, x, tol, max_iter, (hipStream_t)hip_stream, info);
+    });
+}
+
 amg_status amg_update_values(amg_hierarchy* hh, const double* val, amg_ptr_kind kind, void* hip_stream) {
     return guarded([&]() -> amg_status {
         Hierarchy& h = H(hh);

@@ -97,5 +97,11 @@ amg_status pcg_run(Hierarchy& h, const PcgWork& w, const double* b, double tol, 
 // doubles of reduction partials a solve on h needs
 size_t pcg_partials(const Hierarchy& h);
 
+// PCG with its workspace in the library's fixed device array (noalloc.hip):
+// device b and x (x iterated in place), the caller's stream, no allocation
+amg_status pcg_solve_noalloc(Hierarchy& h, const double* b, double* x, double tol, int max_iter, hipStream_t s,
+                             amg_solve_info* info);
+size_t noalloc_need_bytes(const Hierarchy& h);
+size_t noalloc_scratch_bytes();
 
 }  // namespace matamg
