@@ -299,6 +299,7 @@ def run_serving(args, amg, log):
         "mean_latency_s": float(lat.mean()), "max_latency_s": float(lat.max()),
         "solves_per_s": len(reqs) / makespan, "makespan_s": makespan, "served_dof_per_s": sum(dofs) / makespan,
         "status_counts": status, "converged": len(conv),
+        "not_converged_requests": sorted(i for i in range(len(reqs)) if results[i][1]["status"] == "NOT_CONVERGED"),
         # the same figures over the requests that reached the tolerance only
         "converged_only": converged_only,
         "iterations": {"median": float(np.median(iters)), "p90": float(np.percentile(iters, 90)),

@@ -143,9 +143,10 @@ amg_status amg_options_default(amg_options* o);
  * coords     FP64 [n][dim] nodal coordinates
  * opt        options (NULL = defaults with dim 3)
  * out        receives the new hierarchy
- * Errors: INVALID_ARG (bad sizes, unsorted/out-of-range columns, bad options),
- * NOT_SPD (a nodal tensor is not SPD, or the coarse Cholesky fails),
- * COARSENING_STAGNATED, OUT_OF_MEMORY, HIP.  On error *out is NULL.
+ * Errors: INVALID_ARG (bad sizes, unsorted/out-of-range columns, bad options,
+ * a NaN or infinity in val, coords or elem_sigma), NOT_SPD (a nodal tensor is
+ * not SPD, or the coarse Cholesky fails), COARSENING_STAGNATED,
+ * OUT_OF_MEMORY, HIP.  On error *out is NULL.
  */
 amg_status amg_setup(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
                      int64_t nelem, int32_t nodes_per_elem, const int32_t* elem_nodes,
@@ -160,7 +161,9 @@ amg_status amg_setup(int64_t n, const int32_t* rowptr, const int32_t* col, const
  * the iteration continues).  b and x are FP64 [n]; x holds the initial guess
  * on entry and the solution on exit.  The outer CG, its dot products and
  * residual recomputation are FP64 in both precisions.
- * Errors: NOT_CONVERGED, BREAKDOWN (x holds the last iterate), INVALID_ARG.
+ * Errors: NOT_CONVERGED, BREAKDOWN (x holds the last iterate), INVALID_ARG
+ * (null vectors, tol <= 0, max_iter < 0, a NaN or infinity in b or in the
+ * initial guess, or a 2-norm of b that overflows; x is left as it was).
  */
 amg_status amg_pcg_solve(amg_hierarchy* h, const double* b, double* x, double tol, int32_t max_iter,
                          amg_ptr_kind kind, void* hip_stream, amg_solve_info* info);
@@ -186,7 +189,8 @@ amg_status amg_pcg_solve(amg_hierarchy* h, const double* b, double* x, double to
  * any streams, any threads) race and must be serialised by the caller.
  * The call returns after synchronising hip_stream.
  * Errors: INVALID_ARG (null vectors, tol <= 0, max_iter < 0, workspace too
- * small), NOT_CONVERGED, BREAKDOWN, HIP.
+ * small, a NaN or infinity in b or in the initial guess), NOT_CONVERGED,
+ * BREAKDOWN, HIP.
  */
 amg_status amg_pcg_solve_noalloc(amg_hierarchy* h, const double* b, double* x, double tol, int32_t max_iter,
                                  void* hip_stream, amg_solve_info* info);
@@ -208,10 +212,11 @@ amg_status amg_pcg_solve_noalloc(amg_hierarchy* h, const double* b, double* x, d
  * val   FP64 [nnz] values on the rowptr/col pattern given to amg_setup
  * kind  whether val is a host or a device pointer; the call returns after
  *       the update is complete on hip_stream
- * Errors: INVALID_ARG (null arguments, bad kind, or the rows whose
- * off-diagonals are all exactly zero -- the Dirichlet rows -- differ from
- * the setup's; the hierarchy is left unchanged), NOT_SPD (the new coarsest
- * operator is not positive definite; the hierarchy must then be freed), HIP.
+ * Errors: INVALID_ARG (null arguments, bad kind, a NaN or infinity in val,
+ * or the rows whose off-diagonals are all exactly zero -- the Dirichlet
+ * rows -- differ from the setup's; the hierarchy is left unchanged), NOT_SPD
+ * (the new coarsest operator is not positive definite; the hierarchy must
+ * then be freed), HIP.
  * Not to be called while a solve on the same hierarchy is running.
  */
 amg_status amg_update_values(amg_hierarchy* h, const double* val, amg_ptr_kind kind, void* hip_stream);
@@ -322,7 +327,9 @@ typedef struct {
 amg_status amg_server_create(const amg_options* opt, int64_t budget_bytes, int32_t max_active, int32_t setup_workers,
                              amg_server** out);
 /* Arrays as in amg_setup (host memory); b, x0 FP64 [n].  On success
- * *request_id identifies the request.  Errors: INVALID_ARG, BUDGET. */
+ * *request_id identifies the request.  Errors: INVALID_ARG (also for a NaN
+ * or infinity in b or x0; one in the problem arrays is reported as the
+ * request's INVALID_ARG status when its setup runs), BUDGET. */
 amg_status amg_server_submit(amg_server* s, int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
                              int64_t nelem, int32_t nodes_per_elem, const int32_t* elem_nodes,
                              const double* elem_sigma, const double* coords, const double* b, const double* x0,

@@ -64,10 +64,15 @@ def build(force: bool = True) -> str:
 
 
 def lib():
+    """The loaded oracle library: SAAMG_ORACLE_LIB names a prebuilt one (the
+    sanitizer test's instrumented build), else the in-tree build."""
     global _lib
     if _lib is None:
-        build(force=False)
-        L = ctypes.CDLL(_LIB)
+        path = os.environ.get("SAAMG_ORACLE_LIB")
+        if not path:
+            build(force=False)
+            path = _LIB
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i32, i64, f64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
         L.orc_clement.argtypes = [i32, i32, i32, i32, P, P, P]

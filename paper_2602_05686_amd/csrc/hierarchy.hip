@@ -436,6 +436,9 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
     MATAMG_HIP(hipMemcpyAsync(L0.x.get(), coords, sizeof(double) * (size_t)n * dim, kind, s));
     validate_csr(n, L0.A.rowptr.get(), L0.A.col.get(), nnz, flag.get(), s);
     if (read_flag(flag.get(), s)) fail(AMG_ERR_INVALID_ARG, "CSR columns unsorted, duplicated or out of range");
+    check_finite(L0.A.val.get(), nnz, flag.get(), s);
+    check_finite(L0.x.get(), (int64_t)n * dim, flag.get(), s);
+    if (read_flag(flag.get(), s)) fail(AMG_ERR_INVALID_ARG, "a matrix value or a coordinate is not finite");
 
     // ---- Clement nodal tensors
     L0.sig.alloc((size_t)n * ncomp, mc);
@@ -452,6 +455,8 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
             den = en.get();
             des = es.get();
         }
+        check_finite(des, nelem * dim * dim, flag.get(), s);
+        if (read_flag(flag.get(), s)) fail(AMG_ERR_INVALID_ARG, "an element tensor entry is not finite");
         Incidence inc;
         build_node_elements(den, nelem, npe, n, inc, flag.get(), mc, s);
         if (read_flag(flag.get(), s)) fail(AMG_ERR_INVALID_ARG, "element node id out of range");
@@ -608,6 +613,8 @@ void update_values(Hierarchy& h, const double* val, bool host_ptrs, hipStream_t 
         DBuf<double> v(nnz > 0 ? nnz : 1, mc);
         MATAMG_HIP(hipMemcpyAsync(v.get(), val, sizeof(double) * nnz,
                                   host_ptrs ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+        check_finite(v.get(), (int64_t)nnz, flag.get(), s);
+        if (read_flag(flag.get(), s)) fail(AMG_ERR_INVALID_ARG, "a new matrix value is not finite");
         if (h.nlev > 1) {
             DBuf<uint8_t> dir(n > 0 ? n : 1, mc);
             detect_dirichlet(n, L0.A.rowptr.get(), L0.A.col.get(), v.get(), dir.get(), s);
@@ -822,6 +829,9 @@ amg_status pcg_run(Hierarchy& h, const PcgWork& w, const double* b, double tol, 
     dot<double>(b, b, n, w.partial, w.counter, w.scal + S_BB, ws);
     spmv_resid_norm(A, x, b, r, dt(S_RR), ws);
     read_scal();
+    if (!std::isfinite(w.hscal[S_BB]))
+        fail(AMG_ERR_INVALID_ARG, "the right-hand side is not finite (or its 2-norm overflows)");
+    if (!std::isfinite(w.hscal[S_RR])) fail(AMG_ERR_INVALID_ARG, "the initial guess is not finite");
     const double bn = std::sqrt(w.hscal[S_BB]);
     if (bn == 0.0) {
         zero_async(x, sizeof(double) * n, ws);

@@ -813,6 +813,14 @@ __global__ void k_densify(int n, const int* rowptr, const int* col, const double
     }
 }
 
+// *flag = 1 if any of v[0..n) is a NaN or an infinity
+__global__ void k_check_finite(const double* v, int64_t n, int* flag) {
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(v[i]);
+    if (__any(bad) && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
 // eight lanes per row, so neighbouring lanes read neighbouring entries
 __global__ void k_validate_csr(int n, const int* rowptr, const int* col, int64_t nnz, int* flag) {
     const int sub = threadIdx.x & 7;
@@ -999,6 +1007,13 @@ void diag_inverse(int n, const int* rowptr, const int* col, const double* val, d
 
 void densify(int n, const int* rowptr, const int* col, const double* val, double* D, hipStream_t s) {
     LAUNCH(k_densify, n, n, rowptr, col, val, D);
+}
+
+void check_finite(const double* v, int64_t n, int* flag, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_check_finite, dim3(std::min<int64_t>(ceil_div(n, kBlock), 4096)), dim3(kBlock), 0, s, v, n,
+                       flag);
+    MATAMG_LAUNCH_CHECK();
 }
 
 void validate_csr(int n, const int* rowptr, const int* col, int64_t nnz, int* flag, hipStream_t s) {

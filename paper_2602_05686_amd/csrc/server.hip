@@ -319,6 +319,9 @@ amg_status Server::submit(int64_t n, const int* rowptr, const int* col, const do
     if (!(tol > 0.0) || max_iter < 0) fail(AMG_ERR_INVALID_ARG, "submit: tol must be positive, max_iter >= 0");
     const int64_t nnz = rowptr[n];
     if (nnz < 0 || rowptr[0] != 0) fail(AMG_ERR_INVALID_ARG, "submit: bad row pointer");
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(b[i]) || (x0 && !std::isfinite(x0[i])))
+            fail(AMG_ERR_INVALID_ARG, "submit: the right-hand side or the initial guess is not finite");
     const int dim = opt_.dim;
     const int64_t est = estimate_setup_bytes(n, nnz, nelem, npe, dim, opt_.max_coarse);
     if (!adm_.fits_ever(est)) {

@@ -47,6 +47,9 @@ void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, c
                 const uint8_t* state, const int* root_rank, int* phase2, int* agg, int* list, int* nlist,
                 hipStream_t s);
 
+// *flag = 1 (device int) if any value of v[0..n) is not finite
+void check_finite(const double* v, int64_t n, int* flag, hipStream_t s);
+
 // filtered matrix A_F (diagonal + kept entries, lumped diagonal) and its 1-norm
 // diagonal (zero on isolated and empty rows); dir: Dirichlet flags of the level
 void filter_count(const DCsr& A, const uint8_t* mask, int* cnt, hipStream_t s);

@@ -1,7 +1,8 @@
 """Admission policy of the solve server (host-only C++ in
 paper_2602_05686_amd/csrc/admission.h), driven by a small g++ program:
 FIFO order without overtaking, the byte budget and the slot cap, shrinking
-reservations after setup, and the setup-peak estimate's monotonicity."""
+reservations after setup, and the setup-peak estimate's monotonicity; the
+driver is built with AddressSanitizer and UndefinedBehaviorSanitizer."""
 
 import os
 import shutil
@@ -80,7 +81,12 @@ def driver(tmp_path_factory):
     src = d / "adm.cpp"
     src.write_text(DRIVER)
     exe = d / "adm"
-    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    # host code under AddressSanitizer and UndefinedBehaviorSanitizer (no
+    # recovery) where the runtime is installed
+    libasan = subprocess.run(["g++", "-print-file-name=libasan.so"], capture_output=True, text=True).stdout.strip()
+    san = (["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+           if os.path.isabs(libasan) and os.path.exists(libasan) else [])
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-Wall", *san, "-I", CSRC, str(src), "-o", str(exe)], check=True)
     return exe
 
 

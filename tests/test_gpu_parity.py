@@ -308,6 +308,62 @@ def test_error_paths(amg):
     assert info["status"] == "OK" and np.all(x == 0)
 
 
+def test_non_finite_inputs(amg):
+    """A NaN or an infinity in A's values, the coordinates, the element
+    tensors, b or the initial guess is refused with INVALID_ARG (setup,
+    value update, both solves, server submission), and a refused solve
+    leaves x and the hierarchy as they were."""
+    import torch
+
+    banner("non-finite inputs")
+    prob = poisson_box((6, 6), dirichlet="x0")
+    opts = amg.options(dim=2, max_coarse=5)
+    for bad in (np.nan, np.inf, -np.inf):
+        for what in ("val", "coords", "elem_sigma"):
+            arrs = dict(val=prob.val.copy(), coords=prob.coords.copy(), elem_sigma=prob.elem_sigma.copy())
+            arrs[what].reshape(-1)[7] = bad
+            with pytest.raises(amg.AmgError) as e:
+                amg.Hierarchy(prob.rowptr, prob.col, arrs["val"], prob.elem_nodes, arrs["elem_sigma"],
+                              arrs["coords"], opts)
+            assert e.value.status == "INVALID_ARG", (what, bad)
+    h = amg.Hierarchy.from_problem(prob, max_coarse=5)
+    x_ok, i_ok = h.solve(prob.b)
+    for bad in (np.nan, np.inf):
+        b = prob.b.copy()
+        b[3] = bad
+        _, info = h.solve(b, raise_on_error=False)
+        assert info["status"] == "INVALID_ARG"
+        x0 = np.zeros(prob.n)
+        x0[5] = bad
+        _, info = h.solve(prob.b, x0=x0, raise_on_error=False)
+        assert info["status"] == "INVALID_ARG"
+        bt = torch.from_numpy(b).cuda()
+        xt = torch.full((prob.n,), 0.25, dtype=torch.float64, device="cuda")
+        _, info = h.solve(bt, xt, raise_on_error=False)
+        assert info["status"] == "INVALID_ARG" and bool(torch.all(xt == 0.25))
+        _, info = h.solve_noalloc(bt, xt, raise_on_error=False)
+        assert info["status"] == "INVALID_ARG"
+        v = prob.val.copy()
+        v[11] = bad
+        with pytest.raises(amg.AmgError) as e:
+            h.update_values(v)
+        assert e.value.status == "INVALID_ARG"
+    # the hierarchy still solves exactly as before
+    x, info = h.solve(prob.b)
+    assert info["iterations"] == i_ok["iterations"] and np.array_equal(x, x_ok)
+    with amg.Server(budget_bytes=1 << 30, max_active=2, dim=2, max_coarse=5) as srv:
+        b = prob.b.copy()
+        b[0] = np.nan
+        with pytest.raises(amg.AmgError) as e:
+            srv.submit(prob, b=b)
+        assert e.value.status == "INVALID_ARG"
+        x0 = np.zeros(prob.n)
+        x0[1] = np.inf
+        with pytest.raises(amg.AmgError) as e:
+            srv.submit(prob, x0=x0)
+        assert e.value.status == "INVALID_ARG"
+
+
 def test_device_partition_equals_host_walk(amg, monkeypatch):
     """Every matrix's row-block partition computed on the device (pointer
     doubling over the greedy walk's successor map) equals the host walk."""
