@@ -171,6 +171,10 @@ class DBuf {
     bool pooled_ = false;
 };
 
+// distinct-column runs kept per streaming block (see DCsr::urun)
+constexpr int kMaxRuns = 6;
+constexpr int kRunWords = kMaxRuns + 2;
+
 // CSR matrix resident on the device
 struct DCsr {
     int n = 0, m = 0;
@@ -191,6 +195,19 @@ struct DCsr {
     DBuf<uint16_t> col16;
     DBuf<int> cbase;
     int cap = 2048;  // most stored entries in one streaming block (kStreamCap or kStreamCapWide)
+    // distinct columns of each packed streaming block, for staging the
+    // gathered vector in LDS: block b's distinct packed columns, ascending,
+    // are uoff[ustart[b] .. ustart[b+1]), and its entries' col16 then hold
+    // indices into that list.  An empty list (more than unique_cap(cap)
+    // distinct columns, or a block of one long row) leaves the block's col16
+    // as column offsets, gathered from memory.
+    DBuf<int> ustart;
+    DBuf<uint16_t> uoff;
+    int64_t nuniq = 0;  // total length of the lists
+    // blocks whose distinct columns form at most kMaxRuns runs of consecutive
+    // columns keep the runs instead of a list: urun[kRunWords b ..] = {runs,
+    // distinct columns, then start | length << 16 per run}; runs = 0: none
+    DBuf<uint32_t> urun;
     // the setup kernels' row blocks (at most kStreamCap entries) when the
     // streaming blocks above were widened; otherwise they share blk
     DBuf<int> sblk;
@@ -199,6 +216,10 @@ struct DCsr {
     int setup_nblk() const { return sblk ? snblk : nblk; }
     // column bytes per stored entry the streaming kernels read
     double col_bytes() const { return col16 ? 2.0 : 4.0; }
+    // bytes of the distinct-column lists and their block table
+    double unique_bytes() const {
+        return (ustart ? 2.0 * (double)nuniq + 4.0 * (nblk + 1) : 0.0) + (urun ? 4.0 * kRunWords * nblk : 0.0);
+    }
 };
 
 constexpr int kBlock = 256;          // threads per block in streaming kernels
@@ -206,6 +227,11 @@ constexpr int kStreamCap = 2048;     // nnz staged in LDS per streaming block
 // wider streaming blocks for large one-thread-per-row packed matrices: twice
 // the bytes per workgroup (the setup kernels keep kStreamCap blocks)
 constexpr int kStreamCapWide = 4096;
+// most distinct columns of a streaming block of capacity `cap` staged in LDS
+// (in the block's product array), and the reuse a block needs to be staged:
+// at most kUniqueReusePct percent as many distinct columns as entries
+constexpr int unique_cap(int cap) { return cap / 2; }
+constexpr int kUniqueReusePct = 70;
 constexpr int kWideBlockMin = 12000;  // widen a matrix with at least this many kStreamCap blocks
 constexpr int kMaxRowsPerBlock = kBlock;
 constexpr int kLongRow = 96;         // setup kernels: longer single-row blocks take the whole-block path

@@ -67,9 +67,12 @@ int wide_block_min() {
 
 void widen_stream_blocks(DCsr& A, MemCounter* mc, hipStream_t s) {
     if (A.group != 1 || !A.col16 || A.cap != kStreamCap || A.nblk < wide_block_min()) return;
-    DBuf<int> blk = std::move(A.blk), blkk = std::move(A.blkk), cbase = std::move(A.cbase);
-    DBuf<uint16_t> col16 = std::move(A.col16);
+    DBuf<int> blk = std::move(A.blk), blkk = std::move(A.blkk), cbase = std::move(A.cbase),
+              ustart = std::move(A.ustart);
+    DBuf<uint16_t> col16 = std::move(A.col16), uoff = std::move(A.uoff);
+    DBuf<uint32_t> urun = std::move(A.urun);
     const int nblk = A.nblk;
+    const int64_t nuniq = A.nuniq;
     make_blocks(A, mc, s, true, kStreamCapWide);
     if (A.col16 && A.group == 1) {
         A.sblk = std::move(blk);
@@ -81,6 +84,10 @@ void widen_stream_blocks(DCsr& A, MemCounter* mc, hipStream_t s) {
     A.blkk = std::move(blkk);
     A.cbase = std::move(cbase);
     A.col16 = std::move(col16);
+    A.ustart = std::move(ustart);
+    A.uoff = std::move(uoff);
+    A.urun = std::move(urun);
+    A.nuniq = nuniq;
     A.nblk = nblk;
     A.group = 1;
     A.cap = kStreamCap;
@@ -243,7 +250,7 @@ double Hierarchy::time_smoother(int level, int reps, hipStream_t s, double* byte
     // written
     if (bytes_per_launch)
         *bytes_per_launch = (double)L.A.nnz * (sz + L.A.col_bytes()) + 4.0 * (L.A.n + 1) +
-                            (L.A.col16 ? 4.0 * L.A.nblk : 0.0) + 6.0 * sz * L.A.n;
+                            (L.A.col16 ? 4.0 * L.A.nblk : 0.0) + L.A.unique_bytes() + 6.0 * sz * L.A.n;
     return ms_total / reps;
 }
 
@@ -752,7 +759,8 @@ double Hierarchy::vcycle_alg_bytes() const {
         // a matrix: values, columns as stored for the streaming kernels (4
         // bytes, or 2 when packed, plus one base per row block), row pointer
         auto matrix = [&](const DCsr& M) {
-            return (double)M.nnz * (s + M.col_bytes()) + 4.0 * (M.n + 1) + (M.col16 ? 4.0 * M.nblk : 0.0);
+            return (double)M.nnz * (s + M.col_bytes()) + 4.0 * (M.n + 1) + (M.col16 ? 4.0 * M.nblk : 0.0) +
+                   M.unique_bytes();
         };
         // smoother SpMVs: (steps-1) pre + steps post; one residual SpMV
         const double n_spmv = (steps - 1.0) + steps + 1.0;

@@ -189,6 +189,165 @@ __global__ __launch_bounds__(kBlock) void k_pack_cols(int nblk, const int* rp, c
     }
 }
 
+// Distinct packed columns of a block: a bitmap over the 2^16 offsets a
+// packed block can hold (2048 words in LDS), set by the block's entries.
+constexpr int kColWords = 65536 / 32;
+
+__device__ __forceinline__ bool long_row_block(int r0, int r1, int k0, int k1, int group) {
+    return r1 - r0 == 1 && k1 - k0 > long_row_limit(group);
+}
+
+__device__ __forceinline__ void mark_columns(unsigned* bits, const uint16_t* col16, int k0, int k1) {
+    for (int w = threadIdx.x; w < kColWords; w += kBlock) bits[w] = 0u;
+    __syncthreads();
+    for (int k = k0 + (int)threadIdx.x; k < k1; k += kBlock) {
+        const unsigned c = col16[k];
+        atomicOr(&bits[c >> 5], 1u << (c & 31u));
+    }
+    __syncthreads();
+}
+
+// exclusive prefix over the block's threads of v (block-wide, 256 threads);
+// *total receives the sum
+__device__ __forceinline__ int block_exclusive(int v, int* red, int* total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) red[wv] = incl;
+    __syncthreads();
+    int woff = 0, tot = 0;
+    for (int i = 0; i < kBlock / 64; ++i) {
+        if (i < wv) woff += red[i];
+        tot += red[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return woff + incl - v;
+}
+
+// Per block b: the number of distinct columns and of runs of consecutive
+// columns among them.  A block is staged when it is not one long row, has
+// at most ucap distinct columns and at most kUniqueReusePct percent as many
+// as entries (too little reuse does not pay for the staging).  A staged
+// block with at most kMaxRuns runs gets its run record (urun); any other
+// staged block a list of ucnt[b] = its distinct count (0 otherwise).
+__global__ __launch_bounds__(kBlock) void k_block_uniques_count(int nblk, const int* blk, const int* blkk,
+                                                                const uint16_t* col16, int group, int ucap,
+                                                                int* ucnt, uint32_t* urun) {
+    __shared__ unsigned bits[kColWords];
+    __shared__ int red[kBlock / 64];
+    __shared__ int rs[kMaxRuns], re[kMaxRuns];
+    constexpr int kPer = kColWords / kBlock;  // words per thread, contiguous
+    for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int r0 = blk[b], r1 = blk[b + 1], k0 = blkk[b], k1 = blkk[b + 1];
+        const bool skip = long_row_block(r0, r1, k0, k1, group);
+        mark_columns(bits, col16, k0, skip ? k0 : k1);
+        int c = 0, ns = 0, ne = 0;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int w = threadIdx.x * kPer + i;
+            const unsigned m = bits[w];
+            const unsigned prev = w > 0 ? bits[w - 1] >> 31 : 0u;
+            const unsigned next = w + 1 < kColWords ? (bits[w + 1] & 1u) << 31 : 0u;
+            c += __popc(m);
+            ns += __popc(m & ~((m << 1) | prev));
+            ne += __popc(m & ~((m >> 1) | next));
+        }
+        int total = 0, runs = 0, tmp = 0;
+        (void)block_exclusive(c, red, &total);
+        const int s0 = block_exclusive(ns, red, &runs);
+        const int e0 = block_exclusive(ne, red, &tmp);
+        const bool staged = !skip && total <= ucap && total * 100 <= kUniqueReusePct * (k1 - k0) && total > 0;
+        const bool use_runs = staged && runs <= kMaxRuns;
+        if (use_runs) {
+            // the run starts and ends in column order (threads own contiguous words)
+            int si = s0, ei = e0;
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int w = threadIdx.x * kPer + i;
+                const unsigned m = bits[w];
+                const unsigned prev = w > 0 ? bits[w - 1] >> 31 : 0u;
+                const unsigned next = w + 1 < kColWords ? (bits[w + 1] & 1u) << 31 : 0u;
+                unsigned st = m & ~((m << 1) | prev), en = m & ~((m >> 1) | next);
+                while (st) {
+                    rs[si++] = w * 32 + __builtin_ctz(st);
+                    st &= st - 1u;
+                }
+                while (en) {
+                    re[ei++] = w * 32 + __builtin_ctz(en);
+                    en &= en - 1u;
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kRunWords) {
+            uint32_t word = 0u;
+            if (use_runs) {
+                const int t = (int)threadIdx.x;
+                if (t == 0) word = (uint32_t)runs;
+                else if (t == 1) word = (uint32_t)total;
+                else if (t - 2 < runs) word = (uint32_t)rs[t - 2] | ((uint32_t)(re[t - 2] - rs[t - 2] + 1) << 16);
+            }
+            urun[(size_t)b * kRunWords + threadIdx.x] = word;
+        }
+        if (threadIdx.x == 0) ucnt[b] = (staged && !use_runs) ? total : 0;
+        __syncthreads();
+    }
+}
+
+// the lists (ascending offsets) and every staged entry's index into its
+// block's distinct columns (list or runs: the same ascending order)
+__global__ __launch_bounds__(kBlock) void k_block_uniques_fill(int nblk, const int* blkk, const int* ustart,
+                                                               const uint32_t* urun, uint16_t* col16,
+                                                               uint16_t* uoff) {
+    __shared__ unsigned bits[kColWords];
+    __shared__ int wpre[kColWords];
+    __shared__ int red[kBlock / 64];
+    constexpr int kPer = kColWords / kBlock;  // words per thread
+    for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const int u0 = ustart[b];
+        const bool list = ustart[b + 1] > u0;
+        if (!list && urun[(size_t)b * kRunWords] == 0u) continue;  // block-uniform: not staged
+        const int k0 = blkk[b], k1 = blkk[b + 1];
+        mark_columns(bits, col16, k0, k1);
+        // exclusive prefix of the set-bit counts over the words, thread t
+        // owning words [t kPer, (t + 1) kPer)
+        int loc[kPer];
+        int sum = 0;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            loc[i] = sum;
+            sum += __popc(bits[threadIdx.x * kPer + i]);
+        }
+        int tot = 0;
+        const int base = block_exclusive(sum, red, &tot);
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int w = threadIdx.x * kPer + i;
+            wpre[w] = base + loc[i];
+            if (list) {
+                unsigned m = bits[w];
+                int r = base + loc[i];
+                while (m) {
+                    uoff[u0 + r] = (uint16_t)(w * 32 + __builtin_ctz(m));
+                    ++r;
+                    m &= m - 1u;
+                }
+            }
+        }
+        __syncthreads();
+        for (int k = k0 + (int)threadIdx.x; k < k1; k += kBlock) {
+            const unsigned c = col16[k];
+            const unsigned m = bits[c >> 5] & ((1u << (c & 31u)) - 1u);
+            col16[k] = (uint16_t)(wpre[c >> 5] + __popc(m));
+        }
+        __syncthreads();
+    }
+}
+
 // blkk[b] = rp[blk[b]] for b <= nblk
 __global__ void k_block_entries(int nblk, const int* rp, const int* blk, int* blkk) {
     FOR_ROWS(b, (int64_t)nblk + 1) blkk[b] = rp[blk[b]];
@@ -200,6 +359,10 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack, int cap
     const int n = A.n;
     A.col16.release();
     A.cbase.release();
+    A.ustart.release();
+    A.uoff.release();
+    A.urun.release();
+    A.nuniq = 0;
     A.sblk.release();
     A.snblk = 0;
     A.cap = cap;
@@ -275,7 +438,33 @@ void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack, int cap
         hipLaunchKernelGGL(k_pack_cols, dim3(std::min(nblk, 65535)), dim3(kBlock), 0, s, nblk, rp, A.col.get(),
                            (const int*)A.blk.get(), (const int*)A.cbase.get(), A.col16.get());
         MATAMG_LAUNCH_CHECK();
+        block_uniques(A, mc, s);
     }
+}
+
+void block_uniques(DCsr& A, MemCounter* mc, hipStream_t s) {
+    A.ustart.release();
+    A.uoff.release();
+    A.urun.release();
+    A.nuniq = 0;
+    const int nblk = A.nblk;
+    if (!A.col16 || nblk <= 0) return;
+    DBuf<int> cnt((size_t)nblk + 1, mc), tmp(scan_tmp_size((int64_t)nblk + 1), mc);
+    A.urun.alloc((size_t)nblk * kRunWords, mc);
+    const int grid = std::min(nblk, 8192);
+    hipLaunchKernelGGL(k_block_uniques_count, dim3(grid), dim3(kBlock), 0, s, nblk, (const int*)A.blk.get(),
+                       (const int*)A.blkk.get(), (const uint16_t*)A.col16.get(), A.group, unique_cap(A.cap),
+                       cnt.get(), A.urun.get());
+    MATAMG_LAUNCH_CHECK();
+    A.ustart.alloc((size_t)nblk + 1, mc);
+    exclusive_scan(cnt.get(), A.ustart.get(), nblk, tmp.get(), s);
+    int total = 0;
+    d2h(&total, A.ustart.get() + nblk, 1, s);
+    A.nuniq = total;
+    A.uoff.alloc((size_t)(total > 0 ? total : 1), mc);
+    hipLaunchKernelGGL(k_block_uniques_fill, dim3(grid), dim3(kBlock), 0, s, nblk, (const int*)A.blkk.get(),
+                       (const int*)A.ustart.get(), (const uint32_t*)A.urun.get(), A.col16.get(), A.uoff.get());
+    MATAMG_LAUNCH_CHECK();
 }
 
 }  // namespace matamg

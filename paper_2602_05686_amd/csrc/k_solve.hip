@@ -274,6 +274,9 @@ SArgs<T> base_args(const DCsr& A, const T* val, const T* x) {
     a.val = val;
     a.blk = A.blk.get();
     a.blkk = A.blkk.get();
+    a.ustart = A.ustart.get();
+    a.uoff = A.uoff.get();
+    a.urun = A.urun.get();
     a.x = x;
     return a;
 }

@@ -31,6 +31,8 @@ int stream_group(const int* rowptr_host, int n);
 // synchronised once
 // (blocks of at most `cap` stored entries; A.cap records it)
 void stream_partition(DCsr& A, MemCounter* mc, hipStream_t s, bool pack, int cap = kStreamCap);
+// the distinct-column lists of A's packed streaming blocks (see DCsr::ustart)
+void block_uniques(DCsr& A, MemCounter* mc, hipStream_t s);
 
 // dot partials of a streaming launch: one per row block
 constexpr int kStreamPartials = 1;  // dot partials per streaming block

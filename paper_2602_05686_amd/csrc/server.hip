@@ -74,6 +74,9 @@ SArgs<T> sargs(const DCsr& M, const T* val, const T* x) {
     a.val = val;
     a.blk = M.blk.get();
     a.blkk = M.blkk.get();
+    a.ustart = M.ustart.get();
+    a.uoff = M.uoff.get();
+    a.urun = M.urun.get();
     a.x = x;
     return a;
 }

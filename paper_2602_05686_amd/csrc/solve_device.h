@@ -37,6 +37,9 @@ struct SArgs {
     const T* val;
     const int* blk;
     const int* blkk;   // first entry of each block (rowptr at its first row)
+    const int* ustart;       // packed blocks' distinct-column lists (or null):
+    const uint16_t* uoff;    // block b's are uoff[ustart[b] .. ustart[b+1])
+    const uint32_t* urun;    // or their runs (DCsr::urun; null: none)
     const T* x;        // gathered operand
     const T* b;        // right-hand side (RESID, SMOOTH, RESNORM)
     const T* yin;      // ADD: base vector; SMOOTH: iterate at the row
@@ -114,7 +117,8 @@ __device__ __forceinline__ double epilogue(const SArgs<T>& a, int r, T s, const 
 
 constexpr int kPerThread = kStreamCap / kBlock;
 
-// LDS of one streaming block of at most CAP stored entries
+// LDS of one streaming block of at most CAP stored entries: the products
+// (first holding the block's distinct gathered values), reduction scratch
 template <typename T, int CAP = kStreamCap>
 struct StreamShared {
     T prod[CAP];
@@ -144,7 +148,7 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int stage_head(int k0, int cnt) { return cnt > 0 ? (k0 & 1) : 0; }
 
-template <typename T, int NP>
+template <typename T, int NP, int UQ>
 __device__ __forceinline__ void stage_pairs(const SArgs<T>& a, int bid, int k0, int cnt, T* prod) {
     using P2 = typename PairOf<T>::type;
     const int base = a.cbase[bid];
@@ -153,6 +157,12 @@ __device__ __forceinline__ void stage_pairs(const SArgs<T>& a, int bid, int k0, 
     const int np = body >> 1;  // whole pairs from the even position k0 + head
     const int kp = k0 + head;
     const int tid = (int)threadIdx.x;
+    // the block's distinct columns (block-uniform): runs, a list, or none
+    // (gathers)
+    const uint32_t* rec = a.urun ? a.urun + (size_t)bid * kRunWords : nullptr;
+    const int nruns = rec ? (int)rec[0] : 0;
+    const int u0 = a.ustart ? a.ustart[bid] : 0;
+    const int nu = nruns > 0 ? (int)rec[1] : (a.ustart ? a.ustart[bid + 1] - u0 : 0);
     u16x2 c[NP > 0 ? NP : 1];
     P2 v[NP > 0 ? NP : 1];
 #pragma unroll
@@ -169,16 +179,67 @@ __device__ __forceinline__ void stage_pairs(const SArgs<T>& a, int bid, int k0, 
     int cs = 0;
     T vs = 0;
     if (ts >= 0) {
-        cs = base + (int)a.col16[k0 + ts];
+        cs = (int)a.col16[k0 + ts];
         vs = a.val[k0 + ts];
     }
     T x0[NP > 0 ? NP : 1], x1[NP > 0 ? NP : 1];
+    T xsng = T(0);
+    if (UQ > 0 && nu > 0) {
+        // the block's distinct values of the gathered vector, read in
+        // ascending column order (coalesced along the list), staged in the
+        // product array (nu <= unique_cap(CAP) <= CAP entries); the entries'
+        // col16 index the list.  Every thread takes its values into
+        // registers before the products overwrite the array.
+        T* xs = prod;
+        int off[UQ > 0 ? UQ : 1];
+        if (nruns > 0) {
+            // list index j lies in the run whose prefix of lengths it reaches
+            uint32_t rw[kMaxRuns];
 #pragma unroll
-    for (int u = 0; u < NP; ++u) {
-        x0[u] = a.x[base + (int)c[u].x];
-        x1[u] = a.x[base + (int)c[u].y];
+            for (int r = 0; r < kMaxRuns; ++r) rw[r] = rec[2 + r];
+#pragma unroll
+            for (int q = 0; q < UQ; ++q) {
+                const int j0 = tid + q * kBlock;
+                const int j = j0 < nu ? j0 : nu - 1;
+                int pos = (int)(rw[0] & 0xffffu) + j, pre = 0;
+#pragma unroll
+                for (int r = 0; r < kMaxRuns - 1; ++r) {
+                    pre += (int)(rw[r] >> 16);
+                    if (r + 1 < nruns && j >= pre) pos = (int)(rw[r + 1] & 0xffffu) + (j - pre);
+                }
+                off[q] = pos;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < UQ; ++q) {
+                const int j = tid + q * kBlock;
+                off[q] = (int)a.uoff[u0 + (j < nu ? j : nu - 1)];
+            }
+        }
+        T xv[UQ > 0 ? UQ : 1];
+#pragma unroll
+        for (int q = 0; q < UQ; ++q) xv[q] = a.x[base + off[q]];
+#pragma unroll
+        for (int q = 0; q < UQ; ++q) {
+            const int j = tid + q * kBlock;
+            if (j < nu) xs[j] = xv[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            x0[u] = xs[(int)c[u].x];
+            x1[u] = xs[(int)c[u].y];
+        }
+        if (ts >= 0) xsng = xs[cs];
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            x0[u] = a.x[base + (int)c[u].x];
+            x1[u] = a.x[base + (int)c[u].y];
+        }
+        if (ts >= 0) xsng = a.x[base + cs];
     }
-    const T xs = ts >= 0 ? a.x[cs] : T(0);
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
         const int p = tid + u * kBlock;
@@ -187,7 +248,7 @@ __device__ __forceinline__ void stage_pairs(const SArgs<T>& a, int bid, int k0, 
             prod[head + 2 * p + 1] = v[u].y * x1[u];
         }
     }
-    if (ts >= 0) prod[ts] = vs * xs;
+    if (ts >= 0) prod[ts] = vs * xsng;
 }
 
 template <typename T, int NU, bool PACKED>
@@ -260,21 +321,22 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
         // ceil(cnt / kBlock) strides of the block's entries (block-uniform),
         // from packed or plain columns (uniform per matrix)
         const int nu = (cnt + kBlock - 1) / kBlock;
+        constexpr int kUQ = unique_cap(CAP) / kBlock;  // distinct values per thread
         if (a.col16) {
             // pairs of entries: ceil(pairs / kBlock) strides (block-uniform)
             switch (((cnt - stage_head(k0, cnt)) / 2 + kBlock - 1) / kBlock) {
-                case 0: stage_pairs<T, 0>(a, bid, k0, cnt, S.prod); break;
-                case 1: stage_pairs<T, 1>(a, bid, k0, cnt, S.prod); break;
-                case 2: stage_pairs<T, 2>(a, bid, k0, cnt, S.prod); break;
-                case 3: stage_pairs<T, 3>(a, bid, k0, cnt, S.prod); break;
-                case 4: stage_pairs<T, 4>(a, bid, k0, cnt, S.prod); break;
+                case 0: stage_pairs<T, 0, kUQ>(a, bid, k0, cnt, S.prod); break;
+                case 1: stage_pairs<T, 1, kUQ>(a, bid, k0, cnt, S.prod); break;
+                case 2: stage_pairs<T, 2, kUQ>(a, bid, k0, cnt, S.prod); break;
+                case 3: stage_pairs<T, 3, kUQ>(a, bid, k0, cnt, S.prod); break;
+                case 4: stage_pairs<T, 4, kUQ>(a, bid, k0, cnt, S.prod); break;
                 default:
                     if constexpr (CAP > kStreamCap) {
                         switch (((cnt - stage_head(k0, cnt)) / 2 + kBlock - 1) / kBlock) {
-                            case 5: stage_pairs<T, 5>(a, bid, k0, cnt, S.prod); break;
-                            case 6: stage_pairs<T, 6>(a, bid, k0, cnt, S.prod); break;
-                            case 7: stage_pairs<T, 7>(a, bid, k0, cnt, S.prod); break;
-                            case 8: stage_pairs<T, 8>(a, bid, k0, cnt, S.prod); break;
+                            case 5: stage_pairs<T, 5, kUQ>(a, bid, k0, cnt, S.prod); break;
+                            case 6: stage_pairs<T, 6, kUQ>(a, bid, k0, cnt, S.prod); break;
+                            case 7: stage_pairs<T, 7, kUQ>(a, bid, k0, cnt, S.prod); break;
+                            case 8: stage_pairs<T, 8, kUQ>(a, bid, k0, cnt, S.prod); break;
                             default: break;
                         }
                     }
