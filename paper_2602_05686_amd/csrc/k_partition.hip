@@ -236,7 +236,7 @@ __device__ __forceinline__ int block_exclusive(int v, int* red, int* total) {
 // staged block a list of ucnt[b] = its distinct count (0 otherwise).
 __global__ __launch_bounds__(kBlock) void k_block_uniques_count(int nblk, const int* blk, const int* blkk,
                                                                 const uint16_t* col16, int group, int ucap,
-                                                                int* ucnt, uint32_t* urun) {
+                                                                int* ucnt, uint32_t* urun, int* nstaged) {
     __shared__ unsigned bits[kColWords];
     __shared__ int red[kBlock / 64];
     __shared__ int rs[kMaxRuns], re[kMaxRuns];
@@ -293,7 +293,10 @@ __global__ __launch_bounds__(kBlock) void k_block_uniques_count(int nblk, const 
             }
             urun[(size_t)b * kRunWords + threadIdx.x] = word;
         }
-        if (threadIdx.x == 0) ucnt[b] = (staged && !use_runs) ? total : 0;
+        if (threadIdx.x == 0) {
+            ucnt[b] = (staged && !use_runs) ? total : 0;
+            if (staged) atomicAdd(nstaged, 1);
+        }
         __syncthreads();
     }
 }
@@ -449,17 +452,26 @@ void block_uniques(DCsr& A, MemCounter* mc, hipStream_t s) {
     A.nuniq = 0;
     const int nblk = A.nblk;
     if (!A.col16 || nblk <= 0) return;
-    DBuf<int> cnt((size_t)nblk + 1, mc), tmp(scan_tmp_size((int64_t)nblk + 1), mc);
+    DBuf<int> cnt((size_t)nblk + 2, mc), tmp(scan_tmp_size((int64_t)nblk + 1), mc);
     A.urun.alloc((size_t)nblk * kRunWords, mc);
+    zero_async(cnt.get() + nblk + 1, sizeof(int), s);
     const int grid = std::min(nblk, 8192);
     hipLaunchKernelGGL(k_block_uniques_count, dim3(grid), dim3(kBlock), 0, s, nblk, (const int*)A.blk.get(),
                        (const int*)A.blkk.get(), (const uint16_t*)A.col16.get(), A.group, unique_cap(A.cap),
-                       cnt.get(), A.urun.get());
+                       cnt.get(), A.urun.get(), cnt.get() + nblk + 1);
     MATAMG_LAUNCH_CHECK();
     A.ustart.alloc((size_t)nblk + 1, mc);
     exclusive_scan(cnt.get(), A.ustart.get(), nblk, tmp.get(), s);
-    int total = 0;
-    d2h(&total, A.ustart.get() + nblk, 1, s);
+    int res[2] = {0, 0};  // list length, staged blocks
+    MATAMG_HIP(hipMemcpyAsync(cnt.get() + nblk, A.ustart.get() + nblk, sizeof(int), hipMemcpyDeviceToDevice, s));
+    d2h(res, cnt.get() + nblk, 2, s);
+    const int total = res[0];
+    if (res[1] == 0) {
+        // nothing staged: the streaming kernels read no per-block tables
+        A.ustart.release();
+        A.urun.release();
+        return;
+    }
     A.nuniq = total;
     A.uoff.alloc((size_t)(total > 0 ? total : 1), mc);
     hipLaunchKernelGGL(k_block_uniques_fill, dim3(grid), dim3(kBlock), 0, s, nblk, (const int*)A.blkk.get(),

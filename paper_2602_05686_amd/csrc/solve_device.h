@@ -315,9 +315,25 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
         const int rc = owner ? r : r1 - 1;
         const int e0 = a.rowptr[rc], e1 = a.rowptr[rc + 1];
         // one thread per row: every thread prefetches its row's operands;
-        // with G > 1 only the row's first thread needs them, after the sum
+        // with G > 1 every thread prefetches the row bounds of its group's
+        // rows_per_group(G) rows and the group's first thread their operands,
+        // so that none of these loads waits behind the reduction
         RowOperands<T> ops{};
         if constexpr (G == 1) ops = row_operands<T, MODE>(a, rc);
+        constexpr int RQ = G == 1 ? 1 : rows_per_group(G);
+        int gf0[RQ], gf1[RQ];
+        RowOperands<T> gops[RQ];
+        if constexpr (G > 1) {
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) {
+                const int rq = r + q * (kBlock / G);
+                const int rqc = rq < r1 ? rq : r1 - 1;
+                gf0[q] = a.rowptr[rqc] - k0;
+                gf1[q] = a.rowptr[rqc + 1] - k0;
+                gops[q] = RowOperands<T>{};
+                if (gl == 0) gops[q] = row_operands<T, MODE>(a, rqc);
+            }
+        }
         // ceil(cnt / kBlock) strides of the block's entries (block-uniform),
         // from packed or plain columns (uniform per matrix)
         const int nu = (cnt + kBlock - 1) / kBlock;
@@ -388,15 +404,13 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
             // G threads per row, rows_per_group(G) rows per group: strided
             // partial sums, then a fixed shuffle tree, row after row
 #pragma unroll
-            for (int q = 0; q < rows_per_group(G); ++q) {
+            for (int q = 0; q < RQ; ++q) {
                 const int rq = r + q * (kBlock / G);
                 const bool own = rq < r1;
-                const int rqc = own ? rq : r1 - 1;
-                const int f0 = a.rowptr[rqc] - k0, f1 = a.rowptr[rqc + 1] - k0;
                 T s = 0;
-                if (own) s = ordered_sum<T, G>(S.prod, f0 + gl, f1, s);
+                if (own) s = ordered_sum<T, G>(S.prod, gf0[q] + gl, gf1[q], s);
                 for (int off = G / 2; off > 0; off >>= 1) s += __shfl_down(s, off, G);
-                if (gl == 0 && own) dp += epilogue<T, MODE, HAS_DOT>(a, rq, s, row_operands<T, MODE>(a, rq));
+                if (gl == 0 && own) dp += epilogue<T, MODE, HAS_DOT>(a, rq, s, gops[q]);
             }
         }
     } else {
