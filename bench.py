@@ -47,7 +47,7 @@ def measured_traffic():
     once they have changed."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "c2_fine_smoother_traffic.md")
+    path = os.path.join(ROOT, "profiles", "fine_smoother_layered128_traffic.md")
     try:
         kv = {}
         for line in open(path):
@@ -620,6 +620,11 @@ def main():
     ap.add_argument("--c4-max-iter", type=int, default=4000, help="PCG iteration cap on the 192^3 stack")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="one setup, a few V-cycles and a 1 GiB device copy (for counter collection), no JSON")
+    ap.add_argument("--profile-precision", choices=("fp64", "fp32"), default="fp64",
+                    help="--profile-kernels: precision form of the hierarchy")
+    ap.add_argument("--profile-workload", choices=("layered", "aniso"), default="layered",
+                    help="--profile-kernels: the layered stack (--n) or the rotated-anisotropy cube (--aniso-n)")
+    ap.add_argument("--profile-vcycles", type=int, default=3, help="--profile-kernels: V-cycles after the setup")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--aniso-n", type=int, default=96,
                     help="hexes per side of the rotated-anisotropy FP32/FP64 comparison (0: skip)")
@@ -681,8 +686,14 @@ def main():
         print(json.dumps(run_reuse(args, amg, log)), flush=True)
         return
 
-    log(f"generating layered stack {args.n}^3, {args.repeats} repeats, {args.stretch:g}:1")
-    prob = layered_stack_3d(n=args.n, repeats=args.repeats, stretch=args.stretch)
+    if args.profile_kernels and args.profile_workload == "aniso":
+        from workloads import rotated_anisotropic_3d
+
+        log(f"generating rotated-anisotropy cube {args.aniso_n}^3")
+        prob = rotated_anisotropic_3d(n=args.aniso_n, block=8)
+    else:
+        log(f"generating layered stack {args.n}^3, {args.repeats} repeats, {args.stretch:g}:1")
+        prob = layered_stack_3d(n=args.n, repeats=args.repeats, stretch=args.stretch)
     n = prob.n
     d = dict(rowptr=torch.from_numpy(prob.rowptr).to(dev), col=torch.from_numpy(prob.col).to(dev),
              val=torch.from_numpy(prob.val).to(dev), en=torch.from_numpy(prob.elem_nodes).to(dev),
@@ -704,10 +715,14 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        h = amg.Hierarchy(d["rowptr"], d["col"], d["val"], d["en"], d["es"], d["xc"], opts64)
+        opts = amg.options(dim=3, max_levels=args.max_levels, precision=args.profile_precision)
+        h = amg.Hierarchy(d["rowptr"], d["col"], d["val"], d["en"], d["es"], d["xc"], opts)
+        st = h.stats()
+        for lv in range(st["levels"]):
+            log(f"level {lv}: n {st['n'][lv]}, nnz {st['nnz'][lv]}, nnz(P) {st['nnz_p'][lv]}")
         r = torch.randn(n, dtype=torch.float64, device=dev)
         z = torch.zeros_like(r)
-        for _ in range(3):
+        for _ in range(args.profile_vcycles):
             h.vcycle(r, z)
         torch.cuda.synchronize()
         h.close()

@@ -232,7 +232,18 @@ constexpr int kStreamCapWide = 4096;
 // at most kUniqueReusePct percent as many distinct columns as entries
 constexpr int unique_cap(int cap) { return cap / 2; }
 constexpr int kUniqueReusePct = 70;
-constexpr int kWideBlockMin = 12000;  // widen a matrix with at least this many kStreamCap blocks
+// Widen a matrix's streaming blocks to kStreamCapWide when it has at least
+// this many kStreamCap blocks.  A wide FP64 block's products take 32 KB of
+// LDS, which halves the blocks a CU holds, and pays only on the largest
+// operators; the finest operator (streamed by the FP64 outer CG in both
+// forms) widens a little earlier.  A wide FP32 block takes the LDS of a
+// narrow FP64 one, so the coarse operators of the FP32 form, streamed only
+// in FP32, widen at half the size (measured on the 128^3 stack and the
+// 96^3 cube: the fine FP32 smoother of the cube, 11.6k blocks, from 35.6 to
+// 30.2 us; FP64 operators of 6.5k to 9.8k blocks 7 to 20% slower wide).
+constexpr int kWideBlockMin = 12000;
+constexpr int kWideBlockMinFine = 11000;
+constexpr int kWideBlockMinFp32 = 6000;
 constexpr int kMaxRowsPerBlock = kBlock;
 constexpr int kLongRow = 96;         // setup kernels: longer single-row blocks take the whole-block path
 constexpr int kWideRow = 32;         // streaming, one thread per row: wider rows are summed by 8 lanes of its wavefront

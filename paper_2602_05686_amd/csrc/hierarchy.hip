@@ -54,19 +54,20 @@ void make_blocks(DCsr& A, MemCounter* mc, hipStream_t s, bool pack = true, int c
 // one-thread-per-row matrix: twice the bytes per workgroup, which the finest
 // levels stream faster, while the setup kernels keep the kStreamCap blocks
 // (sblk).  Kept only if the wider blocks pack too.
-// MATAMG_WIDE_MIN_BLOCKS=<k> lowers the block-count threshold (used by the
-// tests to run the wide kernels on small operators)
-int wide_block_min() {
+// MATAMG_WIDE_MIN_BLOCKS=<k> sets the block-count threshold of every level
+// (used by the tests to run the wide kernels on small operators)
+int wide_block_min(int level, bool fp32) {
     const char* e = std::getenv("MATAMG_WIDE_MIN_BLOCKS");
     if (e && e[0]) {
         const int v = std::atoi(e);
         if (v > 0) return v;
     }
-    return kWideBlockMin;
+    if (level == 0) return kWideBlockMinFine;
+    return fp32 ? kWideBlockMinFp32 : kWideBlockMin;
 }
 
-void widen_stream_blocks(DCsr& A, MemCounter* mc, hipStream_t s) {
-    if (A.group != 1 || !A.col16 || A.cap != kStreamCap || A.nblk < wide_block_min()) return;
+void widen_stream_blocks(DCsr& A, int min_blocks, MemCounter* mc, hipStream_t s) {
+    if (A.group != 1 || !A.col16 || A.cap != kStreamCap || A.nblk < min_blocks) return;
     DBuf<int> blk = std::move(A.blk), blkk = std::move(A.blkk), cbase = std::move(A.cbase),
               ustart = std::move(A.ustart);
     DBuf<uint16_t> col16 = std::move(A.col16), uoff = std::move(A.uoff);
@@ -575,7 +576,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
     h.nlev = l + 1;
     ensure_partial(h, stream_partials(h.lev[0].A));
     if (wide_blocks)
-        for (int k = 0; k < h.nlev; ++k) widen_stream_blocks(h.lev[k].A, mc, s);
+        for (int k = 0; k < h.nlev; ++k) widen_stream_blocks(h.lev[k].A, wide_block_min(k, h.fp32), mc, s);
 
     smoother_bounds(h, s);
     coarse_inverse(h, flag.get(), s);

@@ -1,9 +1,22 @@
 """Summarise a rocprofv3 --kernel-trace --output-format csv run as a short
 markdown table: per kernel (and per launch grid for the streaming kernels),
-calls, total and average duration."""
+calls, total and average duration.
+
+With --levels, the V-cycles in the trace (each starts with the finest
+level's first smoother step, k_smooth_first) are split by level instead:
+a kernel belongs to the level whose vectors it writes, so a restriction
+(k_stream mode 7, or mode 0 into the coarsest level) to the coarser level,
+a prolongation (mode 2) to the finer one and the dense GEMV to the coarsest.
+The table gives each level's launches and average time per V-cycle; a bench
+log given with --log adds the level sizes it printed.
+
+    python profile_summary.py <run_kernel_trace.csv> [top]
+    python profile_summary.py <run_kernel_trace.csv> --levels [--log bench.log]
+"""
 
 import collections
 import csv
+import re
 import sys
 
 
@@ -12,14 +25,19 @@ def short(name):
     return name.split("(")[0]
 
 
+def load(trace_csv):
+    with open(trace_csv) as f:
+        rows = list(csv.DictReader(f))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    return [(short(r["Kernel_Name"]), int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]),
+             int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in rows]
+
+
 def main(trace_csv, top=30):
     rows = collections.defaultdict(lambda: [0, 0])
-    with open(trace_csv) as f:
-        for r in csv.DictReader(f):
-            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-            key = (short(r["Kernel_Name"]), int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]))
-            rows[key][0] += 1
-            rows[key][1] += dur
+    for k, g, dur in load(trace_csv):
+        rows[(k, g)][0] += 1
+        rows[(k, g)][1] += dur
     total = sum(v[1] for v in rows.values())
     print(f"total kernel time {total / 1e6:.1f} ms\n")
     print("| kernel | workgroups | calls | total ms | avg us |")
@@ -28,5 +46,50 @@ def main(trace_csv, top=30):
         print(f"| `{k}` | {g} | {c} | {d / 1e6:.2f} | {d / c / 1e3:.1f} |")
 
 
+def stream_mode(k):
+    m = re.match(r"k_stream<\w+, (\d+),", k)
+    return int(m.group(1)) if m else None
+
+
+def levels(trace_csv, log=None):
+    seq = load(trace_csv)
+    starts = [i for i, (k, _, _) in enumerate(seq) if k.startswith("k_smooth_first")]
+    cycles = [seq[a:b] for a, b in zip(starts, starts[1:] + [len(seq)])]
+    per = collections.defaultdict(lambda: [0, 0])  # level -> launches, ns (summed over cycles)
+    walls = []
+    for cyc in cycles:
+        lev = 0
+        for k, _, dur in cyc:
+            mode = stream_mode(k)
+            if mode in (7, 0):
+                lev += 1
+            elif mode == 2:
+                lev -= 1
+            per[lev][0] += 1
+            per[lev][1] += dur
+        walls.append(sum(d for _, _, d in cyc))
+    sizes = {}
+    if log:
+        with open(log) as f:
+            for line in f:
+                m = re.search(r"level (\d+): n (\d+), nnz (\d+)", line)
+                if m:
+                    sizes[int(m.group(1))] = (int(m.group(2)), int(m.group(3)))
+    nc = len(cycles)
+    tot = sum(v[1] for v in per.values()) / nc
+    print(f"{nc} V-cycles, kernel time {tot / 1e3:.1f} us per V-cycle\n")
+    print("| level | rows | stored entries | launches per V-cycle | us per V-cycle | share |")
+    print("|---:|---:|---:|---:|---:|---:|")
+    for lv in sorted(per):
+        c, d = per[lv]
+        n, z = sizes.get(lv, ("", ""))
+        print(f"| {lv} | {n} | {z} | {c / nc:.0f} | {d / nc / 1e3:.1f} | {100 * d / nc / tot:.1f}% |")
+
+
 if __name__ == "__main__":
-    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 30)
+    a = sys.argv[1:]
+    if "--levels" in a:
+        lg = a[a.index("--log") + 1] if "--log" in a else None
+        levels(a[0], lg)
+    else:
+        main(a[0], int(a[1]) if len(a) > 1 else 30)
