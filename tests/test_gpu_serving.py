@@ -270,3 +270,53 @@ def test_destroy_with_requests_in_flight(amg):
     assert time.time() - t0 < 30
     out, st = serve(amg, probs[:2], "fp32", max_coarse=200)
     assert st["completed"] == 2
+
+
+def test_thin_stacks_served_as_the_oracle_solves_them(amg):
+    """The serving stream's thin layered stacks (60 layers on 32 to 47
+    elements per side) converge slowly: the oracle needs 184 to 570
+    iterations on some and stops at the 1000-iteration cap on others.  Seven
+    oracle runs per request (tests/golden/make_serving_oracle_outcomes.py:
+    b as generated, b moved by one ulp, A's values scaled by 1 + j 2^-52
+    with the setup rerun) give the spread of the outcome under rounding:
+    the exits of the converged requests hardly move, while the residual
+    after 1000 iterations of a stopped one moves by up to a factor of six.
+    Served in the FP64 form, each request ends as the oracle's do: the
+    converged ones within the oracle's exit range widened by max(2, its
+    width) on each side, the others at the cap with a true relative
+    residual within the oracle's range widened by its own ratio (at least
+    10%) on each side."""
+    import json
+    import os
+
+    from workloads import problem_from_request, serving_stream
+
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    with open(os.path.join(gold, "serving_oracle_ulp_exits.json")) as f:
+        rec = json.load(f)
+    runs = {c["request"]: c["runs"] for c in rec["cases"]}
+    ids = sorted(rec["converged"] + rec["stopped"])
+    byid = {r["id"]: r for r in serving_stream(num=256, rate=20.0)}
+    probs = [problem_from_request(byid[i]) for i in ids]
+    banner(f"thin stacks: {len(ids)} requests through the FP64-form server")
+    out, st = serve(amg, probs, "fp64")
+    assert st["completed"] == len(ids)
+    bad = []
+    for k, i in enumerate(ids):
+        _, info, _ = out[k]
+        exits = [r["iterations"] for r in runs[i]]
+        rels = [r["rel_res_true"] for r in runs[i]]
+        if i in rec["converged"]:
+            w = max(2, max(exits) - min(exits))
+            ok = info["status"] == "OK" and min(exits) - w <= info["iterations"] <= max(exits) + w
+            want = f"OK in [{min(exits) - w}, {max(exits) + w}]"
+        else:
+            f = max(1.1, max(rels) / min(rels))
+            lo, hi = min(rels) / f, max(rels) * f
+            ok = info["status"] == "NOT_CONVERGED" and info["iterations"] == 1000 and lo <= info["rel_res"] <= hi
+            want = f"NOT_CONVERGED at 1000, rel-res in [{lo:.2e}, {hi:.2e}]"
+        print(f"request {i} ({probs[k].n} DOF): {info['status']} after {info['iterations']}, "
+              f"rel-res {info['rel_res']:.2e}; oracle {want}")
+        if not ok:
+            bad.append(i)
+    assert not bad, f"requests served unlike the oracle: {bad}"
