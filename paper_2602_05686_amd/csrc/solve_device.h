@@ -414,11 +414,32 @@ __device__ __forceinline__ void stream_block(const SArgs<T>& a, int bid, StreamS
             }
         }
     } else {
-        // one long row (a block of its own): strided partial sums, fixed tree
+        // one long row (a block of its own): strided partial sums, fixed
+        // tree.  Each thread adds its entries t, t + kBlock, ... in order;
+        // four strides at a time have their loads, then their gathers, in
+        // flight together.  A long row's block is never staged, so packed
+        // columns hold plain offsets from the block's base.
         T s = 0;
-        for (int t = threadIdx.x; t < cnt; t += kBlock) {
+        const int* col = a.col16 ? nullptr : a.col;
+        const int base = a.col16 ? a.cbase[bid] : 0;
+        int t = (int)threadIdx.x;
+        for (; t + 3 * kBlock < cnt; t += 4 * kBlock) {
+            int c[4];
+            T v[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + t + u * kBlock;
+                c[u] = col ? col[k] : base + (int)a.col16[k];
+                v[u] = a.val[k];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = a.x[c[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s += v[u] * xv[u];
+        }
+        for (; t < cnt; t += kBlock) {
             const int k = k0 + t;
-            s += a.val[k] * a.x[a.col[k]];
+            s += a.val[k] * a.x[col ? col[k] : base + (int)a.col16[k]];
         }
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
