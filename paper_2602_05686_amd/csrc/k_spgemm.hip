@@ -483,8 +483,13 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric_big(int nrows, const 
 // in order of first appearance, in registers with their running sums; the
 // sorted output position of each is its rank among them.  Every entry
 // therefore gets the same additions, in the same order, as on the wavefront
-// path.
+// path.  A row with more than kThreadProducts products takes the wavefront
+// path even when its columns would fit: each product costs a thread a
+// compare against every register slot, a wavefront one hash probe per lane
+// (the coarse levels' Galerkin rows collapse hundreds of products into few
+// columns).
 constexpr int kThreadCols = 32;
+constexpr int kThreadProducts = 64;
 constexpr int kThreadRow = -3;  // pcount marker of a row on the thread path
 
 // add product (c, v) to the row's column list key/acc[0..d) of S slots (v
@@ -513,7 +518,8 @@ __device__ __forceinline__ bool thread_row_add(int (&key)[S], double (&acc)[S], 
 // the products of row i in canonical order, f(column, value): A's row in
 // chunks of CH entries whose column, B-row bounds and first B entry are all
 // loaded before any is used (P rows mostly hold one entry), so a chunk costs
-// three memory latencies instead of three per entry
+// three memory latencies instead of three per entry.  f returns whether to
+// go on.
 template <bool VAL, int CH, typename F>
 __device__ __forceinline__ void thread_row_products(const int* arp, const int* acol, const double* aval,
                                                     const int* brp, const int* bcol, const double* bval, int i,
@@ -542,14 +548,17 @@ __device__ __forceinline__ void thread_row_products(const int* arp, const int* a
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
             if (c0 + u >= a1 || b0[u] >= b1[u]) continue;
-            f(fc[u], VAL ? av[u] * fv[u] : 0.0);
-            for (int kb = b0[u] + 1; kb < b1[u]; ++kb) f(bcol[kb], VAL ? av[u] * bval[kb] : 0.0);
+            if (!f(fc[u], VAL ? av[u] * fv[u] : 0.0)) return;
+            for (int kb = b0[u] + 1; kb < b1[u]; ++kb)
+                if (!f(bcol[kb], VAL ? av[u] * bval[kb] : 0.0)) return;
         }
     }
 }
 
 // symbolic: cnt[i] = distinct columns and pcount[i] = kThreadRow for rows
-// that fit; wide[i] = 1 (and cnt[i] untouched) for the others
+// that fit (at most kThreadCols columns from at most kThreadProducts
+// products); wide[i] = 1 (and cnt[i] untouched) for the others, whose walk
+// stops where they stop fitting
 __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic_thread(int n, const int* arp, const int* acol,
                                                                    const int* brp, const int* bcol, int* cnt,
                                                                    int* pcount, int* wide) {
@@ -558,10 +567,11 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic_thread(int n, const 
         double acc[kThreadCols];
 #pragma unroll
         for (int j = 0; j < kThreadCols; ++j) key[j] = -1;
-        int d = 0;
+        int d = 0, m = 0;
         bool fits = true;
         thread_row_products<false, 8>(arp, acol, nullptr, brp, bcol, nullptr, i, [&](int c, double) {
-            if (fits && !thread_row_add<false, kThreadCols>(key, acc, d, c, 0.0)) fits = false;
+            fits = ++m <= kThreadProducts && thread_row_add<false, kThreadCols>(key, acc, d, c, 0.0);
+            return fits;
         });
         wide[i] = fits ? 0 : 1;
         if (fits) {
@@ -593,8 +603,10 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric_thread(int n, const i
             acc[j] = 0.0;
         }
         int d = 0;
-        thread_row_products<true, 4>(arp, acol, aval, brp, bcol, bval, i,
-                                     [&](int c, double v) { (void)thread_row_add<true, S>(key, acc, d, c, v); });
+        thread_row_products<true, 4>(arp, acol, aval, brp, bcol, bval, i, [&](int c, double v) {
+            (void)thread_row_add<true, S>(key, acc, d, c, v);
+            return true;
+        });
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             if (key[j] < 0) continue;
