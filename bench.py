@@ -117,6 +117,33 @@ def time_vcycles(h, n, reps, dev):
     return e0.elapsed_time(e1) / reps
 
 
+def achievable_bandwidth(dev, nbytes=1 << 30, reps=20):
+    """What plain streaming reaches on this GPU: a read (sum), a device copy
+    (read + write) and a fill of nbytes, each the mean of reps launches
+    between HIP events on torch's current stream, in GB/s of bytes moved."""
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, fn, moved in (("read", lambda: src.sum(), nbytes), ("copy", lambda: dst.copy_(src), 2 * nbytes),
+                            ("fill", lambda: dst.fill_(2.0), nbytes)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[f"{name}_GBps"] = moved / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def vcycle_record(h, n, reps, dev):
     st = h.stats()
     ms = time_vcycles(h, n, reps, dev)
@@ -765,6 +792,8 @@ def main():
     achieved = kt["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
     log(f"V-cycle {t_vc_ms:.3f} ms = {vc_gbs:.0f} GB/s algorithmic; fine smoother SpMV {avg_ms * 1e3:.1f} us "
         f"= {achieved:.0f} GB/s")
+    stream_bw = achievable_bandwidth(dev)
+    log("plain streaming, 1 GiB: " + ", ".join(f"{k[:-5]} {v:.0f} GB/s" for k, v in stream_bw.items()))
 
     # the same solve from seeded initial guesses x0 ~ U(0, 1): how the exit
     # count and the throughput move with the starting point
@@ -874,7 +903,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_stream<double, SMOOTH> on the finest level",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_launch_us": avg_ms * 1e3, "launches": args.vcycles,
-                     "alg_bytes_per_launch": kt["bytes_per_launch"]},
+                     "alg_bytes_per_launch": kt["bytes_per_launch"],
+                     # plain streaming on this GPU (1 GiB, torch kernels), beside the published peak
+                     "achievable": stream_bw,
+                     "frac_of_achievable_read": achieved / stream_bw["read_GBps"]},
         "fp32_form": fp32,
         "layered192": c4,
         "serving": serving,
