@@ -529,7 +529,7 @@ __global__ void k_root_flags(int n, const uint8_t* state, int* flags) {
 }
 
 __global__ void k_agg_phase2(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint8_t* dir,
-                             const uint8_t* state, const int* rank, int* phase2) {
+                             const uint8_t* state, const int* rank, int* phase2, int* list, int* nlist) {
     ROW_LOOP(i, n) {
         int a = -1;
         if (state[i] == MIS_IN) {
@@ -537,8 +537,13 @@ __global__ void k_agg_phase2(int n, const int* rowptr, const int* col, const uin
         } else if (!(dir && dir[i])) {
             // the first kept neighbour (ascending stored order) that is a
             // root; the row is read eight entries at a time, each chunk's
-            // columns and masks, then their states, loaded together
+            // columns and masks, then their states, loaded together.  Rows
+            // longer than kLongRow are listed for k_agg_phase2_long instead.
             const int lo = rowptr[i], hi = rowptr[i + 1];
+            if (hi - lo > kLongRow) {
+                list[atomicAdd(nlist, 1)] = (int)i;
+                continue;
+            }
             int root = -1;
             for (int k0 = lo; k0 < hi && root < 0; k0 += 8) {
                 int c[8];
@@ -558,6 +563,40 @@ __global__ void k_agg_phase2(int n, const int* rowptr, const int* col, const uin
             if (root >= 0) a = rank[root];
         }
         phase2[i] = a;
+    }
+}
+
+// Phase 2 of the rows listed above, a wavefront each: the first kept
+// neighbour in stored order that is a root, as the row's thread would find
+// it.  Each lane takes the first match among its entries (four strides of
+// columns and masks, then their states, loaded together) and the smallest
+// position over the lanes wins.
+__global__ void k_agg_phase2_long(const int* rowptr, const int* col, const uint8_t* mask, const uint8_t* state,
+                                  const int* rank, const int* list, const int* nlist, int* phase2) {
+    const int lane = threadIdx.x & 63;
+    const int nl = *nlist;
+    const int nw = (int)((gridDim.x * blockDim.x) >> 6);
+    for (int w = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); w < nl; w += nw) {
+        const int i = list[w];
+        const int lo = rowptr[i], hi = rowptr[i + 1];
+        int kf = hi;
+        for (int k0 = lo + lane; k0 < hi && kf == hi; k0 += 4 * 64) {
+            int c[4];
+            uint8_t m[4], st[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = min(k0 + u * 64, hi - 1);
+                c[u] = col[k];
+                m[u] = mask[k];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) st[u] = state[c[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (kf == hi && k0 + u * 64 < hi && c[u] != i && m[u] && st[u] == MIS_IN) kf = k0 + u * 64;
+        }
+        for (int off = 32; off > 0; off >>= 1) kf = min(kf, __shfl_xor(kf, off, 64));
+        if (lane == 0) phase2[i] = kf < hi ? rank[col[kf]] : -1;
     }
 }
 
@@ -668,32 +707,49 @@ __global__ __launch_bounds__(kBlock) void k_filter_count(const int* rowptr, cons
 //    (1 -+ omega) factor; the drop mask decides instead, reproducibly;
 //  - empty rows: a filtered row whose 1-norm is at most 2^-46 of that.
 // Both sums run in ascending stored order, one IEEE operation at a time.
-__device__ __forceinline__ void filter_row(int i, const int* cs, const double* vs, const uint8_t* ms, int lo, int hi,
-                                           int p, bool dirichlet, int* fcol, double* fval, double* dt, double* dtinv) {
-    const int p0 = p;
-    int diagpos = -1;
-    double lump = 0.0, rowabs = 0.0, keptabs = 0.0;
+// running state of one row's filtering (its entries may come in pieces)
+struct FilterAcc {
+    int p0, p, diagpos;
+    double lump, rowabs, keptabs;
+};
+
+__device__ __forceinline__ FilterAcc filter_begin(int p) { return FilterAcc{p, p, -1, 0.0, 0.0, 0.0}; }
+
+// the row's entries lo..hi of cs/vs/ms, next in stored order
+__device__ __forceinline__ void filter_entries(int i, const int* cs, const double* vs, const uint8_t* ms, int lo,
+                                               int hi, FilterAcc& f, int* fcol, double* fval) {
     for (int k = lo; k < hi; ++k) {
         const int j = cs[k];
         const double v = vs[k];
-        rowabs += fabs(v);
+        f.rowabs += fabs(v);
         if (j == i || ms[k]) {
-            if (j == i) diagpos = p;
-            else keptabs += fabs(v);
-            fcol[p] = j;
-            fval[p] = v;
-            p++;
+            if (j == i) f.diagpos = f.p;
+            else f.keptabs += fabs(v);
+            fcol[f.p] = j;
+            fval[f.p] = v;
+            f.p++;
         } else {
-            lump += v;
+            f.lump += v;
         }
     }
-    if (diagpos >= 0) fval[diagpos] = fval[diagpos] + lump;
+}
+
+__device__ __forceinline__ void filter_end(int i, bool dirichlet, const FilterAcc& f, double* fval, double* dt,
+                                           double* dtinv) {
+    if (f.diagpos >= 0) fval[f.diagpos] = fval[f.diagpos] + f.lump;
     double s = 0.0;
-    for (int q = p0; q < p; ++q) s += fabs(fval[q]);
-    const bool isolated = !dirichlet && !(keptabs > kRowNoise * rowabs);
-    if (isolated || !(s > kRowNoise * rowabs)) s = 0.0;
+    for (int q = f.p0; q < f.p; ++q) s += fabs(fval[q]);
+    const bool isolated = !dirichlet && !(f.keptabs > kRowNoise * f.rowabs);
+    if (isolated || !(s > kRowNoise * f.rowabs)) s = 0.0;
     dt[i] = s;
     dtinv[i] = s > 0.0 ? 1.0 / s : 0.0;
+}
+
+__device__ __forceinline__ void filter_row(int i, const int* cs, const double* vs, const uint8_t* ms, int lo, int hi,
+                                           int p, bool dirichlet, int* fcol, double* fval, double* dt, double* dtinv) {
+    FilterAcc f = filter_begin(p);
+    filter_entries(i, cs, vs, ms, lo, hi, f, fcol, fval);
+    filter_end(i, dirichlet, f, fval, dt, dtinv);
 }
 
 __global__ __launch_bounds__(kBlock) void k_filter_fill(const int* rowptr, const int* col, const double* val,
@@ -717,9 +773,23 @@ __global__ __launch_bounds__(kBlock) void k_filter_fill(const int* rowptr, const
         if (r < rb.r1)
             filter_row(r, cs, vs, ms, rowptr[r] - rb.k0, rowptr[r + 1] - rb.k0, frowptr[r], dir[r] != 0, fcol, fval,
                        dt, dtinv);
-    } else if (threadIdx.x == 0) {
-        filter_row(rb.r0, col + rb.k0, val + rb.k0, mask + rb.k0, 0, rb.cnt, frowptr[rb.r0], dir[rb.r0] != 0, fcol,
-                   fval, dt, dtinv);
+    } else {
+        // one long row: the block stages it through LDS kStreamCap entries
+        // at a time, and thread 0 filters each piece in stored order (the
+        // same operations as a row of a short block)
+        FilterAcc f = filter_begin(frowptr[rb.r0]);
+        for (int c0 = 0; c0 < rb.cnt; c0 += kStreamCap) {
+            const int cn = rb.cnt - c0 < kStreamCap ? rb.cnt - c0 : kStreamCap;
+            __syncthreads();  // the previous piece has been filtered
+            for (int t = threadIdx.x; t < cn; t += kBlock) {
+                cs[t] = col[rb.k0 + c0 + t];
+                vs[t] = val[rb.k0 + c0 + t];
+                ms[t] = mask[rb.k0 + c0 + t];
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) filter_entries(rb.r0, cs, vs, ms, 0, cn, f, fcol, fval);
+        }
+        if (threadIdx.x == 0) filter_end(rb.r0, dir[rb.r0] != 0, f, fval, dt, dtinv);
     }
 }
 
@@ -948,7 +1018,13 @@ void agg_root_flags(int n, const uint8_t* state, int* flags, hipStream_t s) {
 void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint8_t* dir,
                 const uint8_t* state, const int* root_rank, int* phase2, int* agg, int* list, int* nlist,
                 hipStream_t s) {
-    LAUNCH(k_agg_phase2, n, n, rowptr, col, mask, dir, state, root_rank, phase2);
+    zero_async(nlist, sizeof(int), s);
+    LAUNCH(k_agg_phase2, n, n, rowptr, col, mask, dir, state, root_rank, phase2, list, nlist);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_agg_phase2_long, dim3(std::min(ceil_div(n, kBlock / 64), 1024)), dim3(kBlock), 0, s,
+                           rowptr, col, mask, state, root_rank, (const int*)list, (const int*)nlist, phase2);
+        MATAMG_LAUNCH_CHECK();
+    }
     zero_async(nlist, sizeof(int), s);
     LAUNCH(k_agg_phase3_split, n, n, dir, phase2, agg, list, nlist);
     if (n > 0) {

@@ -688,21 +688,51 @@ __global__ void k_col_counts(int64_t nnz, const int* col, int* cnt) {
         atomicAdd(cnt + col[k], 1);
 }
 
+// the transpose's entries, in the order the atomic slots hand out within
+// each row, with each entry's row
 __global__ void k_transpose_fill(int n, const int* rp, const int* col, const double* val, const int* trp,
-                                 int* fill, int* tcol, double* tval) {
+                                 int* fill, int* tcol, double* tval, int* trow) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         for (int k = rp[i]; k < rp[i + 1]; ++k) {
             const int c = col[k];
             const int p = trp[c] + atomicAdd(fill + c, 1);
             tcol[p] = i;
             tval[p] = val[k];
+            trow[p] = c;
         }
     }
 }
 
+// Rows of the transpose up to this long are put in column order by ranking;
+// longer ones are sorted in place afterwards
+constexpr int kRankRow = 256;
+
+// Each entry to its place in column order.  A row's columns (the source
+// rows) are distinct, so an entry's place is the number of the row's
+// columns below its own: one thread per entry, reading the row with
+// independent loads.  Entries of longer rows are copied where they are.
+__global__ void k_rank_place(int64_t nnz, const int* trp, const int* trow, const int* tcol, const double* tval,
+                             int* col, double* val) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = trow[e];
+        const int lo = trp[j], hi = trp[j + 1];
+        const int c = tcol[e];
+        int64_t pos = e;
+        if (hi - lo <= kRankRow) {
+            int r = 0;
+            for (int k = lo; k < hi; ++k) r += tcol[k] < c ? 1 : 0;
+            pos = lo + r;
+        }
+        col[pos] = c;
+        val[pos] = tval[e];
+    }
+}
+
+// insertion sort of the rows longer than kRankRow, one thread per row
 __global__ void k_sort_pairs(int n, const int* rp, int* col, double* val) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int lo = rp[i], hi = rp[i + 1];
+        if (hi - lo <= kRankRow) continue;
         for (int a = lo + 1; a < hi; ++a) {
             const int c = col[a];
             const double v = val[a];
@@ -842,11 +872,18 @@ void transpose(const DCsr& A, DCsr& T, MemCounter* mc, hipStream_t s) {
     DBuf<int> tmp(scan_tmp_size(m), mc);
     exclusive_scan(cnt.get(), T.rowptr.get(), m, tmp.get(), s);
     zero_async(cnt.get(), sizeof(int) * (size_t)(m > 0 ? m : 1), s);
-    T.col.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), mc);
-    T.val.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), mc);
+    const size_t nz = (size_t)(A.nnz > 0 ? A.nnz : 1);
+    T.col.alloc(nz, mc);
+    T.val.alloc(nz, mc);
+    DBuf<int> tcol(nz, mc), trow(nz, mc);
+    DBuf<double> tval(nz, mc);
     if (n > 0)
         hipLaunchKernelGGL(k_transpose_fill, dim3(g1(n)), dim3(kBlock), 0, s, n, A.rowptr.get(), A.col.get(),
-                           A.val.get(), T.rowptr.get(), cnt.get(), T.col.get(), T.val.get());
+                           A.val.get(), T.rowptr.get(), cnt.get(), tcol.get(), tval.get(), trow.get());
+    if (A.nnz > 0)
+        hipLaunchKernelGGL(k_rank_place, dim3(g1(A.nnz)), dim3(kBlock), 0, s, A.nnz, (const int*)T.rowptr.get(),
+                           (const int*)trow.get(), (const int*)tcol.get(), (const double*)tval.get(), T.col.get(),
+                           T.val.get());
     if (m > 0)
         hipLaunchKernelGGL(k_sort_pairs, dim3(g1(m)), dim3(kBlock), 0, s, m, T.rowptr.get(), T.col.get(),
                            T.val.get());
