@@ -10,8 +10,13 @@ a prolongation (mode 2) to the finer one and the dense GEMV to the coarsest.
 The table gives each level's launches and average time per V-cycle; a bench
 log given with --log adds the level sizes it printed.
 
+With --setup, only the last setup in the trace is summarised (from its
+input validation, k_validate_csr, to the first V-cycle after it), per
+kernel name, with the gaps between its kernels.
+
     python profile_summary.py <run_kernel_trace.csv> [top]
     python profile_summary.py <run_kernel_trace.csv> --levels [--log bench.log]
+    python profile_summary.py <run_kernel_trace.csv> --setup [top]
 """
 
 import collections
@@ -25,12 +30,38 @@ def short(name):
     return name.split("(")[0]
 
 
-def load(trace_csv):
+def load(trace_csv, starts=False):
     with open(trace_csv) as f:
         rows = list(csv.DictReader(f))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    return [(short(r["Kernel_Name"]), int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]),
-             int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in rows]
+    out = [(short(r["Kernel_Name"]), int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]),
+            int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in rows]
+    if starts:
+        return out, [(int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows]
+    return out
+
+
+def setup(trace_csv, top=25):
+    seq, times = load(trace_csv, starts=True)
+    val = [i for i, (k, _, _) in enumerate(seq) if k.startswith("k_validate_csr")]
+    a = val[-1]
+    b = next((i for i in range(a, len(seq)) if seq[i][0].startswith("k_smooth_first")), len(seq))
+    win = seq[a:b]
+    t = times[a:b]
+    wall = t[-1][1] - t[0][0]
+    busy = sum(d for _, _, d in win)
+    gaps = sum(max(0, y[0] - x[1]) for x, y in zip(t, t[1:]))
+    print(f"setup window {wall / 1e6:.2f} ms: kernels {busy / 1e6:.2f} ms ({len(win)} launches), "
+          f"gaps {gaps / 1e6:.2f} ms\n")
+    per = collections.defaultdict(lambda: [0, 0])
+    for k, _, d in win:
+        name = k if k.startswith("k_stream") else k.split("<")[0]
+        per[name][0] += 1
+        per[name][1] += d
+    print("| kernel | launches | total ms |")
+    print("|---|---:|---:|")
+    for k, (c, d) in sorted(per.items(), key=lambda kv: -kv[1][1])[:top]:
+        print(f"| `{k}` | {c} | {d / 1e6:.2f} |")
 
 
 def main(trace_csv, top=30):
@@ -88,7 +119,10 @@ def levels(trace_csv, log=None):
 
 if __name__ == "__main__":
     a = sys.argv[1:]
-    if "--levels" in a:
+    if "--setup" in a:
+        rest = [x for x in a[1:] if x != "--setup"]
+        setup(a[0], int(rest[0]) if rest else 25)
+    elif "--levels" in a:
         lg = a[a.index("--log") + 1] if "--log" in a else None
         levels(a[0], lg)
     else:
