@@ -5,12 +5,15 @@ settings of the numerical section).
 
 Cases: the right-hand side as generated, from x0 = 0; the same with every
 nonzero entry of b moved by one ulp (five seeded coin flips); and five seeded
-starts x0 ~ U(0, 1).  Each records the iteration count, the true relative
-residual and the relative error against the exact discrete solution (the
-z-only series-resistor profile).  Only the oracle and the input generators
-run here.  Run from the repository root:
+starts x0 ~ U(0, 1).  With --add, the seeded start 0 again under one-ulp
+changes of b (three seeds, "x0ulp") and with A's values scaled by
+1 + j 2^-52 (j = 1, 2, 3, the setup rerun, "x0scale") are appended to the
+record.  Each records the iteration count, the true relative residual and the
+relative error against the exact discrete solution (the z-only
+series-resistor profile).  Only the oracle and the input generators run here.
+Run from the repository root:
 
-    python tests/golden/make_layered128_oracle_exits.py [--workers 6]
+    python tests/golden/make_layered128_oracle_exits.py [--workers 6] [--add]
 
 Each case builds its own oracle hierarchy (about 5 GB, 20 s) and solves
 (two to four minutes on one core); the cases run in parallel processes.
@@ -44,6 +47,8 @@ def exact(prob):
 
 
 def run_case(case):
+    import dataclasses
+
     import numpy as np
     import oracle
     from workloads.q1 import seeded_start, ulp_perturbed
@@ -54,6 +59,15 @@ def run_case(case):
         b = ulp_perturbed(prob.b, k)
     elif kind == "x0":
         x0 = seeded_start(prob.n, k)
+    elif kind == "x0ulp":
+        b = ulp_perturbed(prob.b, k)
+        x0 = seeded_start(prob.n, 0)
+    elif kind == "x0scale":
+        # in exact arithmetic the hierarchy scales by c and the iterates by
+        # 1/c; in floating point every rounding of setup and solve changes
+        prob = dataclasses.replace(prob, val=prob.val * (1.0 + k * 2.0**-52))
+        b = prob.b
+        x0 = seeded_start(prob.n, 0)
     h = oracle.Hierarchy(prob)
     t = time.time()
     x, info = h.pcg(b, x0=x0)
@@ -66,11 +80,25 @@ def run_case(case):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workers", type=int, default=6)
+    ap.add_argument("--add", action="store_true", help="append the seeded-start spread cases to the record")
     args = ap.parse_args()
     prob = problem()
     from workloads.q1 import problem_digest
     digest = problem_digest(prob)
     del prob
+    if args.add:
+        with open(OUT) as f:
+            out = json.load(f)
+        assert out["input_sha256"] == digest
+        cases = [("x0ulp", k) for k in range(3)] + [("x0scale", j) for j in (1, 2, 3)]
+        with mp.get_context("spawn").Pool(args.workers) as pool:
+            rows = pool.map(run_case, cases, chunksize=1)
+        out["cases"] = [c for c in out["cases"] if c["case"] not in ("x0ulp", "x0scale")] + rows
+        with open(OUT, "w") as f:
+            json.dump(out, f, indent=1)
+        for r in rows:
+            print(r)
+        return
     cases = [("b", 0)] + [("ulp", k) for k in range(5)] + [("x0", k) for k in range(5)]
     with mp.get_context("spawn").Pool(args.workers) as pool:
         rows = pool.map(run_case, cases, chunksize=1)
