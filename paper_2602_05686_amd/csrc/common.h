@@ -24,12 +24,16 @@ struct Error {
 
 [[noreturn]] void fail(amg_status code, const std::string& msg);
 
+// A failed call is reported once: the runtime's last-error value it leaves
+// behind is cleared, so that it cannot resurface in a later, unrelated call.
 #define MATAMG_HIP(call)                                                                        \
     do {                                                                                        \
         hipError_t e_ = (call);                                                                 \
-        if (e_ != hipSuccess)                                                                   \
+        if (e_ != hipSuccess) {                                                                 \
+            (void)hipGetLastError();                                                            \
             ::matamg::fail(e_ == hipErrorOutOfMemory ? AMG_ERR_OUT_OF_MEMORY : AMG_ERR_HIP,     \
                            std::string(#call) + ": " + hipGetErrorString(e_));                  \
+        }                                                                                       \
     } while (0)
 
 #define MATAMG_LAUNCH_CHECK() MATAMG_HIP(hipGetLastError())

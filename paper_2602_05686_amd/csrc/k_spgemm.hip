@@ -761,7 +761,8 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
     C.m = B.m;
     const int nn = n > 0 ? n : 1;
     DBuf<int> cnt((size_t)nn, mc), flags((size_t)nn, mc), pos((size_t)n + 1, mc), pcount((size_t)nn, mc);
-    DBuf<int> wide((size_t)nn, mc), wpos((size_t)n + 1, mc), wl((size_t)nn, mc), cntc((size_t)nn, mc);
+    // cntc also takes the pair {overflow rows, stored entries} read back below
+    DBuf<int> wide((size_t)nn, mc), wpos((size_t)n + 1, mc), wl((size_t)nn, mc), cntc((size_t)std::max(nn, 2), mc);
     DBuf<int> tmp(scan_tmp_size(n), mc);
     C.rowptr.alloc((size_t)n + 1, mc);
     // wavefront launches loop over a row list whose length stays on the device

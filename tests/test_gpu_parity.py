@@ -483,3 +483,27 @@ def test_jacobi_smoother_matches_oracle(amg, name, smoother):
     else:
         assert err <= 1e-6
     assert i32["status"] == "OK" and rel32 <= 1e-8
+
+
+def test_one_node_coarsest_level_then_next_setup(amg):
+    """Two domains at h = 1/512, kappa = 1e4, cut dropping at theta 0.02
+    and at most 50 coarse unknowns: the 70-node level coarsens into a single
+    aggregate, so the last Galerkin product has one row.  That setup, and
+    the next one in the same process (theta 0.04, a 10-node coarsest level),
+    equal the oracle's: level sizes, iterations within one, solution within
+    1e-6."""
+    prob = two_domain_2d(n=512, kappa=1e4)
+    for theta in (0.02, 0.04):
+        banner(f"two-domain 1/512 cut theta {theta}: oracle")
+        orc = oracle.Hierarchy(prob, drop="cut", theta=theta, max_coarse=50)
+        xo, io = orc.pcg(prob.b)
+        banner(f"two-domain 1/512 cut theta {theta}: GPU")
+        h = amg.Hierarchy.from_problem(prob, drop="cut", theta=theta, max_coarse=50)
+        n_gpu = h.stats()["n"]
+        x, info = h.solve(prob.b)
+        h.close()
+        err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+        print(f"theta {theta}: levels {n_gpu} (oracle {orc.stats()['n']}), iterations {info['iterations']} "
+              f"(oracle {io['iterations']}), rel err {err:.1e}")
+        assert n_gpu == orc.stats()["n"]
+        assert info["status"] == "OK" and abs(info["iterations"] - io["iterations"]) <= 1 and err <= 1e-6
