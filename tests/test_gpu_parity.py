@@ -507,3 +507,46 @@ def test_one_node_coarsest_level_then_next_setup(amg):
               f"(oracle {io['iterations']}), rel err {err:.1e}")
         assert n_gpu == orc.stats()["n"]
         assert info["status"] == "OK" and abs(info["iterations"] - io["iterations"]) <= 1 and err <= 1e-6
+
+
+TINY = {
+    "twodomain32": lambda: two_domain_2d(n=32, kappa=1e4),
+    "box987": lambda: poisson_box((9, 8, 7)),
+    "layered8": lambda: layered_stack_3d(n=8, repeats=2, seed=11),
+}
+
+
+@pytest.mark.parametrize("drop", ["pointwise", "cut"])
+@pytest.mark.parametrize("max_coarse", [1, 2, 7])
+@pytest.mark.parametrize("name", sorted(TINY))
+def test_tiny_coarse_targets_match_oracle(amg, name, max_coarse, drop):
+    """Coarsening toward 1, 2 or 7 unknowns: single-node levels,
+    one-column prolongators, one-row Galerkin products, or stagnation at the
+    level cap.  The GPU ends as the oracle does: the same level sizes,
+    iterations within one and the solution within 1e-6, or the same error
+    status (the two number their statuses alike)."""
+    prob = TINY[name]()
+    kw = dict(drop=drop, max_coarse=max_coarse)
+    banner(f"tiny targets: {name} max_coarse {max_coarse} {drop}")
+    try:
+        orc = oracle.Hierarchy(prob, **kw)
+        ocode = 0
+    except oracle.OracleError as e:
+        orc, ocode = None, e.code
+    try:
+        h = amg.Hierarchy.from_problem(prob, **kw)
+        gcode = 0
+    except amg.AmgError as e:
+        h, gcode = None, e.code
+    print(f"{name} max_coarse {max_coarse} {drop}: oracle status {ocode}, GPU status {gcode}")
+    assert gcode == ocode
+    if orc is None:
+        return
+    n_gpu = h.stats()["n"]
+    assert n_gpu == orc.stats()["n"]
+    xo, io = orc.pcg(prob.b)
+    x, info = h.solve(prob.b, raise_on_error=False)
+    h.close()
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"  levels {n_gpu}, iterations {info['iterations']} (oracle {io['iterations']}), rel err {err:.1e}")
+    assert info["status"] == "OK" and abs(info["iterations"] - io["iterations"]) <= 1 and err <= 1e-6
