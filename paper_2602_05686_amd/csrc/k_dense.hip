@@ -56,53 +56,44 @@ __device__ void tile_mac(double acc[4][4], const double* A, int lda, bool ta, in
     }
 }
 
-// factor the diagonal tile kb; flag <- 1 if not positive definite.  One
-// wavefront, right-looking, thread i holding row i in registers (every index
-// below is a compile-time constant once the loops are unrolled): at step j
-// thread j takes the square root of its fully updated diagonal, every row
-// i > j divides its entry in column j by it and publishes the entry in LDS,
-// then subtracts L_ij L_kj from its entries in columns j < k <= i.  Each
-// entry receives its subtractions in ascending j, the order of the
-// left-looking dot products, and a step's updates are independent of each
-// other.
-constexpr int kPotrfThreads = NB;
+// factor the diagonal tile kb; flag <- 1 if not positive definite.  The
+// tile sits in LDS and a 256-thread block factors it right-looking: at step
+// j one thread takes the square root of the fully updated diagonal, the
+// block divides column j below it, then 16 x 16 threads subtract L_ij L_kj
+// from the entries j < k <= i of the trailing triangle.  Each entry receives
+// its subtractions in ascending j, the order of the left-looking dot
+// products, and a step's updates are independent of each other.
+constexpr int kPotrfThreads = kBlock;
 __global__ __launch_bounds__(kPotrfThreads) void k_potrf_diag(double* A, int n, int kb, int* flag) {
-    __shared__ double C[NB][NB + 1];  // C[k][j] = L_kj once column j is done
+    __shared__ double T[NB][NB + 1];
     const int o = kb * NB;
     const int nb = min(NB, n - o);
-    const int i = threadIdx.x;
-    const bool live = i < nb;
-    double row[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) row[k] = (live && k < nb) ? A[(size_t)(o + i) * n + o + k] : 0.0;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        if (j < nb) {
-            if (i == j) {
-                double d = row[j];
-                if (!(d > 0.0) || !isfinite(d)) {
-                    *flag = 1;
-                    d = 1.0;
-                }
-                row[j] = sqrt(d);
-                C[j][j] = row[j];
-            }
-            __syncthreads();
-            if (live && i > j) {
-                row[j] = row[j] / C[j][j];
-                C[i][j] = row[j];
-            }
-            __syncthreads();
-            const double lij = row[j];
-#pragma unroll
-            for (int k = j + 1; k < NB; ++k)
-                if (live && i >= k) row[k] -= lij * C[k][j];
-        }
+    for (int e = threadIdx.x; e < NB * NB; e += kPotrfThreads) {
+        const int i = e / NB, k = e % NB;
+        T[i][k] = (i < nb && k < nb) ? A[(size_t)(o + i) * n + o + k] : 0.0;
     }
-    if (live)
-#pragma unroll
-        for (int k = 0; k < NB; ++k)
-            if (k < nb) A[(size_t)(o + i) * n + o + k] = (k <= i) ? row[k] : 0.0;
+    __syncthreads();
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int j = 0; j < nb; ++j) {
+        if (threadIdx.x == 0) {
+            double d = T[j][j];
+            if (!(d > 0.0) || !isfinite(d)) {
+                *flag = 1;
+                d = 1.0;
+            }
+            T[j][j] = sqrt(d);
+        }
+        __syncthreads();
+        for (int i = j + 1 + (int)threadIdx.x; i < nb; i += kPotrfThreads) T[i][j] = T[i][j] / T[j][j];
+        __syncthreads();
+        for (int i = j + 1 + ty; i < nb; i += 16)
+            for (int k = j + 1 + tx; k <= i; k += 16) T[i][k] = T[i][k] - T[i][j] * T[k][j];
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < NB * NB; e += kPotrfThreads) {
+        const int i = e / NB, k = e % NB;
+        if (i < nb && k < nb) A[(size_t)(o + i) * n + o + k] = (k <= i) ? T[i][k] : 0.0;
+    }
 }
 
 // rows below the diagonal tile: X L_kk^T = B, one thread per row
