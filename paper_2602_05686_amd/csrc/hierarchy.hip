@@ -281,14 +281,13 @@ DotTarget Hierarchy::dt(int slot) const { return DotTarget{partial.get(), counte
 
 namespace {
 
-// filtered matrix, 1-norm diagonal, damping and smoothed prolongator of
-// level l from its operator, drop mask and aggregates; sets lam_pf and omega
-void smoothed_prolongator(Hierarchy& h, int l, DCsr& P, hipStream_t s) {
+// filtered matrix of level l (the diagonal, lumped, and the entries its drop
+// mask keeps, in the operator's stored order) with its 1-norm diagonal and
+// that diagonal's inverse
+void filtered_operator(Hierarchy& h, int l, DCsr& F, DBuf<double>& dt, DBuf<double>& dtinv, hipStream_t s) {
     Level& L = h.lev[l];
-    const amg_options& opt = h.opt;
     MemCounter* mc = &h.mem;
     const int nl = L.A.n;
-    DCsr F;
     F.n = F.m = nl;
     DBuf<int> cnt(nl, mc), tmp(scan_tmp_size(nl), mc);
     filter_count(L.A, L.mask.get(), cnt.get(), s);
@@ -299,11 +298,23 @@ void smoothed_prolongator(Hierarchy& h, int l, DCsr& P, hipStream_t s) {
     F.nnz = fnnz;
     F.col.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
     F.val.alloc((size_t)(fnnz > 0 ? fnnz : 1), mc);
-    DBuf<double> dt(nl, mc), dtinv(nl, mc);
+    dt.alloc(nl, mc);
+    dtinv.alloc(nl, mc);
     filter_fill(L.A, L.mask.get(), L.dir.get(), F.rowptr.get(), F.col.get(), F.val.get(), dt.get(), dtinv.get(), s);
-    make_blocks(F, mc, s, false);  // ten power steps: not worth packing
+    make_blocks(F, mc, s, false);  // a few passes each: not worth packing
+}
+
+// damping and smoothed prolongator of level l from its filtered matrix F,
+// F's 1-norm diagonal and the aggregates; sets lam_pf and omega
+void smoothed_prolongator(Hierarchy& h, int l, const DCsr& F, const double* dt, const double* dtinv, DCsr& P,
+                          hipStream_t s) {
+    Level& L = h.lev[l];
+    const amg_options& opt = h.opt;
+    MemCounter* mc = &h.mem;
+    const int nl = L.A.n;
+    DBuf<int> cnt(nl, mc), tmp(scan_tmp_size(nl), mc);
     ensure_partial(h, std::max(stream_partials(F), stream_partials(L.A)));
-    L.lam_pf = power_method(F, dtinv.get(), opt.power_iters, stream_key(opt.seed, kPurposePf, l), h, s);
+    L.lam_pf = power_method(F, dtinv, opt.power_iters, stream_key(opt.seed, kPurposePf, l), h, s);
     L.omega = L.lam_pf > 0.0 ? opt.omega_sym / L.lam_pf : 0.0;
     DCsr Ph;
     Ph.n = nl;
@@ -318,7 +329,7 @@ void smoothed_prolongator(Hierarchy& h, int l, DCsr& P, hipStream_t s) {
     Ph.val.alloc((size_t)(pn > 0 ? pn : 1), mc);
     phat_fill(nl, L.agg.get(), Ph.rowptr.get(), Ph.col.get(), Ph.val.get(), s);
     spgemm(F, Ph, P, mc, s);
-    prolongator_finalize(nl, P.rowptr.get(), P.col.get(), P.val.get(), L.agg.get(), dt.get(), L.omega, s);
+    prolongator_finalize(nl, P.rowptr.get(), P.col.get(), P.val.get(), L.agg.get(), dt, L.omega, s);
 }
 
 // Chebyshev bounds and coefficients of every smoothing level
@@ -509,6 +520,13 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
         ldiag.release();
         minv.release();
 
+        // the filtered matrix holds the diagonal and exactly the kept entries
+        // in stored order, so the independent set and the aggregation walk
+        // its pattern with no mask, and the prolongator smooths with it
+        DCsr F;
+        DBuf<double> dt, dtinv;
+        filtered_operator(h, l, F, dt, dtinv, s);
+
         // distance-2 maximal independent set, synchronous rounds
         {
             DBuf<uint8_t> state(nl, mc);
@@ -524,7 +542,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
             for (bool done = false; !done;) {
                 zero_async(und.get(), sizeof(int) * kMisBatch, s);
                 for (int j = 0; j < kMisBatch; ++j)
-                    mis_round(L.A, L.mask.get(), key, state.get(), t1.get(), t2.get(), und.get() + j, s);
+                    mis_round(F, nullptr, key, state.get(), t1.get(), t2.get(), und.get() + j, s);
                 int left[kMisBatch];
                 d2h(left, und.get(), kMisBatch, s);
                 for (int j = 0; j < kMisBatch && !done; ++j) {
@@ -547,11 +565,14 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
                          std::to_string(nl) + ")");
             L.nc = nagg;
             L.agg.alloc(nl, mc);
-            agg_assign(nl, L.A.rowptr.get(), L.A.col.get(), L.mask.get(), L.dir.get(), state.get(), rank.get(),
-                       phase2.get(), L.agg.get(), flags.get(), und.get(), s);
+            agg_assign(nl, F.rowptr.get(), F.col.get(), nullptr, L.dir.get(), state.get(), rank.get(), phase2.get(),
+                       L.agg.get(), flags.get(), und.get(), s);
         }
 
-        smoothed_prolongator(h, l, L.P, s);
+        smoothed_prolongator(h, l, F, dt.get(), dtinv.get(), L.P, s);
+        F = DCsr();
+        dt.release();
+        dtinv.release();
         transpose(L.P, L.R, mc, s);
         Level& C = h.lev[l + 1];
         {
@@ -643,8 +664,10 @@ void update_values(Hierarchy& h, const double* val, bool host_ptrs, hipStream_t 
         diag_inverse_blocks(L.A, L.dinv.get(), s);
         if (l + 1 == h.nlev) break;
         {
-            DCsr P;
-            smoothed_prolongator(h, l, P, s);
+            DCsr F, P;
+            DBuf<double> dt, dtinv;
+            filtered_operator(h, l, F, dt, dtinv, s);
+            smoothed_prolongator(h, l, F, dt.get(), dtinv.get(), P, s);
             take_values(L.P, P, "P");
         }
         {

@@ -460,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_mis_hop(const int* rowptr, const int
                 const int t = (int)threadIdx.x + u * kBlock;
                 const int k = rb.k0 + (t < rb.cnt ? t : rb.cnt - 1);
                 c[u] = col[k];
-                m[u] = mask[k];
+                m[u] = mask ? mask[k] : (uint8_t)1;
             }
             uint64_t v[U];
 #pragma unroll
@@ -485,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_mis_hop(const int* rowptr, const int
         uint64_t best = 0ull;
         for (int t = threadIdx.x; t < rb.cnt; t += kBlock) {
             const int k = rb.k0 + t;
-            if (mask[k]) {
+            if (!mask || mask[k]) {
                 const uint64_t v = tuple_at(col[k]);
                 best = v > best ? v : best;
             }
@@ -552,7 +552,7 @@ __global__ void k_agg_phase2(int n, const int* rowptr, const int* col, const uin
                 for (int u = 0; u < 8; ++u) {
                     const int k = min(k0 + u, hi - 1);
                     c[u] = col[k];
-                    m[u] = mask[k];
+                    m[u] = mask ? mask[k] : (uint8_t)1;
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) st[u] = state[c[u]];
@@ -587,7 +587,7 @@ __global__ void k_agg_phase2_long(const int* rowptr, const int* col, const uint8
             for (int u = 0; u < 4; ++u) {
                 const int k = min(k0 + u * 64, hi - 1);
                 c[u] = col[k];
-                m[u] = mask[k];
+                m[u] = mask ? mask[k] : (uint8_t)1;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) st[u] = state[c[u]];
@@ -619,7 +619,7 @@ __device__ __forceinline__ int phase3_candidate(const int* col, const uint8_t* m
                                                 int hi) {
     if (k >= hi) return -1;
     const int j = col[k];
-    if (j == i || !mask[k]) return -1;
+    if (j == i || (mask && !mask[k])) return -1;
     return phase2[j];  // -1 if j is unassigned too
 }
 

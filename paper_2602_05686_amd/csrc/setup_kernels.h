@@ -37,12 +37,15 @@ void soc_mask(const DCsr& A, const uint8_t* dir, const double* lval, const doubl
 void cut_drop(const DCsr& A, const uint8_t* dir, const double* lval, const double* ldiag, double theta,
               uint8_t* keep, uint8_t* mask, hipStream_t s);
 void mis_init(int n, const uint8_t* dir, uint8_t* state, hipStream_t s);
-// one synchronous round; *undecided (device, zero on entry) receives the number of nodes still undecided
+// one synchronous round over the entries mask keeps (nullptr: every stored
+// entry); *undecided (device, zero on entry) receives the number of nodes
+// still undecided
 void mis_round(const DCsr& A, const uint8_t* mask, uint64_t key, uint8_t* state, uint64_t* t1, uint64_t* t2,
                int* undecided, hipStream_t s);
 void agg_root_flags(int n, const uint8_t* state, int* flags, hipStream_t s);
-// phase 2 (neighbours of roots) and phase 3 (leftovers); list: n ints and
-// nlist: one int of device scratch
+// phase 2 (neighbours of roots) and phase 3 (leftovers) over the entries
+// mask keeps (nullptr: every stored entry); list: n ints and nlist: one int
+// of device scratch
 void agg_assign(int n, const int* rowptr, const int* col, const uint8_t* mask, const uint8_t* dir,
                 const uint8_t* state, const int* root_rank, int* phase2, int* agg, int* list, int* nlist,
                 hipStream_t s);
