@@ -586,21 +586,36 @@ __device__ __forceinline__ void gemv_body(const GemvArgs<T>& a, int lb) {
     const int row = lb * (kBlock / 64) + (threadIdx.x >> 6);
     if (row >= a.n) return;
     const double* m = a.M + (size_t)row * a.n;
-    // lane-strided sum (columns lane, lane + 64, ... in order), eight loads
-    // of the row in flight at a time
-    double s = 0.0;
-    int j = lane;
-    for (; j + 7 * 64 < a.n; j += 8 * 64) {
-        double mv[8], iv[8];
+    const int n = a.n;
+    // lane-strided sum (columns lane, lane + 64, ... in order) over chunks of
+    // sixteen columns per lane; the next chunk's loads are issued before the
+    // current chunk is summed, so a row costs about one memory latency
+    // instead of one per chunk.  Indices past the row's end are clamped to
+    // its last column and their products skipped.
+    constexpr int U = 16;
+    double mv[U], iv[U];
+    auto load = [&](int j0) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            mv[u] = m[j + u * 64];
-            iv[u] = (double)a.in[j + u * 64];
+        for (int u = 0; u < U; ++u) {
+            const int j = min(j0 + u * 64, n - 1);
+            mv[u] = m[j];
+            iv[u] = (double)a.in[j];
         }
+    };
+    double s = 0.0;
+    load(lane);
+    for (int j0 = lane; j0 < n; j0 += U * 64) {
+        double cm[U], ci[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += mv[u] * iv[u];
+        for (int u = 0; u < U; ++u) {
+            cm[u] = mv[u];
+            ci[u] = iv[u];
+        }
+        if (j0 + U * 64 < n) load(j0 + U * 64);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + u * 64 < n) s += cm[u] * ci[u];
     }
-    for (; j < a.n; j += 64) s += m[j] * (double)a.in[j];
     s = wave_sum(s);
     if (lane == 0) a.out[row] = (T)s;
 }
