@@ -656,6 +656,9 @@ def main():
     ap.add_argument("--aniso-n", type=int, default=96,
                     help="hexes per side of the rotated-anisotropy FP32/FP64 comparison (0: skip)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-studies", action="store_true",
+                    help="skip the strength-measure comparison, the drop-tolerance sweep and the annulus study "
+                         "(about 45 s; each also runs alone with --compare, --sweep, --annulus)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream (its JSON object)")
     ap.add_argument("--compare", action="store_true",
                     help="run only the strength-measure / dropping comparison (its JSON object)")
@@ -845,6 +848,12 @@ def main():
         torch.cuda.empty_cache()
         c4 = run_layered192(args, amg, dev, log)
 
+    # the paper's parameter studies on their synthetic stand-ins (their own
+    # JSON objects under "studies"; outside the timed region)
+    studies = None
+    if not args.no_studies:
+        studies = {"compare": run_compare(amg, log), "sweep": run_sweep(args, amg, log),
+                   "annulus": run_annulus(args, amg, log)}
     serving = None
     if not args.no_serving:
         torch.cuda.empty_cache()
@@ -910,6 +919,7 @@ def main():
         "fp32_form": fp32,
         "layered192": c4,
         "serving": serving,
+        "studies": studies,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
