@@ -342,18 +342,67 @@ void smoother_bounds(Hierarchy& h, hipStream_t s) {
     }
 }
 
-// dense inverse of the coarsest operator through its Cholesky factor
-void coarse_inverse(Hierarchy& h, int* flag, hipStream_t s) {
-    Level& C = h.lev[h.nlev - 1];
+// dense inverse of the coarsest operator through its Cholesky factor,
+// enqueued on q (h.Ainv and work, nc * nc doubles each, allocated by the
+// caller); *flag becomes 1 if the operator is not positive definite
+void coarse_inverse_enqueue(Hierarchy& h, double* work, int* flag, hipStream_t q) {
+    const Level& C = h.lev[h.nlev - 1];
     const int nc = C.A.n;
+    zero_async(h.Ainv.get(), sizeof(double) * (size_t)nc * nc, q);
+    densify(nc, C.A.rowptr.get(), C.A.col.get(), C.A.val.get(), h.Ainv.get(), q);
+    dense_spd_inverse(nc, h.Ainv.get(), work, flag, q);
+}
+
+void coarse_inverse_alloc(Hierarchy& h) {
+    const int nc = h.lev[h.nlev - 1].A.n;
     h.nL = nc;
     if (h.Ainv.size() != (size_t)nc * nc) h.Ainv.alloc((size_t)nc * nc, &h.mem);
-    zero_async(h.Ainv.get(), sizeof(double) * (size_t)nc * nc, s);
-    densify(nc, C.A.rowptr.get(), C.A.col.get(), C.A.val.get(), h.Ainv.get(), s);
-    DBuf<double> work((size_t)nc * nc, &h.mem);
-    if (!dense_spd_inverse(nc, h.Ainv.get(), work.get(), flag, s))
-        fail(AMG_ERR_NOT_SPD, "coarsest operator is not positive definite (n=" + std::to_string(nc) + ")");
 }
+
+void coarse_inverse_check(Hierarchy& h, int* flag, hipStream_t s) {
+    if (read_flag(flag, s))
+        fail(AMG_ERR_NOT_SPD, "coarsest operator is not positive definite (n=" + std::to_string(h.nL) + ")");
+}
+
+// A library stream that runs work beside stream s: everything enqueued on s
+// before construction runs first, and join() makes s wait for all of it.
+// Without a join (an error on s's side) the destructor waits for the side
+// stream itself, so no buffer it uses is released to the pool while it runs.
+class SideStream {
+  public:
+    explicit SideStream(hipStream_t s) : s_(s), side_(take_stream()) {
+        if (hipEventCreateWithFlags(&ev_, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            give_stream(side_);
+            fail(AMG_ERR_HIP, "hipEventCreateWithFlags failed");
+        }
+        if (hipEventRecord(ev_, s_) != hipSuccess || hipStreamWaitEvent(side_, ev_, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipEventDestroy(ev_);
+            give_stream(side_);
+            fail(AMG_ERR_HIP, "ordering a side stream after the setup stream failed");
+        }
+    }
+    SideStream(const SideStream&) = delete;
+    SideStream& operator=(const SideStream&) = delete;
+    hipStream_t get() const { return side_; }
+    void join() {
+        MATAMG_HIP(hipEventRecord(ev_, side_));
+        MATAMG_HIP(hipStreamWaitEvent(s_, ev_, 0));
+        joined_ = true;
+    }
+    ~SideStream() {
+        if (!joined_) (void)hipStreamSynchronize(side_);
+        (void)hipEventDestroy(ev_);
+        give_stream(side_);
+    }
+
+  private:
+    hipStream_t s_;
+    hipStream_t side_;
+    hipEvent_t ev_ = nullptr;
+    bool joined_ = false;
+};
 
 // FP32 copies of A, D^{-1}, P and R on the smoothing levels
 void cast_fp32(Hierarchy& h, hipStream_t s) {
@@ -596,11 +645,22 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
     }
     h.nlev = l + 1;
     ensure_partial(h, stream_partials(h.lev[0].A));
-    if (wide_blocks)
-        for (int k = 0; k < h.nlev; ++k) widen_stream_blocks(h.lev[k].A, wide_block_min(k, h.fp32), mc, s);
 
-    smoother_bounds(h, s);
-    coarse_inverse(h, flag.get(), s);
+    {
+        // the dense coarse inverse reads only the coarsest operator and runs
+        // a few workgroups at a time: it goes on a second stream while the
+        // partitions are widened and the smoother bounds estimated on this one
+        coarse_inverse_alloc(h);
+        DBuf<double> work((size_t)h.nL * h.nL, mc);
+        DBuf<int> cflag(1, mc);
+        SideStream side(s);
+        coarse_inverse_enqueue(h, work.get(), cflag.get(), side.get());
+        if (wide_blocks)
+            for (int k = 0; k < h.nlev; ++k) widen_stream_blocks(h.lev[k].A, wide_block_min(k, h.fp32), mc, s);
+        smoother_bounds(h, s);
+        side.join();
+        coarse_inverse_check(h, cflag.get(), s);
+    }
 
     // work vectors and reduced-precision copies
     for (int k = 0; k < h.nlev; ++k) {
@@ -680,8 +740,17 @@ void update_values(Hierarchy& h, const double* val, bool host_ptrs, hipStream_t 
         spgemm(L.R, AP, Ac, mc, s);
         take_values(h.lev[l + 1].A, Ac, "a coarse operator");
     }
-    smoother_bounds(h, s);
-    coarse_inverse(h, flag.get(), s);
+    {
+        // as in the setup: the dense coarse inverse beside the smoother bounds
+        coarse_inverse_alloc(h);
+        DBuf<double> work((size_t)h.nL * h.nL, mc);
+        DBuf<int> cflag(1, mc);
+        SideStream side(s);
+        coarse_inverse_enqueue(h, work.get(), cflag.get(), side.get());
+        smoother_bounds(h, s);
+        side.join();
+        coarse_inverse_check(h, cflag.get(), s);
+    }
     if (h.fp32) cast_fp32(h, s);
     // the captured CG steps hold the old smoother coefficients as kernel arguments
     for (auto& g : h.graph)

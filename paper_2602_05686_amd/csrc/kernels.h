@@ -96,8 +96,9 @@ void fill_seeded_uniform(int64_t n, uint64_t key, double* v, hipStream_t s);
 // out = Minv * in for a dense row-major n x n FP64 matrix; in/out of type T
 template <typename T>
 void dense_gemv(int n, const double* M, const T* in, T* out, hipStream_t s);
-// A (n x n, row-major, symmetric) -> A^{-1} in place via blocked Cholesky.
-// Returns false if the matrix is not positive definite.  work: n*n doubles.
-bool dense_spd_inverse(int n, double* A, double* work, int* flag, hipStream_t s);
+// A (n x n, row-major, symmetric) -> A^{-1} in place via blocked Cholesky,
+// enqueued on s; *flag (device int, set to 0 here) becomes 1 if the matrix is
+// not positive definite, and A then holds no inverse.  work: n*n doubles.
+void dense_spd_inverse(int n, double* A, double* work, int* flag, hipStream_t s);
 
 }  // namespace matamg
