@@ -607,11 +607,25 @@ __global__ void k_agg_phase2_long(const int* rowptr, const int* col, const uint8
 // aggregates among the row's kept neighbours, counts each with ballots and
 // keeps (largest count, smallest id).  The outcome of a node
 // depends only on phase 2, so the list order does not matter.
+// every lane with `want` set appends `value` to list (length *nlist): one
+// atomic per wavefront, the lanes in lane order after the wavefront's base
+__device__ __forceinline__ void wave_append(bool want, int value, int* list, int* nlist) {
+    const unsigned long long m = __ballot(want);
+    if (!want) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int leader = __builtin_ctzll(m);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(nlist, __popcll(m));
+    base = __shfl(base, leader, 64);
+    list[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
+}
+
 __global__ void k_agg_phase3_split(int n, const uint8_t* dir, const int* phase2, int* agg, int* list, int* nlist) {
     ROW_LOOP(i, n) {
         const int a = phase2[i];
-        if (a < 0 && !(dir && dir[i])) list[atomicAdd(nlist, 1)] = (int)i;
-        else agg[i] = a;
+        const bool left = a < 0 && !(dir && dir[i]);
+        if (!left) agg[i] = a;
+        wave_append(left, (int)i, list, nlist);
     }
 }
 

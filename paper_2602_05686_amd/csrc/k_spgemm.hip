@@ -440,21 +440,72 @@ __device__ void numeric_row_big(int i, const int* arp, const int* acol, const do
     }
     for (int e = tid; e < d; e += kBlock) acc[e] = 0.0;
     __syncthreads();
-    if (w == 0) {
-        for_each_product<true>(arp, acol, aval, brp, bcol, bval, i,
-                               [&](bool valid, int c, double pv, int t0, int total, int seg) {
-                                   int r = valid ? vals[hash_find_fresh<false>(keys, mask, c)] : 0;
-                                   r = (r >= 0 && r < d) ? r : 0;
-                                   const int m = min(64, total - t0);
-                                   const int s0 = __shfl(seg, 0, 64), s1 = __shfl(seg, m - 1, 64);
-                                   for (int sg = s0; sg <= s1; ++sg) {
-                                       if (valid && seg == sg) acc[r] += pv;
-                                       phase_fence<false>();
-                                   }
-                                   return true;
-                               });
+    // Accumulation in canonical product order by every wavefront: within
+    // each chunk of 64 A entries the wavefronts take the chunk's steps of 64
+    // products in turn (wavefront w the steps w, w + kWaves, ...).  In a
+    // round each wavefront loads its step's products and output positions,
+    // then the round's steps are added in step order, one wavefront after
+    // the other between barriers, each step's segments one after the other
+    // as on the wavefront path: every entry receives the same additions in
+    // the same order, while the loads of kWaves steps are in flight at once.
+    const int a0 = arp[i], a1 = arp[i + 1];
+    for (int c0 = a0; c0 < a1; c0 += 64) {
+        const int ka = c0 + lane;
+        int blen = 0, bstart = 0;
+        double av = 0.0;
+        if (ka < a1) {
+            const int k = acol[ka];
+            bstart = brp[k];
+            blen = brp[k + 1] - bstart;
+            av = aval[ka];
+        }
+        int incl = blen;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        const int excl = incl - blen;
+        const int total = __shfl(incl, 63, 64);
+        const int nsteps = (total + 63) / 64;  // the same in every wavefront
+        for (int sr = 0; sr < nsteps; sr += kWaves) {
+            const int st = sr + w;
+            const int t0 = st * 64;
+            const int t = t0 + lane;
+            const bool valid = st < nsteps && t < total;
+            // source A entry of product t: the last lane whose exclusive
+            // offset is <= t (empty B rows lose to the next non-empty one)
+            int lo = 0, hi = 63;
+            for (int it = 0; it < 6; ++it) {
+                const int mid = (lo + hi + 1) >> 1;
+                const int om = __shfl(excl, mid, 64);
+                if (om <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const int sb = __shfl(bstart, lo, 64);
+            const int so = __shfl(excl, lo, 64);
+            const double sa = __shfl(av, lo, 64);
+            int r = 0;
+            double pv = 0.0;
+            if (valid) {
+                const int kb = sb + (t - so);
+                const int c = bcol[kb];
+                pv = sa * bval[kb];
+                r = vals[hash_find_fresh<false>(keys, mask, c)];
+                r = (r >= 0 && r < d) ? r : 0;
+            }
+            const int m = st < nsteps ? min(64, total - t0) : 0;
+            const int s0 = __shfl(lo, 0, 64), s1 = __shfl(lo, m > 0 ? m - 1 : 0, 64);
+            for (int q = 0; q < kWaves; ++q) {
+                if (q == w && m > 0) {
+                    for (int sg = s0; sg <= s1; ++sg) {
+                        if (valid && lo == sg) acc[r] += pv;
+                        phase_fence<false>();
+                    }
+                }
+                __syncthreads();
+            }
+        }
     }
-    __syncthreads();
     for (int e = tid; e < d; e += kBlock) cval[base + e] = acc[e];
     __syncthreads();  // the tables are reused by the workgroup's next row
 }
