@@ -50,9 +50,14 @@ def setup(trace_csv, top=25):
     t = times[a:b]
     wall = t[-1][1] - t[0][0]
     busy = sum(d for _, _, d in win)
-    gaps = sum(max(0, y[0] - x[1]) for x, y in zip(t, t[1:]))
-    print(f"setup window {wall / 1e6:.2f} ms: kernels {busy / 1e6:.2f} ms ({len(win)} launches), "
-          f"gaps {gaps / 1e6:.2f} ms\n")
+    # idle: time with no kernel running on any stream (kernels of the setup's
+    # side stream overlap those of its main stream)
+    gaps, end = 0, t[0][1]
+    for st, en in t[1:]:
+        gaps += max(0, st - end)
+        end = max(end, en)
+    print(f"setup window {wall / 1e6:.2f} ms: kernels {busy / 1e6:.2f} ms ({len(win)} launches, summed over "
+          f"streams), no kernel running {gaps / 1e6:.2f} ms\n")
     per = collections.defaultdict(lambda: [0, 0])
     for k, _, d in win:
         name = k if k.startswith("k_stream") else k.split("<")[0]
