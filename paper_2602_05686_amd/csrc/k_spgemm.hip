@@ -28,7 +28,7 @@ namespace {
 constexpr int kWaves = kBlock / 64;
 constexpr int kHS = 1024;     // LDS hash slots per wave
 constexpr int kDMax = 512;    // max distinct columns on the LDS path
-constexpr int kHSSmall = 256; // LDS hash slots per wave for rows of at most 128 products
+constexpr int kHSSmall = 256; // LDS hash slots per wave for rows of at most 128 distinct columns
 constexpr int kRankTile = 1024;  // LDS tile of the column list when ranking long rows
 constexpr int kRankKeys = 8;     // keys per lane per ranking pass
 constexpr int kDBig = 4096;      // overflow rows with at most this many columns: numeric phase in LDS
@@ -128,7 +128,8 @@ __device__ __forceinline__ int row_products(const int* arp, const int* acol, con
     return m;
 }
 
-// LDS table size for a row with m products: a power of two >= 2m, 64..kHS
+// LDS table size for m keys (products in the symbolic phase, distinct
+// columns in the numeric one): a power of two >= 2m, 64..kHS
 __device__ __forceinline__ unsigned lds_table_mask(int m) {
     unsigned t = 64;
     while (t < 2u * (unsigned)m && t < (unsigned)kHS) t <<= 1;
@@ -229,11 +230,13 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
     constexpr bool GLOBAL = MODE == N_GLOBAL;
     const int lane = threadIdx.x & 63;
     const int i = rows ? rows[ridx] : ridx;
-    int m = 0;
     if constexpr (MODE == N_LDS) {
+        // routed by the row's distinct columns (known from the symbolic
+        // phase): a table of at least twice as many slots holds them all, so
+        // rows of many products but few columns take the small tables
         if (skip && skip[i]) return;
-        m = pcount[i];
-        if (m <= mlo || m > mhi) return;
+        const int dc = crp[i + 1] - crp[i];
+        if (dc <= mlo || dc > mhi) return;
     } else {
         // overflow rows of up to kDBig columns take the large LDS table
         if (crp[i + 1] - crp[i] <= kDBig) return;
@@ -251,7 +254,7 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
         keys = lds_keys;
         vals = lds_vals;
         acc = lds_acc;
-        mask = lds_table_mask(m);
+        mask = lds_table_mask(crp[i + 1] - crp[i]);
     }
     for (unsigned h = lane; h <= mask; h += 64) {
         keys[h] = -1;
@@ -348,9 +351,9 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
     for (int e = lane; e < d; e += 64) cval[base + e] = acc[e];
 }
 
-// LDS path (N_LDS): the rows of the list whose product count m lies in
-// (mlo, mhi] and that did not overflow (skip), with HS hash slots per wave
-// (HS >= 2 * mhi unless HS = kHS); N_GLOBAL: the listed overflow rows with
+// LDS path (N_LDS): the rows of the list whose distinct column count lies in
+// (mlo, mhi] and that did not overflow (skip), with HS >= 2 * mhi hash slots
+// per wave; N_GLOBAL: the listed overflow rows with
 // more than kDBig columns.  A wavefront per row, grid-stride; nrows_dev (if
 // set) holds the count.
 template <int MODE, int HS>
@@ -878,7 +881,8 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
         hipLaunchKernelGGL(k_spgemm_numeric_thread<kThreadCols>, dim3(g1(n)), dim3(kBlock), 0, s, n, A.rowptr.get(),
                            A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(), B.val.get(),
                            (const int*)pcount.get(), C.rowptr.get(), C.col.get(), C.val.get(), kThreadCols / 2);
-        // wide rows with few products: small tables, so more wavefronts fit a CU
+        // wide rows with few distinct columns: small tables, so more
+        // wavefronts fit a CU
         hipLaunchKernelGGL((k_spgemm_numeric<N_LDS, kHSSmall>), dim3(wgrid), dim3(kBlock), 0, s, 0, nwide_dev,
                            (const int*)wl.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(), B.col.get(),
                            B.val.get(), C.rowptr.get(), C.col.get(), C.val.get(), (const int*)flags.get(),
