@@ -241,6 +241,23 @@ __device__ __forceinline__ double edge_l(const SocArgs& a, int i, int k) {
     return 1.0 / q;
 }
 
+// s plus the positive values of l[lo..hi) in ascending order, the loads of
+// eight values issued before any is added
+__device__ __forceinline__ double positive_sum(const double* l, int lo, int hi, double s) {
+    int k = lo;
+    for (; k + 8 <= hi; k += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = l[k + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (v[u] > 0.0) s += v[u];
+    }
+    for (; k < hi; ++k)
+        if (l[k] > 0.0) s += l[k];
+    return s;
+}
+
 // the row's L_ii: ascending sum of the positive |L_ij| (or |A_ii| for the classical measure)
 __device__ __forceinline__ double row_diag(const SocArgs& a, int i, const double* l, int base) {
     const int lo = a.rowptr[i], hi = a.rowptr[i + 1];
@@ -250,12 +267,7 @@ __device__ __forceinline__ double row_diag(const SocArgs& a, int i, const double
             if (a.col[k] == i) ad = fabs(a.val[k]);
         return ad;
     }
-    double li = 0.0;
-    for (int k = lo; k < hi; ++k) {
-        const double v = l[k - base];
-        if (v > 0.0) li += v;
-    }
-    return li;
+    return positive_sum(l, lo - base, hi - base, 0.0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_soc_values(SocArgs a) {
@@ -275,11 +287,28 @@ __global__ __launch_bounds__(kBlock) void k_soc_values(SocArgs a) {
         const int r = rb.r0 + (int)threadIdx.x;
         if (r < rb.r1) a.ldiag[r] = row_diag(a, r, lv, rb.k0);
     } else {
+        // one long row, kStreamCap entries at a time: the block computes a
+        // piece's values into memory and LDS, then thread 0 continues the
+        // row's ascending sum over the piece from LDS (the order row_diag
+        // adds in); the classical measure's |A_ii| is the diagonal entry's
+        __shared__ double li;
         const int i = rb.r0;
-        for (int t = threadIdx.x; t < rb.cnt; t += kBlock) a.lval[rb.k0 + t] = edge_l(a, i, rb.k0 + t);
-        __threadfence_block();
+        if (threadIdx.x == 0) li = 0.0;
+        for (int c0 = 0; c0 < rb.cnt; c0 += kStreamCap) {
+            const int cn = rb.cnt - c0 < kStreamCap ? rb.cnt - c0 : kStreamCap;
+            __syncthreads();  // the previous piece has been summed
+            for (int t = threadIdx.x; t < cn; t += kBlock) {
+                const int k = rb.k0 + c0 + t;
+                const double l = edge_l(a, i, k);
+                a.lval[k] = l;
+                lv[t] = l;
+                if (a.soc == AMG_SOC_SA && a.col[k] == i) li = fabs(a.val[k]);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0 && a.soc != AMG_SOC_SA) li = positive_sum(lv, 0, cn, li);
+        }
         __syncthreads();
-        if (threadIdx.x == 0) a.ldiag[i] = row_diag(a, i, a.lval, 0);
+        if (threadIdx.x == 0) a.ldiag[i] = li;
     }
 }
 
@@ -729,30 +758,56 @@ struct FilterAcc {
 
 __device__ __forceinline__ FilterAcc filter_begin(int p) { return FilterAcc{p, p, -1, 0.0, 0.0, 0.0}; }
 
-// the row's entries lo..hi of cs/vs/ms, next in stored order
+// one entry of the row, in stored order
+__device__ __forceinline__ void filter_entry(int i, int j, double v, uint8_t m, FilterAcc& f, int* fcol,
+                                             double* fval) {
+    f.rowabs += fabs(v);
+    if (j == i || m) {
+        if (j == i) f.diagpos = f.p;
+        else f.keptabs += fabs(v);
+        fcol[f.p] = j;
+        fval[f.p] = v;
+        f.p++;
+    } else {
+        f.lump += v;
+    }
+}
+
+// the row's entries lo..hi of cs/vs/ms, next in stored order; the LDS loads
+// of eight entries are issued before any of them is used
 __device__ __forceinline__ void filter_entries(int i, const int* cs, const double* vs, const uint8_t* ms, int lo,
                                                int hi, FilterAcc& f, int* fcol, double* fval) {
-    for (int k = lo; k < hi; ++k) {
-        const int j = cs[k];
-        const double v = vs[k];
-        f.rowabs += fabs(v);
-        if (j == i || ms[k]) {
-            if (j == i) f.diagpos = f.p;
-            else f.keptabs += fabs(v);
-            fcol[f.p] = j;
-            fval[f.p] = v;
-            f.p++;
-        } else {
-            f.lump += v;
+    int k = lo;
+    for (; k + 8 <= hi; k += 8) {
+        int j[8];
+        double v[8];
+        uint8_t m[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            j[u] = cs[k + u];
+            v[u] = vs[k + u];
+            m[u] = ms[k + u];
         }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) filter_entry(i, j[u], v[u], m[u], f, fcol, fval);
     }
+    for (; k < hi; ++k) filter_entry(i, cs[k], vs[k], ms[k], f, fcol, fval);
 }
 
 __device__ __forceinline__ void filter_end(int i, bool dirichlet, const FilterAcc& f, double* fval, double* dt,
                                            double* dtinv) {
     if (f.diagpos >= 0) fval[f.diagpos] = fval[f.diagpos] + f.lump;
+    // the filtered row read back in order, eight loads in flight at a time
     double s = 0.0;
-    for (int q = f.p0; q < f.p; ++q) s += fabs(fval[q]);
+    int q = f.p0;
+    for (; q + 8 <= f.p; q += 8) {
+        double w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w[u] = fval[q + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += fabs(w[u]);
+    }
+    for (; q < f.p; ++q) s += fabs(fval[q]);
     const bool isolated = !dirichlet && !(f.keptabs > kRowNoise * f.rowabs);
     if (isolated || !(s > kRowNoise * f.rowabs)) s = 0.0;
     dt[i] = s;
