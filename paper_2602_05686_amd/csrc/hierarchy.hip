@@ -639,8 +639,6 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
             coarse_aux(L.nc, dim, mem, L.x.get(), L.sig.get(), C.x.get(), C.sig.get(), s);
             MATAMG_HIP(hipStreamSynchronize(s));
         }
-        make_blocks(L.P, mc, s);
-        make_blocks(L.R, mc, s);
         h.nlev = l + 2;
     }
     h.nlev = l + 1;
@@ -649,12 +647,19 @@ std::unique_ptr<Hierarchy> build_hierarchy(int64_t n64, const int* rowptr, const
     {
         // the dense coarse inverse reads only the coarsest operator and runs
         // a few workgroups at a time: it goes on a second stream while the
-        // partitions are widened and the smoother bounds estimated on this one
+        // transfer operators are partitioned, the operators' partitions
+        // widened and the smoother bounds estimated on this one
         coarse_inverse_alloc(h);
         DBuf<double> work((size_t)h.nL * h.nL, mc);
         DBuf<int> cflag(1, mc);
         SideStream side(s);
         coarse_inverse_enqueue(h, work.get(), cflag.get(), side.get());
+        // the transfer operators' streaming partitions serve only the
+        // V-cycle, so they are made here, beside the coarse inverse too
+        for (int k = 0; k + 1 < h.nlev; ++k) {
+            make_blocks(h.lev[k].P, mc, s);
+            make_blocks(h.lev[k].R, mc, s);
+        }
         if (wide_blocks)
             for (int k = 0; k < h.nlev; ++k) widen_stream_blocks(h.lev[k].A, wide_block_min(k, h.fp32), mc, s);
         smoother_bounds(h, s);
