@@ -56,6 +56,18 @@ __device__ __forceinline__ int hash_insert(int* keys, unsigned mask, int key) {
     return -1;
 }
 
+// slot of key, inserting it if absent (the table has room for every key of
+// the row: at least twice as many slots)
+__device__ __forceinline__ unsigned hash_insert_slot(int* keys, unsigned mask, int key) {
+    unsigned h = hash_slot(key, mask);
+    for (unsigned probe = 0; probe <= mask; ++probe) {
+        const int old = atomicCAS(keys + h, -1, key);
+        if (old == -1 || old == key) return h;
+        h = (h + 1) & mask;
+    }
+    return 0;
+}
+
 // Enumerate the products of row i of A*B in canonical order, 64 per step
 // (with stride > 1, only the steps s with s % stride == offset).
 // f(valid, colB, value, t0, total, seg) is called by every lane for each step
@@ -256,6 +268,55 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
         acc = lds_acc;
         mask = lds_table_mask(crp[i + 1] - crp[i]);
     }
+    if constexpr (MODE == N_LDS) {
+        // One walk over the products: each takes its column's hash slot
+        // (inserting the column on first sight) and is added to that slot's
+        // running sum in canonical order, the segments of a step one after
+        // the other as below; then the occupied slots are ranked by column
+        // and written out.  Every entry receives the same additions in the
+        // same order as on the two-walk path (a zeroed sum plus the first
+        // product, then the others).
+        for (unsigned h = lane; h <= mask; h += 64) {
+            keys[h] = -1;
+            acc[h] = 0.0;
+        }
+        phase_fence<false>();
+        for_each_product<true>(arp, acol, aval, brp, bcol, bval, i,
+                               [&](bool valid, int c, double pv, int t0, int total, int seg) {
+                                   const unsigned h = valid ? hash_insert_slot(keys, mask, c) : 0u;
+                                   const int m = min(64, total - t0);
+                                   const int s0 = __shfl(seg, 0, 64), s1 = __shfl(seg, m - 1, 64);
+                                   for (int sg = s0; sg <= s1; ++sg) {
+                                       if (valid && seg == sg) acc[h] += pv;
+                                       phase_fence<false>();
+                                   }
+                                   return true;
+                               });
+        phase_fence<false>();
+        const int base = crp[i];
+        const int d = crp[i + 1] - base;
+        int* lst = vals;  // the row's columns, compacted (arbitrary order)
+        int filled = 0;
+        for (unsigned h0 = 0; h0 <= mask; h0 += 64) {
+            const unsigned h = h0 + lane;
+            const int key = (h <= mask) ? keys[h] : -1;
+            const bool occ = key >= 0;
+            const uint64_t bal = __ballot(occ);
+            const int before = __popcll(bal & ((1ull << lane) - 1ull));
+            if (occ && filled + before < d) lst[filled + before] = key;
+            filled += __popcll(bal);
+        }
+        phase_fence<false>();
+        for (int e = lane; e < d; e += 64) {
+            const int c = lst[e];
+            int r = 0;
+            for (int q = 0; q < d; ++q) r += (lst[q] < c);
+            ccol[base + r] = c;
+            cval[base + r] = acc[hash_find_fresh<false>(keys, mask, c)];
+        }
+        phase_fence<false>();  // the tables are reused by the wavefront's next row
+        return;
+    }
     for (unsigned h = lane; h <= mask; h += 64) {
         keys[h] = -1;
         vals[h] = 0;
@@ -366,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
     constexpr bool GLOBAL = MODE == N_GLOBAL;
     __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS];
     __shared__ int svals[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS];
-    __shared__ double sacc[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS / 2];
+    __shared__ double sacc[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : HS];  // one running sum per hash slot
     __shared__ int stile[GLOBAL ? kWaves : 1][GLOBAL ? kRankTile : 1];
     const int w = threadIdx.x >> 6;
     const int nr = nrows_dev ? *nrows_dev : nrows;
