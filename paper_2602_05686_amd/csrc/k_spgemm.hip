@@ -33,8 +33,8 @@ constexpr int kRankTile = 1024;  // LDS tile of the column list when ranking lon
 constexpr int kRankKeys = 8;     // keys per lane per ranking pass
 constexpr int kDBig = 4096;      // overflow rows with at most this many columns: numeric phase in LDS
 constexpr int kHSBig = 8192;     // their LDS hash slots (one workgroup per row)
-// dynamic LDS of the large-table workgroup: keys and ranks per slot, one accumulator per column
-constexpr size_t kBigLds = sizeof(int) * 2 * kHSBig + sizeof(double) * kDBig;
+// dynamic LDS of the large-table workgroup: a key, a list entry and a running sum per slot
+constexpr size_t kBigLds = (sizeof(int) * 2 + sizeof(double)) * kHSBig;
 // numeric phase of the wavefront path: LDS table per wavefront (rows of at
 // most kDMax columns) or global-memory table (overflow rows of more than
 // kDBig columns); the overflow rows in between take numeric_row_big
@@ -438,9 +438,16 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int*
 }
 
 // Overflow row i with at most kDBig columns, by a whole workgroup of kWaves
-// wavefronts on one table in LDS: the wavefronts share the symbolic
-// insertion (every kWaves-th step of 64 products each) and the ranking, and
-// wavefront 0 alone accumulates, in canonical order as numeric_row does.
+// wavefronts on one table in LDS.  Within each chunk of 64 A entries the
+// wavefronts take the chunk's steps of 64 products in turn (wavefront w the
+// steps w, w + kWaves, ...): in a round each loads its step's products and
+// takes their columns' hash slots (inserting a column on first sight), then
+// the round's steps are added to the slots' running sums in step order, one
+// wavefront after the other between barriers, each step's segments one
+// after the other.  Every entry thus receives the additions of a serial row
+// product in the same order (a zeroed sum plus the first product, then the
+// others), while kWaves steps' loads are in flight at once.  The occupied
+// slots are then ranked by column and written out.
 __device__ void numeric_row_big(int i, const int* arp, const int* acol, const double* aval, const int* brp,
                                 const int* bcol, const double* bval, const int* crp, int* ccol, double* cval,
                                 int* keys, int* vals, double* acc) {
@@ -452,66 +459,9 @@ __device__ void numeric_row_big(int i, const int* arp, const int* acol, const do
     const unsigned mask = tsz - 1;
     for (unsigned h = tid; h <= mask; h += kBlock) {
         keys[h] = -1;
-        vals[h] = 0;
+        acc[h] = 0.0;
     }
     __syncthreads();
-    for_each_product<false>(
-        arp, acol, nullptr, brp, bcol, nullptr, i,
-        [&](bool valid, int c, double, int, int, int) {
-            if (valid) (void)hash_insert(keys, mask, c);
-            return true;
-        },
-        kWaves, w);
-    __syncthreads();
-    // compact the occupied slots (wavefront 0) into the accumulators' space
-    int* lst = reinterpret_cast<int*>(acc);
-    if (w == 0) {
-        int filled = 0;
-        for (unsigned h0 = 0; h0 <= mask; h0 += 64) {
-            const unsigned h = h0 + lane;
-            const int key = (h <= mask) ? keys[h] : -1;
-            const bool occ = key >= 0;
-            const uint64_t bal = __ballot(occ);
-            const int before = __popcll(bal & ((1ull << lane) - 1ull));
-            if (occ && filled + before < d) lst[filled + before] = key;
-            filled += __popcll(bal);
-        }
-    }
-    __syncthreads();
-    // ranks: kRankKeys keys per lane at a time, the wavefronts taking turns
-    for (int e0 = w * 64 * kRankKeys; e0 < d; e0 += kWaves * 64 * kRankKeys) {
-        int c[kRankKeys], r[kRankKeys];
-#pragma unroll
-        for (int u = 0; u < kRankKeys; ++u) {
-            const int e = e0 + u * 64 + lane;
-            c[u] = e < d ? lst[e] : -1;
-            r[u] = 0;
-        }
-        for (int q = 0; q < d; ++q) {
-            const int v = lst[q];
-#pragma unroll
-            for (int u = 0; u < kRankKeys; ++u) r[u] += (v < c[u]) ? 1 : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < kRankKeys; ++u)
-            if (c[u] >= 0) vals[hash_find_fresh<false>(keys, mask, c[u])] = r[u];
-    }
-    __syncthreads();
-    for (unsigned h = tid; h <= mask; h += kBlock) {
-        const int key = keys[h];
-        const int r = vals[h];
-        if (key >= 0 && r >= 0 && r < d) ccol[base + r] = key;
-    }
-    for (int e = tid; e < d; e += kBlock) acc[e] = 0.0;
-    __syncthreads();
-    // Accumulation in canonical product order by every wavefront: within
-    // each chunk of 64 A entries the wavefronts take the chunk's steps of 64
-    // products in turn (wavefront w the steps w, w + kWaves, ...).  In a
-    // round each wavefront loads its step's products and output positions,
-    // then the round's steps are added in step order, one wavefront after
-    // the other between barriers, each step's segments one after the other
-    // as on the wavefront path: every entry receives the same additions in
-    // the same order, while the loads of kWaves steps are in flight at once.
     const int a0 = arp[i], a1 = arp[i + 1];
     for (int c0 = a0; c0 < a1; c0 += 64) {
         const int ka = c0 + lane;
@@ -548,21 +498,19 @@ __device__ void numeric_row_big(int i, const int* arp, const int* acol, const do
             const int sb = __shfl(bstart, lo, 64);
             const int so = __shfl(excl, lo, 64);
             const double sa = __shfl(av, lo, 64);
-            int r = 0;
+            unsigned h = 0;
             double pv = 0.0;
             if (valid) {
                 const int kb = sb + (t - so);
-                const int c = bcol[kb];
+                h = hash_insert_slot(keys, mask, bcol[kb]);
                 pv = sa * bval[kb];
-                r = vals[hash_find_fresh<false>(keys, mask, c)];
-                r = (r >= 0 && r < d) ? r : 0;
             }
             const int m = st < nsteps ? min(64, total - t0) : 0;
             const int s0 = __shfl(lo, 0, 64), s1 = __shfl(lo, m > 0 ? m - 1 : 0, 64);
             for (int q = 0; q < kWaves; ++q) {
                 if (q == w && m > 0) {
                     for (int sg = s0; sg <= s1; ++sg) {
-                        if (valid && lo == sg) acc[r] += pv;
+                        if (valid && lo == sg) acc[h] += pv;
                         phase_fence<false>();
                     }
                 }
@@ -570,19 +518,57 @@ __device__ void numeric_row_big(int i, const int* arp, const int* acol, const do
             }
         }
     }
-    for (int e = tid; e < d; e += kBlock) cval[base + e] = acc[e];
+    __syncthreads();
+    // compact the occupied slots' columns (wavefront 0)
+    int* lst = vals;
+    if (w == 0) {
+        int filled = 0;
+        for (unsigned h0 = 0; h0 <= mask; h0 += 64) {
+            const unsigned h = h0 + lane;
+            const int key = (h <= mask) ? keys[h] : -1;
+            const bool occ = key >= 0;
+            const uint64_t bal = __ballot(occ);
+            const int before = __popcll(bal & ((1ull << lane) - 1ull));
+            if (occ && filled + before < d) lst[filled + before] = key;
+            filled += __popcll(bal);
+        }
+    }
+    __syncthreads();
+    // ranks: kRankKeys keys per lane at a time, the wavefronts taking turns;
+    // each column goes to its rank's output position with its slot's sum
+    for (int e0 = w * 64 * kRankKeys; e0 < d; e0 += kWaves * 64 * kRankKeys) {
+        int c[kRankKeys], r[kRankKeys];
+#pragma unroll
+        for (int u = 0; u < kRankKeys; ++u) {
+            const int e = e0 + u * 64 + lane;
+            c[u] = e < d ? lst[e] : -1;
+            r[u] = 0;
+        }
+        for (int q = 0; q < d; ++q) {
+            const int v = lst[q];
+#pragma unroll
+            for (int u = 0; u < kRankKeys; ++u) r[u] += (v < c[u]) ? 1 : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kRankKeys; ++u)
+            if (c[u] >= 0 && r[u] < d) {
+                ccol[base + r[u]] = c[u];
+                cval[base + r[u]] = acc[hash_find_fresh<false>(keys, mask, c[u])];
+            }
+    }
     __syncthreads();  // the tables are reused by the workgroup's next row
 }
 
 // the listed overflow rows with at most kDBig columns: a workgroup per row,
-// with a kHSBig-slot hash table and kDBig accumulators in 96 KB of dynamic LDS
+// with a kHSBig-slot hash table and one running sum per slot in 128 KB of
+// dynamic LDS
 __global__ __launch_bounds__(kBlock) void k_spgemm_numeric_big(int nrows, const int* rows, const int* arp,
                                                                const int* acol, const double* aval, const int* brp,
                                                                const int* bcol, const double* bval, const int* crp,
                                                                int* ccol, double* cval) {
     extern __shared__ __align__(16) unsigned char big_lds[];
     double* sacc = reinterpret_cast<double*>(big_lds);
-    int* skeys = reinterpret_cast<int*>(sacc + kDBig);
+    int* skeys = reinterpret_cast<int*>(sacc + kHSBig);
     int* svals = skeys + kHSBig;
     for (int ridx = blockIdx.x; ridx < nrows; ridx += gridDim.x) {
         const int i = rows[ridx];
