@@ -8,13 +8,15 @@
 // scanned offsets.  Symbolic phase: product columns go into an open-addressed
 // hash set in LDS (1024 slots per wave, at most 512 distinct columns); rows
 // that overflow it are redone with a table in global memory sized from the
-// row's product count.  Numeric phase: the distinct columns are compacted and
-// rank-sorted (ascending output columns), and the products are accumulated
-// strictly in canonical order, A entry after A entry (the products of one A
-// entry have distinct columns and are added at once), so every entry is the
-// same sequence of IEEE additions as a serial row-by-row product.  Overflow
-// rows of at most kDBig columns run their numeric phase in a large LDS table
-// shared by a workgroup's wavefronts, the others in global memory.
+// row's product count.  Numeric phase: the products are accumulated strictly
+// in canonical order, A entry after A entry (the products of one A entry
+// have distinct columns and are added at once), so every entry is the same
+// sequence of IEEE additions as a serial row-by-row product.  On LDS tables a
+// single walk adds each product to its column's hash-slot sum and the slots
+// are ranked by column (ascending output positions) afterwards; the global
+// tables rank the columns first and accumulate by rank in a second walk.
+// Overflow rows of at most kDBig columns run their numeric phase in a large
+// LDS table shared by a workgroup's wavefronts, the others in global memory.
 
 #pragma clang fp contract(off)
 
