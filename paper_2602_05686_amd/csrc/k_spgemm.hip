@@ -20,6 +20,10 @@
 
 #pragma clang fp contract(off)
 
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+
 #include "device_util.h"
 #include "kernels.h"
 #include "setup_kernels.h"
@@ -184,7 +188,8 @@ __device__ __forceinline__ unsigned hash_find_fresh(const int* keys, unsigned ma
 // one row (list position ridx) of the symbolic phase, by one wavefront
 template <bool GLOBAL>
 __device__ void symbolic_row(int ridx, const int* rows, const int* arp, const int* acol, const int* brp,
-                             const int* bcol, int* cnt, int* gkeys, const int64_t* goff, int* pcount, int* lds_keys) {
+                             const int* bcol, int* cnt, int* gkeys, const int64_t* goff, int* pcount, int dmax,
+                             int* lds_keys) {
     const int lane = threadIdx.x & 63;
     const int i = rows ? rows[ridx] : ridx;
     int* keys;
@@ -212,10 +217,10 @@ __device__ void symbolic_row(int ridx, const int* rows, const int* arp, const in
                                 added += __popcll(__ballot(r > 0));
                                 const bool overflow = __ballot(r < 0) != 0;
                                 full = full || overflow;
-                                return GLOBAL || !(full || added > kDMax);
+                                return GLOBAL || !(full || added > dmax);
                             });
     if (lane == 0) {
-        if (!GLOBAL && (full || added > kDMax)) cnt[i] = -1;
+        if (!GLOBAL && (full || added > dmax)) cnt[i] = -1;
         else cnt[i] = added;
     }
 }
@@ -226,12 +231,13 @@ template <bool GLOBAL>
 __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic(int nrows, const int* nrows_dev, const int* rows,
                                                             const int* arp, const int* acol, const int* brp,
                                                             const int* bcol, int* cnt, int* gkeys,
-                                                            const int64_t* goff, int* pcount) {
+                                                            const int64_t* goff, int* pcount, int dmax) {
     __shared__ int skeys[GLOBAL ? 1 : kWaves][GLOBAL ? 1 : kHS];
     const int w = threadIdx.x >> 6;
     const int nr = nrows_dev ? *nrows_dev : nrows;
     for (int ridx = blockIdx.x * kWaves + w; ridx < nr; ridx += gridDim.x * kWaves)
-        symbolic_row<GLOBAL>(ridx, rows, arp, acol, brp, bcol, cnt, gkeys, goff, pcount, skeys[GLOBAL ? 0 : w]);
+        symbolic_row<GLOBAL>(ridx, rows, arp, acol, brp, bcol, cnt, gkeys, goff, pcount, dmax,
+                             skeys[GLOBAL ? 0 : w]);
 }
 
 // one row (list position ridx) of the numeric phase, by one wavefront
@@ -252,8 +258,8 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
         const int dc = crp[i + 1] - crp[i];
         if (dc <= mlo || dc > mhi) return;
     } else {
-        // overflow rows of up to kDBig columns take the large LDS table
-        if (crp[i + 1] - crp[i] <= kDBig) return;
+        // overflow rows of up to mlo columns take the large LDS table
+        if (crp[i + 1] - crp[i] <= mlo) return;
     }
     int *keys, *vals;
     double* acc;
@@ -417,7 +423,7 @@ __device__ void numeric_row(int ridx, const int* rows, const int* arp, const int
 // LDS path (N_LDS): the rows of the list whose distinct column count lies in
 // (mlo, mhi] and that did not overflow (skip), with HS >= 2 * mhi hash slots
 // per wave; N_GLOBAL: the listed overflow rows with
-// more than kDBig columns.  A wavefront per row, grid-stride; nrows_dev (if
+// more than mlo (at most kDBig) columns.  A wavefront per row, grid-stride; nrows_dev (if
 // set) holds the count.
 template <int MODE, int HS>
 __global__ __launch_bounds__(kBlock) void k_spgemm_numeric(int nrows, const int* nrows_dev, const int* rows,
@@ -567,14 +573,14 @@ __device__ void numeric_row_big(int i, const int* arp, const int* acol, const do
 __global__ __launch_bounds__(kBlock) void k_spgemm_numeric_big(int nrows, const int* rows, const int* arp,
                                                                const int* acol, const double* aval, const int* brp,
                                                                const int* bcol, const double* bval, const int* crp,
-                                                               int* ccol, double* cval) {
+                                                               int* ccol, double* cval, int dbig) {
     extern __shared__ __align__(16) unsigned char big_lds[];
     double* sacc = reinterpret_cast<double*>(big_lds);
     int* skeys = reinterpret_cast<int*>(sacc + kHSBig);
     int* svals = skeys + kHSBig;
     for (int ridx = blockIdx.x; ridx < nrows; ridx += gridDim.x) {
         const int i = rows[ridx];
-        if (crp[i + 1] - crp[i] > kDBig) continue;  // block-uniform
+        if (crp[i + 1] - crp[i] > dbig) continue;  // block-uniform
         numeric_row_big(i, arp, acol, aval, brp, bcol, bval, crp, ccol, cval, skeys, svals, sacc);
     }
 }
@@ -664,7 +670,7 @@ __device__ __forceinline__ void thread_row_products(const int* arp, const int* a
 // stops where they stop fitting
 __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic_thread(int n, const int* arp, const int* acol,
                                                                    const int* brp, const int* bcol, int* cnt,
-                                                                   int* pcount, int* wide) {
+                                                                   int* pcount, int* wide, int tprod) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int key[kThreadCols];
         double acc[kThreadCols];
@@ -673,7 +679,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_symbolic_thread(int n, const 
         int d = 0, m = 0;
         bool fits = true;
         thread_row_products<false, 8>(arp, acol, nullptr, brp, bcol, nullptr, i, [&](int c, double) {
-            fits = ++m <= kThreadProducts && thread_row_add<false, kThreadCols>(key, acc, d, c, 0.0);
+            fits = ++m <= tprod && thread_row_add<false, kThreadCols>(key, acc, d, c, 0.0);
             return fits;
         });
         wide[i] = fits ? 0 : 1;
@@ -856,9 +862,31 @@ inline int g1(int64_t n) {
     return g < 65535 ? g : 65535;
 }
 
+// The rows' routes: at most tprod products (and kThreadCols columns) for one
+// thread, at most dmax columns for a wavefront's LDS table, at most dbig for
+// a workgroup's, a global-memory table beyond.  MATAMG_SPGEMM_ROUTE=t,d,b
+// lowers them (the tests send rows down every path: every route adds the
+// same products in the same order).
+struct Route {
+    int tprod = kThreadProducts, dmax = kDMax, dbig = kDBig;
+};
+
+Route spgemm_route() {
+    Route r;
+    const char* e = std::getenv("MATAMG_SPGEMM_ROUTE");
+    int t = 0, d = 0, b = 0;
+    if (e && std::sscanf(e, "%d,%d,%d", &t, &d, &b) == 3) {
+        r.tprod = std::max(0, std::min(t, kThreadProducts));
+        r.dmax = std::max(0, std::min(d, kDMax));
+        r.dbig = std::max(0, std::min(b, kDBig));
+    }
+    return r;
+}
+
 }  // namespace
 
 void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s) {
+    const Route route = spgemm_route();
     const int n = A.n;
     C.n = n;
     C.m = B.m;
@@ -875,13 +903,13 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
         // one thread per row where at most kThreadCols columns come out; the
         // remaining (wide) rows take a wavefront each
         hipLaunchKernelGGL(k_spgemm_symbolic_thread, dim3(g1(n)), dim3(kBlock), 0, s, n, A.rowptr.get(),
-                           A.col.get(), B.rowptr.get(), B.col.get(), cnt.get(), pcount.get(), wide.get());
+                           A.col.get(), B.rowptr.get(), B.col.get(), cnt.get(), pcount.get(), wide.get(), route.tprod);
         exclusive_scan(wide.get(), wpos.get(), n, tmp.get(), s);
         hipLaunchKernelGGL(k_list_flagged, dim3(g1(n)), dim3(kBlock), 0, s, n, (const int*)wide.get(),
                            (const int*)wpos.get(), wl.get());
         hipLaunchKernelGGL((k_spgemm_symbolic<false>), dim3(wgrid), dim3(kBlock), 0, s, 0, nwide_dev,
                            (const int*)wl.get(), A.rowptr.get(), A.col.get(), B.rowptr.get(), B.col.get(), cnt.get(),
-                           (int*)nullptr, (const int64_t*)nullptr, pcount.get());
+                           (int*)nullptr, (const int64_t*)nullptr, pcount.get(), route.dmax);
         // overflow flags, and the row pointer as if no row overflowed
         hipLaunchKernelGGL(k_overflow_flags, dim3(g1(n)), dim3(kBlock), 0, s, n, (const int*)cnt.get(), flags.get(),
                            cntc.get());
@@ -915,7 +943,7 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
         gacc.alloc((size_t)tot, mc);
         hipLaunchKernelGGL((k_spgemm_symbolic<true>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
                            (const int*)nullptr, list.get(), A.rowptr.get(), A.col.get(), B.rowptr.get(), B.col.get(),
-                           cnt.get(), gkeys.get(), toff.get(), (int*)nullptr);
+                           cnt.get(), gkeys.get(), toff.get(), (int*)nullptr, route.dmax);
         MATAMG_LAUNCH_CHECK();
         exclusive_scan(cnt.get(), C.rowptr.get(), n, tmp.get(), s);
         d2h(&nnz, C.rowptr.get() + n, 1, s);
@@ -954,11 +982,12 @@ void spgemm(const DCsr& A, const DCsr& B, DCsr& C, MemCounter* mc, hipStream_t s
         (void)big_lds_set;
         hipLaunchKernelGGL(k_spgemm_numeric_big, dim3(std::min(novf, 4096)), dim3(kBlock), kBigLds, s, novf,
                            (const int*)list.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(),
-                           B.col.get(), B.val.get(), (const int*)C.rowptr.get(), C.col.get(), C.val.get());
+                           B.col.get(), B.val.get(), (const int*)C.rowptr.get(), C.col.get(), C.val.get(),
+                           route.dbig);
         hipLaunchKernelGGL((k_spgemm_numeric<N_GLOBAL, 1>), dim3(ceil_div(novf, kWaves)), dim3(kBlock), 0, s, novf,
                            (const int*)nullptr, list.get(), A.rowptr.get(), A.col.get(), A.val.get(), B.rowptr.get(),
                            B.col.get(), B.val.get(), C.rowptr.get(), C.col.get(), C.val.get(), (const int*)nullptr,
-                           gkeys.get(), gvals.get(), gacc.get(), toff.get(), (const int*)nullptr, 0, 0);
+                           gkeys.get(), gvals.get(), gacc.get(), toff.get(), (const int*)nullptr, route.dbig, 0);
         MATAMG_LAUNCH_CHECK();
     }
     // no synchronisation: temporaries go back to the pool in stream order

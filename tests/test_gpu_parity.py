@@ -233,6 +233,53 @@ def test_wide_stream_blocks_on_small_operators(amg, name, monkeypatch):
             assert d <= 1e-6
 
 
+# MATAMG_SPGEMM_ROUTE = thread-row products, wavefront-table columns,
+# workgroup-table columns: every wide row on wavefronts; small wavefront
+# tables and workgroup tables with the rest in global memory; every row with a
+# product in global memory; a few thread rows and the rest in global memory
+ROUTES = ["0,512,4096", "0,8,32", "0,0,0", "16,4,0"]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["layered16", "aniso16", "checker64"])
+def test_sparse_product_routes_agree_bitwise(amg, name, monkeypatch):
+    """The sparse products (filtered operator times tentative prolongator,
+    A P, R (A P)) route each row to one thread, a wavefront's LDS table, a
+    workgroup's LDS table or a global-memory table by its size; each route
+    adds the same products in the same order, so rows forced down other
+    routes must leave every level's P, R and coarse operator, the V-cycle and
+    the solve bitwise as they are."""
+    import torch
+
+    prob_fn, kw = CASES[name]
+    prob = prob_fn()
+    banner(f"{name}: sparse-product routes")
+    r = torch.from_numpy(np.random.default_rng(11).standard_normal(prob.n)).cuda()
+
+    def outputs(h):
+        st = h.stats()
+        mats = [h.level_csr(l, w) for l in range(len(st["n"])) for w in ("A", "P", "R") if w == "A" or
+                l + 1 < len(st["n"])]
+        z = torch.zeros_like(r)
+        h.vcycle(r, z)
+        torch.cuda.synchronize()
+        x, info = h.solve(prob.b)
+        return st["n"], mats, z.cpu().numpy(), x, info["iterations"]
+
+    ref = outputs(amg.Hierarchy.from_problem(prob, **kw))
+    for route in ROUTES:
+        monkeypatch.setenv("MATAMG_SPGEMM_ROUTE", route)
+        got = outputs(amg.Hierarchy.from_problem(prob, **kw))
+        monkeypatch.delenv("MATAMG_SPGEMM_ROUTE")
+        print(f"{name} route {route}: levels {got[0]}, iterations {got[4]}")
+        assert got[0] == ref[0], route
+        for a, b in zip(ref[1], got[1]):
+            for u, v in zip(a, b):
+                assert np.array_equal(u, v), route
+        assert np.array_equal(got[2], ref[2]), route
+        assert np.array_equal(got[3], ref[3]) and got[4] == ref[4], route
+
+
 def test_determinism(amg):
     prob = rotated_anisotropic_3d(n=12, block=4)
     banner("determinism: aniso12")
