@@ -280,6 +280,41 @@ def test_sparse_product_routes_agree_bitwise(amg, name, monkeypatch):
         assert np.array_equal(got[3], ref[3]) and got[4] == ref[4], route
 
 
+@pytest.mark.gpu
+def test_unpooled_setup_matches_pooled(amg, monkeypatch):
+    """With the stream-ordered pool switched off (MATAMG_NO_POOL=1: plain
+    device allocations and frees) the setup, whose dense coarse inverse runs
+    on a second stream, gives bitwise the pooled hierarchy: every level's
+    operators, the V-cycle output and the solve."""
+    import torch
+
+    prob_fn, kw = CASES["layered16"]
+    prob = prob_fn()
+    banner("layered16: unpooled setup")
+    r = torch.from_numpy(np.random.default_rng(12).standard_normal(prob.n)).cuda()
+
+    def outputs():
+        h = amg.Hierarchy.from_problem(prob, **kw)
+        st = h.stats()
+        mats = [h.level_csr(l, "A") for l in range(len(st["n"]))]
+        z = torch.zeros_like(r)
+        h.vcycle(r, z)
+        torch.cuda.synchronize()
+        x, info = h.solve(prob.b)
+        h.close()
+        return mats, z.cpu().numpy(), x, info["iterations"]
+
+    ref = outputs()
+    monkeypatch.setenv("MATAMG_NO_POOL", "1")
+    got = outputs()
+    monkeypatch.delenv("MATAMG_NO_POOL")
+    for a, b in zip(ref[0], got[0]):
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+    assert np.array_equal(ref[1], got[1])
+    assert np.array_equal(ref[2], got[2]) and ref[3] == got[3]
+
+
 def test_determinism(amg):
     prob = rotated_anisotropic_3d(n=12, block=4)
     banner("determinism: aniso12")
