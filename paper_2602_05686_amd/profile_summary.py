@@ -10,11 +10,14 @@ a prolongation (mode 2) to the finer one and the dense GEMV to the coarsest.
 The table gives each level's launches and average time per V-cycle; a bench
 log given with --log adds the level sizes it printed.
 
+With --vcycle, the per-kernel table covers only the trace from the first
+V-cycle on (a run that times V-cycles after one setup).
+
 With --setup, only the last setup in the trace is summarised (from its
 input validation, k_validate_csr, to the first V-cycle after it), per
 kernel name, with the gaps between its kernels.
 
-    python profile_summary.py <run_kernel_trace.csv> [top]
+    python profile_summary.py <run_kernel_trace.csv> [top] [--vcycle]
     python profile_summary.py <run_kernel_trace.csv> --levels [--log bench.log]
     python profile_summary.py <run_kernel_trace.csv> --setup [top]
 """
@@ -69,9 +72,13 @@ def setup(trace_csv, top=25):
         print(f"| `{k}` | {c} | {d / 1e6:.2f} |")
 
 
-def main(trace_csv, top=30):
+def main(trace_csv, top=30, vcycle=False):
     rows = collections.defaultdict(lambda: [0, 0])
-    for k, g, dur in load(trace_csv):
+    seq = load(trace_csv)
+    if vcycle:
+        first = next((i for i, (k, _, _) in enumerate(seq) if k.startswith("k_smooth_first")), len(seq))
+        seq = seq[first:]
+    for k, g, dur in seq:
         rows[(k, g)][0] += 1
         rows[(k, g)][1] += dur
     total = sum(v[1] for v in rows.values())
@@ -131,4 +138,6 @@ if __name__ == "__main__":
         lg = a[a.index("--log") + 1] if "--log" in a else None
         levels(a[0], lg)
     else:
-        main(a[0], int(a[1]) if len(a) > 1 else 30)
+        vc = "--vcycle" in a
+        rest = [x for x in a[1:] if x != "--vcycle"]
+        main(a[0], int(rest[0]) if rest else 30, vc)
