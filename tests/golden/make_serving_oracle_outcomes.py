@@ -3,10 +3,11 @@
 the seeded serving stream (256 requests, seed 0) with at most 64 elements
 per side -- the thin stacks (60 layers on 32 to 64 elements) on which the
 server reports NOT_CONVERGED -- so that the server's failures can be matched
-against the oracle's.  Only the oracle and the input generators run here.
-From the repository root:
+against the oracle's.  --add appends the layered requests with more
+elements per side (65 to 128; hours of CPU time) to the existing file.  Only
+the oracle and the input generators run here.  From the repository root:
 
-    python tests/golden/make_serving_oracle_outcomes.py [--workers 6]
+    python tests/golden/make_serving_oracle_outcomes.py [--workers 6] [--add]
 
 With --ulp it reads that file back, selects the requests a GPU test serves
 (converged within 600 iterations on at most 100000 unknowns, or stopped at
@@ -88,8 +89,25 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workers", type=int, default=6)
     ap.add_argument("--ulp", action="store_true")
+    ap.add_argument("--add", action="store_true")
     args = ap.parse_args()
     from workloads import serving_stream
+
+    if args.add:
+        with open(OUT) as f:
+            rec = json.load(f)
+        have = {c["request"] for c in rec["cases"]}
+        more = [r for r in serving_stream(num=256, rate=20.0)
+                if r["kind"] == "layered" and r["n"] > 64 and r["id"] not in have]
+        more.sort(key=lambda r: -r["n"])
+        with mp.get_context("spawn").Pool(args.workers) as pool:
+            rows = pool.map(run, more, chunksize=1)
+        rec["cases"] = sorted(rec["cases"] + rows, key=lambda r: r["request"])
+        rec["stream"] = "serving_stream(num=256, rate=20.0, seed=0), every layered request"
+        with open(OUT, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(f"{sum(r['status'] != 0 for r in rows)} of {len(rows)} added requests not converged")
+        return
 
     reqs = [r for r in serving_stream(num=256, rate=20.0) if r["kind"] == "layered" and r["n"] <= 64]
     if args.ulp:
