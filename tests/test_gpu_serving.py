@@ -320,3 +320,38 @@ def test_thin_stacks_served_as_the_oracle_solves_them(amg):
         if not ok:
             bad.append(i)
     assert not bad, f"requests served unlike the oracle: {bad}"
+
+
+# large layered requests of the stream (1.4 to 2.1 M unknowns) that the
+# oracle solves in 10 to 120 iterations
+LARGE_IDS = [11, 35, 60, 66, 80, 84, 147, 201]
+
+
+def test_large_stacks_take_the_oracles_iterations(amg):
+    """The serving stream's large layered requests, solved in the FP64 form on
+    one hierarchy each, stop within one iteration of the oracle's own solve
+    (tests/golden/serving_oracle_outcomes.json, written by
+    tests/golden/make_serving_oracle_outcomes.py --add) at a true relative
+    residual of at most 1e-8: on stacks whose residual falls steadily the
+    exit does not depend on rounding."""
+    import json
+    import os
+
+    from workloads import problem_from_request, serving_stream
+
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    with open(os.path.join(gold, "serving_oracle_outcomes.json")) as f:
+        rec = {c["request"]: c for c in json.load(f)["cases"]}
+    byid = {r["id"]: r for r in serving_stream(num=256, rate=20.0)}
+    for rid in LARGE_IDS:
+        orc = rec[rid]
+        prob = problem_from_request(byid[rid])
+        assert prob.n == orc["dof"]
+        h = amg.Hierarchy.from_problem(prob, precision="fp64")
+        x, info = h.solve(prob.b, max_iter=1000)
+        h.close()
+        true = np.linalg.norm(prob.b - oracle.spmv(prob.rowptr, prob.col, prob.val, x)) / np.linalg.norm(prob.b)
+        print(f"request {rid}: {prob.n} DOF, iterations {info['iterations']} (oracle {orc['iterations']}), "
+              f"true rel-res {true:.2e}", flush=True)
+        assert orc["status"] == 0
+        assert abs(info["iterations"] - orc["iterations"]) <= 1 and true <= 1e-8
